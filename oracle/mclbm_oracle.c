@@ -1,0 +1,615 @@
+/*
+ * Plain FP64 CPU oracle for the multi-component Shan-Chen lattice Boltzmann
+ * method with a coupled reactive advection-diffusion solute (CooLBM,
+ * arXiv 2502.12955).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * statement of what one time step computes.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or constant with the HIP library: every lattice table
+ * and every formula below is written out again from the paper.
+ *
+ * Notation follows the paper:
+ *   f^s_i   flow populations of component s (s = 0..ncomp-1), i over D2Q9/D3Q19
+ *   h_k     solute populations, k over D2Q5/D3Q7
+ *   rho_s   component density, psi_s pseudo-potential, F^s total force
+ *   u       barycentric velocity, tau_s, tau_d relaxation times
+ *
+ * Layout: node index n = x + nx*(y + ny*z); f[(s*Q + i)*N + n]; h[k*N + n].
+ * Solid nodes carry no populations (their slots are left untouched).
+ *
+ * Readings taken where the paper is silent or ambiguous (listed with reasons
+ * in the design notes):
+ *   - psi of a solid node is 0; walls act only through the adhesion force.
+ *   - Guo forcing is one option, the Shan-Chen velocity shift the other.
+ *   - body force on component s is rho_s * accel.
+ *   - D3Q7 solute lattice: rest weight J0, link weights (1-J0)/6; the 2-D
+ *     D2Q5 lattice: J0 and (1-J0)/4.  Solute c_s^2 = sum_k W_k e_kx^2.
+ *   - the solute is advected by the barycentric velocity with half force.
+ *   - the wet-node reaction is applied per missing link.
+ *   - inlet (x = 0) anti-bounce-back Dirichlet, outlet (x = nx-1) zero
+ *     gradient, when the solute runs in inlet/outlet mode.
+ *   - fluid voxels pinched between two solids along one axis are made solid
+ *     before anything else (in inlet/outlet mode the planes beyond x = 0 and
+ *     x = nx-1 count as solid for this test).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t lattice;   /* 0: D2Q9 flow + D2Q5 solute, 1: D3Q19 flow + D3Q7 solute */
+    int32_t nx, ny, nz;
+    int32_t ncomp;     /* 1 or 2 */
+    int32_t forcing;   /* 0: Guo, 1: Shan-Chen velocity shift */
+    int32_t solute;    /* 0: off, 1: periodic, 2: inlet at x=0 / outlet at x=nx-1 */
+    int32_t pad_;
+    double tau[2];
+    double G[2][2];
+    double G_ads[2];
+    double rho0;
+    double accel[3];
+    double D, J0, k_wall, C_in;
+} orc_params;
+
+/* ---------------------------------------------------------------------------
+ * Lattice tables, typed in from the paper's tables of velocities and weights
+ * (subsection "3D and 2D LBM Models"): D3Q19, D2Q9 (with w_4 = 1/9, the
+ * printed 1/36 being inconsistent with normalisation), D2Q5.  D3Q7 takes the
+ * first seven D3Q19 vectors.
+ * ------------------------------------------------------------------------- */
+static const int D3Q19_C[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, 0, 1}, {-1, 0, -1}, {0, 1, 1}, {0, -1, -1},
+    {1, -1, 0}, {-1, 1, 0}, {1, 0, -1}, {-1, 0, 1}, {0, 1, -1}, {0, -1, 1}};
+static const double D3Q19_W[19] = {
+    1.0 / 3.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int D2Q9_C[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+static const double D2Q9_W[9] = {
+    4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int D2Q5_C[5][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}};
+static const int D3Q7_C[7][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+/* Speed of sound squared of the flow lattices (both D2Q9 and D3Q19). */
+#define CS2 (1.0 / 3.0)
+
+typedef struct {
+    int Q;
+    const int (*c)[3];
+    const double* w;
+    int opp[19];
+} flow_lat;
+
+typedef struct {
+    int Q;
+    const int (*c)[3];
+    double w[7];
+    double cs2;
+    int opp[7];
+} sol_lat;
+
+static void fill_opp(int Q, const int (*c)[3], int* opp) {
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j)
+            if (c[j][0] == -c[i][0] && c[j][1] == -c[i][1] && c[j][2] == -c[i][2]) opp[i] = j;
+}
+
+static flow_lat make_flow(int lattice) {
+    flow_lat L;
+    if (lattice == 1) { L.Q = 19; L.c = D3Q19_C; L.w = D3Q19_W; }
+    else              { L.Q = 9;  L.c = D2Q9_C;  L.w = D2Q9_W; }
+    fill_opp(L.Q, L.c, L.opp);
+    return L;
+}
+
+static sol_lat make_sol(int lattice, double J0) {
+    sol_lat S;
+    if (lattice == 1) { S.Q = 7; S.c = D3Q7_C; }
+    else              { S.Q = 5; S.c = D2Q5_C; }
+    S.w[0] = J0;
+    for (int k = 1; k < S.Q; ++k) S.w[k] = (1.0 - J0) / (double)(S.Q - 1);
+    S.cs2 = 0.0;
+    for (int k = 0; k < S.Q; ++k) S.cs2 += S.w[k] * S.c[k][0] * S.c[k][0];
+    fill_opp(S.Q, S.c, S.opp);
+    return S;
+}
+
+/* Table export for the tests (velocities as int[Q][3], weights, opposites). */
+int orc_flow_lattice(int lattice, int* c, double* w, int* opp) {
+    flow_lat L = make_flow(lattice);
+    for (int i = 0; i < L.Q; ++i) {
+        for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
+        w[i] = L.w[i];
+        opp[i] = L.opp[i];
+    }
+    return L.Q;
+}
+
+int orc_solute_lattice(int lattice, double J0, int* c, double* w, int* opp, double* cs2) {
+    sol_lat S = make_sol(lattice, J0);
+    for (int k = 0; k < S.Q; ++k) {
+        for (int a = 0; a < 3; ++a) c[3 * k + a] = S.c[k][a];
+        w[k] = S.w[k];
+        opp[k] = S.opp[k];
+    }
+    *cs2 = S.cs2;
+    return S.Q;
+}
+
+/* ---------------------------------------------------------------------------
+ * Local formulas
+ * ------------------------------------------------------------------------- */
+
+/* Second-order equilibrium, eq:6: w_i rho [1 + c.v/cs2 + ((c.v)^2 - cs2 v.v)/(2 cs2^2)]. */
+static double feq_i(const flow_lat* L, int i, double rho, const double v[3]) {
+    double cu = L->c[i][0] * v[0] + L->c[i][1] * v[1] + L->c[i][2] * v[2];
+    double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    return L->w[i] * rho * (1.0 + cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2));
+}
+
+/* Guo forcing term, eq:1.21: w_i [c_a/cs2 + (c_a c_b - cs2 d_ab) u_b/cs2^2] F_a. */
+static double guo_i(const flow_lat* L, int i, const double F[3], const double u[3]) {
+    double cF = L->c[i][0] * F[0] + L->c[i][1] * F[1] + L->c[i][2] * F[2];
+    double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
+    double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    return L->w[i] * (cF / CS2 + (cF * cu - CS2 * uF) / (CS2 * CS2));
+}
+
+/* Pseudo-potential, eq:1.11 / pseudo-potential_multicomponent. */
+static double psi_of(double rho, double rho0) { return rho0 * (1.0 - exp(-rho / rho0)); }
+
+/* Solute equilibrium, eq:therpopeq_species: W_k C (1 + e_k.u / cs2). */
+static double heq_k(const sol_lat* S, int k, double C, const double u[3]) {
+    double eu = S->c[k][0] * u[0] + S->c[k][1] * u[1] + S->c[k][2] * u[2];
+    return S->w[k] * C * (1.0 + eu / S->cs2);
+}
+
+void orc_feq(int lattice, double rho, const double* v, double* out) {
+    flow_lat L = make_flow(lattice);
+    for (int i = 0; i < L.Q; ++i) out[i] = feq_i(&L, i, rho, v);
+}
+
+void orc_guo(int lattice, const double* F, const double* u, double* out) {
+    flow_lat L = make_flow(lattice);
+    for (int i = 0; i < L.Q; ++i) out[i] = guo_i(&L, i, F, u);
+}
+
+double orc_psi(double rho, double rho0) { return psi_of(rho, rho0); }
+
+/* ---------------------------------------------------------------------------
+ * Grid helpers
+ * ------------------------------------------------------------------------- */
+static int64_t nnodes(const orc_params* p) { return (int64_t)p->nx * p->ny * p->nz; }
+
+static int wrap(int a, int n) { return ((a % n) + n) % n; }
+
+static int64_t idx(const orc_params* p, int x, int y, int z) {
+    return (int64_t)x + (int64_t)p->nx * ((int64_t)y + (int64_t)p->ny * z);
+}
+
+static void coords(const orc_params* p, int64_t n, int* x, int* y, int* z) {
+    *x = (int)(n % p->nx);
+    *y = (int)((n / p->nx) % p->ny);
+    *z = (int)(n / ((int64_t)p->nx * p->ny));
+}
+
+/* Periodic neighbour x + d. */
+static int64_t nbr(const orc_params* p, int64_t n, const int d[3]) {
+    int x, y, z;
+    coords(p, n, &x, &y, &z);
+    return idx(p, wrap(x + d[0], p->nx), wrap(y + d[1], p->ny), wrap(z + d[2], p->nz));
+}
+
+/* Periodic neighbour x - d. */
+static int64_t nbr_back(const orc_params* p, int64_t n, const int d[3]) {
+    int m[3] = {-d[0], -d[1], -d[2]};
+    return nbr(p, n, m);
+}
+
+/* ---------------------------------------------------------------------------
+ * Geometry: pinch-fill to a fixed point, then link masks.
+ * A fluid voxel is "pinched" when along some axis both neighbours are
+ * blocked (solid, or beyond the x-seams in solute inlet/outlet mode).
+ * ------------------------------------------------------------------------- */
+static int blocked(const orc_params* p, const uint8_t* mask, int x, int y, int z) {
+    if (p->solute == 2 && (x < 0 || x >= p->nx)) return 1;
+    return mask[idx(p, wrap(x, p->nx), wrap(y, p->ny), wrap(z, p->nz))] != 0;
+}
+
+int64_t orc_pinch_fill(const orc_params* p, uint8_t* mask) {
+    int64_t N = nnodes(p), total = 0;
+    int naxes = (p->lattice == 1) ? 3 : 2;
+    uint8_t* add = (uint8_t*)malloc((size_t)N);
+    for (;;) {
+        int64_t changed = 0;
+        memset(add, 0, (size_t)N);
+        for (int64_t n = 0; n < N; ++n) {
+            if (mask[n]) continue;
+            int x, y, z;
+            coords(p, n, &x, &y, &z);
+            for (int a = 0; a < naxes; ++a) {
+                int d[3] = {0, 0, 0};
+                d[a] = 1;
+                if (blocked(p, mask, x + d[0], y + d[1], z + d[2]) &&
+                    blocked(p, mask, x - d[0], y - d[1], z - d[2])) {
+                    add[n] = 1;
+                    break;
+                }
+            }
+        }
+        for (int64_t n = 0; n < N; ++n)
+            if (add[n]) { mask[n] = 1; ++changed; }
+        total += changed;
+        if (!changed) break;
+    }
+    free(add);
+    return total;
+}
+
+/* Bit i of flow_bits[n] set iff fluid node n has solid upstream node n - c_i
+ * (periodic); bit k of solute_bits[n] set iff the solute link k is a wet
+ * (reactive) link: upstream n - e_k is solid and not across an x-seam in
+ * inlet/outlet mode.  Solid nodes get 0. */
+void orc_link_masks(const orc_params* p, const uint8_t* mask, uint32_t* flow_bits,
+                    uint32_t* solute_bits) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    for (int64_t n = 0; n < N; ++n) {
+        uint32_t fb = 0, sb = 0;
+        if (!mask[n]) {
+            for (int i = 0; i < L.Q; ++i)
+                if (mask[nbr_back(p, n, L.c[i])]) fb |= 1u << i;
+            int x, y, z;
+            coords(p, n, &x, &y, &z);
+            for (int k = 0; k < S.Q; ++k) {
+                int sx = x - S.c[k][0];
+                if (p->solute == 2 && (sx < 0 || sx >= p->nx)) continue;
+                if (mask[nbr_back(p, n, S.c[k])]) sb |= 1u << k;
+            }
+        }
+        flow_bits[n] = fb;
+        solute_bits[n] = sb;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Initialisation: f^s_i = f^eq_i(rho_s, u), h_k = h^eq_k(C, u), no force term.
+ * rho: [ncomp][N]; u: [3][N] or NULL (rest); C: [N] or NULL (zero).
+ * ------------------------------------------------------------------------- */
+void orc_init(const orc_params* p, const uint8_t* mask, const double* rho, const double* u,
+              const double* C, double* f, double* h) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    for (int64_t n = 0; n < N; ++n) {
+        if (mask[n]) continue;
+        double v[3] = {0, 0, 0};
+        if (u) { v[0] = u[n]; v[1] = u[N + n]; v[2] = u[2 * N + n]; }
+        for (int s = 0; s < p->ncomp; ++s)
+            for (int i = 0; i < L.Q; ++i) f[((int64_t)s * L.Q + i) * N + n] = feq_i(&L, i, rho[(int64_t)s * N + n], v);
+        if (p->solute && h) {
+            double c0 = C ? C[n] : 0.0;
+            for (int k = 0; k < S.Q; ++k) h[(int64_t)k * N + n] = heq_k(&S, k, c0, v);
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Step pieces
+ * ------------------------------------------------------------------------- */
+
+/* Phase 1: densities (eq:1.7) and pseudo-potentials of every node; solid -> 0. */
+static void densities(const orc_params* p, const flow_lat* L, const uint8_t* mask,
+                      const double* f, double* rho, double* psi) {
+    int64_t N = nnodes(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        for (int s = 0; s < p->ncomp; ++s) {
+            double r = 0.0;
+            if (!mask[n])
+                for (int i = 0; i < L->Q; ++i) r += f[((int64_t)s * L->Q + i) * N + n];
+            rho[(int64_t)s * N + n] = r;
+            psi[(int64_t)s * N + n] = mask[n] ? 0.0 : psi_of(r, p->rho0);
+        }
+    }
+}
+
+/* Total force on component s at fluid node n:
+ *   cohesion   eq:1.14   -psi_s(x) sum_t G_st sum_i w_i psi_t(x+c_i) c_i
+ *   adhesion   eq:1.15   -G_ads,s rho_s(x) sum_i w_i s(x+c_i) c_i
+ *   body force           rho_s(x) accel                                    */
+static void force_at(const orc_params* p, const flow_lat* L, const uint8_t* mask,
+                     const double* rho, const double* psi, int64_t n, double F[2][3]) {
+    int64_t N = nnodes(p);
+    for (int s = 0; s < p->ncomp; ++s) {
+        double coh[3] = {0, 0, 0}, ads[3] = {0, 0, 0};
+        for (int i = 1; i < L->Q; ++i) {
+            int64_t m = nbr(p, n, L->c[i]);
+            double sumG = 0.0;
+            for (int t = 0; t < p->ncomp; ++t) sumG += p->G[s][t] * psi[(int64_t)t * N + m];
+            double solid = mask[m] ? 1.0 : 0.0;
+            for (int a = 0; a < 3; ++a) {
+                coh[a] += L->w[i] * sumG * L->c[i][a];
+                ads[a] += L->w[i] * solid * L->c[i][a];
+            }
+        }
+        double ps = psi[(int64_t)s * N + n], rs = rho[(int64_t)s * N + n];
+        for (int a = 0; a < 3; ++a)
+            F[s][a] = -ps * coh[a] - p->G_ads[s] * rs * ads[a] + rs * p->accel[a];
+    }
+}
+
+/* Barycentric velocity with half force, eq:1.19 (also the "actual velocity"
+ * of the Shan-Chen scheme). */
+static void bary_u(const orc_params* p, const flow_lat* L, const double* f, int64_t n,
+                   const double* rho, double F[2][3], double u[3]) {
+    int64_t N = nnodes(p);
+    double rt = 0.0, m[3] = {0, 0, 0};
+    for (int s = 0; s < p->ncomp; ++s) {
+        rt += rho[(int64_t)s * N + n];
+        for (int i = 0; i < L->Q; ++i) {
+            double fi = f[((int64_t)s * L->Q + i) * N + n];
+            for (int a = 0; a < 3; ++a) m[a] += L->c[i][a] * fi;
+        }
+        for (int a = 0; a < 3; ++a) m[a] += 0.5 * F[s][a];
+    }
+    for (int a = 0; a < 3; ++a) u[a] = m[a] / rt;
+}
+
+/* Post-collision populations of node n (flow: eq:1.16 with Guo eq:1.19-1.21 or
+ * Shan-Chen eq:1.17-1.18; solute: eq:therpop_species). */
+static void collide_at(const orc_params* p, const flow_lat* L, const sol_lat* S,
+                       const uint8_t* mask, const double* f, const double* h,
+                       const double* rho, const double* psi, int64_t n,
+                       double fs[2][19], double hs[7]) {
+    int64_t N = nnodes(p);
+    double F[2][3];
+    force_at(p, L, mask, rho, psi, n, F);
+    double u[3];
+    bary_u(p, L, f, n, rho, F, u);
+
+    double ueq[2][3];
+    if (p->forcing == 0) {
+        for (int s = 0; s < p->ncomp; ++s)
+            for (int a = 0; a < 3; ++a) ueq[s][a] = u[a];
+    } else {
+        /* u' = sum_s (j_s / tau_s) / sum_s (rho_s / tau_s), u^eq_s = u' + tau_s F_s / rho_s */
+        double num[3] = {0, 0, 0}, den = 0.0;
+        for (int s = 0; s < p->ncomp; ++s) {
+            double j[3] = {0, 0, 0};
+            for (int i = 0; i < L->Q; ++i) {
+                double fi = f[((int64_t)s * L->Q + i) * N + n];
+                for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * fi;
+            }
+            for (int a = 0; a < 3; ++a) num[a] += j[a] / p->tau[s];
+            den += rho[(int64_t)s * N + n] / p->tau[s];
+        }
+        for (int s = 0; s < p->ncomp; ++s)
+            for (int a = 0; a < 3; ++a)
+                ueq[s][a] = num[a] / den + p->tau[s] * F[s][a] / rho[(int64_t)s * N + n];
+    }
+
+    for (int s = 0; s < p->ncomp; ++s) {
+        double tau = p->tau[s], rs = rho[(int64_t)s * N + n];
+        double lam = 1.0 - 1.0 / (2.0 * tau);
+        for (int i = 0; i < L->Q; ++i) {
+            double fi = f[((int64_t)s * L->Q + i) * N + n];
+            double src = (p->forcing == 0) ? guo_i(L, i, F[s], u) : 0.0;
+            fs[s][i] = fi - (fi - feq_i(L, i, rs, ueq[s])) / tau + lam * src;
+        }
+    }
+
+    if (p->solute) {
+        double tau_d = p->D / S->cs2 + 0.5;
+        double C = 0.0;
+        for (int k = 0; k < S->Q; ++k) C += h[(int64_t)k * N + n];
+        for (int k = 0; k < S->Q; ++k) {
+            double hk = h[(int64_t)k * N + n];
+            hs[k] = hk - (hk - heq_k(S, k, C, u)) / tau_d;
+        }
+    }
+}
+
+/* Value of flow population i at fluid node y after streaming (eq:5 with
+ * halfway bounce-back: a link whose upstream node is solid returns the
+ * node's own post-collision population of the opposite direction). */
+static double flow_stream_value(const orc_params* p, const flow_lat* L, const uint8_t* mask,
+                                const double* fstar, int s, int i, int64_t y) {
+    int64_t N = nnodes(p);
+    int64_t src = nbr_back(p, y, L->c[i]);
+    if (mask[src]) return fstar[((int64_t)s * L->Q + L->opp[i]) * N + y];
+    return fstar[((int64_t)s * L->Q + i) * N + src];
+}
+
+/* Value of solute population k at fluid node y after streaming.
+ * Precedence: inlet/outlet seam > wet (reactive) link > plain pull.
+ *   inlet  (x = 0, e_kx = +1):      h_k = 2 W_k C_in - h_kbar(y, t+1)
+ *   outlet (x = nx-1, e_kx = -1):   h_k = h_k(nx-2, t+1) = h*_k(y)
+ *   wet link (y - e_k solid):       C_b = 2 h_in / (2 W_k + k tau/(tau - 1/2)),
+ *                                   h_k = 2 W_k C_b - h_in,  h_in = h_kbar(y, t+1)
+ * (eq:wetnode9 generalised to any missing link; the node sits on the wall.)
+ * h_kbar(y, t+1) is always a plain value h*_kbar(y + e_k): pinch-fill
+ * guarantees that y + e_k is a fluid node inside the domain. */
+static double solute_stream_value(const orc_params* p, const sol_lat* S, const uint8_t* mask,
+                                  const double* hstar, int k, int64_t y) {
+    int64_t N = nnodes(p);
+    int x, yy, z;
+    coords(p, y, &x, &yy, &z);
+    int kb = S->opp[k];
+    if (p->solute == 2 && x == 0 && S->c[k][0] == 1) {
+        double hin = hstar[(int64_t)kb * N + nbr(p, y, S->c[k])];
+        return 2.0 * S->w[k] * p->C_in - hin;
+    }
+    if (p->solute == 2 && x == p->nx - 1 && S->c[k][0] == -1) {
+        return hstar[(int64_t)k * N + y];
+    }
+    int64_t src = nbr_back(p, y, S->c[k]);
+    if (mask[src]) {
+        double tau_d = p->D / S->cs2 + 0.5;
+        double hin = hstar[(int64_t)kb * N + nbr(p, y, S->c[k])];
+        double Cb = 2.0 * hin / (2.0 * S->w[k] + p->k_wall * tau_d / (tau_d - 0.5));
+        return 2.0 * S->w[k] * Cb - hin;
+    }
+    return hstar[(int64_t)k * N + src];
+}
+
+/* ---------------------------------------------------------------------------
+ * One or more full time steps.  State: pre-collision populations at t.
+ *   1. rho_s, psi_s of every node (densities of step t everywhere first)
+ *   2. post-collision populations of every fluid node
+ *   3. streaming (pull) with bounce-back, seams and wet links
+ * ------------------------------------------------------------------------- */
+void orc_step(const orc_params* p, const uint8_t* mask, double* f, double* h, int64_t nsteps) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    int NC = p->ncomp;
+    double* rho = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* psi = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* fstar = (double*)calloc((size_t)(NC * L.Q * N), sizeof(double));
+    double* hstar = p->solute ? (double*)calloc((size_t)(S.Q * N), sizeof(double)) : NULL;
+
+    for (int64_t t = 0; t < nsteps; ++t) {
+        densities(p, &L, mask, f, rho, psi);
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            if (mask[n]) continue;
+            double fs[2][19], hs[7];
+            collide_at(p, &L, &S, mask, f, h, rho, psi, n, fs, hs);
+            for (int s = 0; s < NC; ++s)
+                for (int i = 0; i < L.Q; ++i) fstar[((int64_t)s * L.Q + i) * N + n] = fs[s][i];
+            if (p->solute)
+                for (int k = 0; k < S.Q; ++k) hstar[(int64_t)k * N + n] = hs[k];
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            if (mask[n]) continue;
+            for (int s = 0; s < NC; ++s)
+                for (int i = 0; i < L.Q; ++i)
+                    f[((int64_t)s * L.Q + i) * N + n] = flow_stream_value(p, &L, mask, fstar, s, i, n);
+            if (p->solute)
+                for (int k = 0; k < S.Q; ++k)
+                    h[(int64_t)k * N + n] = solute_stream_value(p, &S, mask, hstar, k, n);
+        }
+    }
+    free(rho);
+    free(psi);
+    free(fstar);
+    free(hstar);
+}
+
+/* Post-step populations at selected fluid nodes only, from the state at t.
+ * Needs post-collision values at the nodes' upstream neighbours, which are
+ * computed one by one from the densities of the whole field.
+ * f_out: [count][ncomp*Q], h_out: [count][QS] (may be NULL without solute). */
+void orc_step_nodes(const orc_params* p, const uint8_t* mask, const double* f, const double* h,
+                    const int64_t* nodes, int64_t count, double* f_out, double* h_out) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    int NC = p->ncomp;
+    double* rho = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* psi = (double*)calloc((size_t)(NC * N), sizeof(double));
+    densities(p, &L, mask, f, rho, psi);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t y = nodes[q];
+        int x, yy, z;
+        coords(p, y, &x, &yy, &z);
+        double fs[2][19], hs[7], fs_n[2][19], hs_n[7];
+        collide_at(p, &L, &S, mask, f, h, rho, psi, y, fs, hs);
+        for (int i = 0; i < L.Q; ++i) {
+            int64_t src = nbr_back(p, y, L.c[i]);
+            int solid = mask[src] != 0;
+            if (!solid) collide_at(p, &L, &S, mask, f, h, rho, psi, src, fs_n, hs_n);
+            for (int s = 0; s < NC; ++s)
+                f_out[q * NC * L.Q + s * L.Q + i] = solid ? fs[s][L.opp[i]] : fs_n[s][i];
+        }
+        if (p->solute && h_out) {
+            for (int k = 0; k < S.Q; ++k) {
+                int kb = S.opp[k];
+                double v;
+                int64_t src = nbr_back(p, y, S.c[k]);
+                if (p->solute == 2 && x == 0 && S.c[k][0] == 1) {
+                    collide_at(p, &L, &S, mask, f, h, rho, psi, nbr(p, y, S.c[k]), fs_n, hs_n);
+                    v = 2.0 * S.w[k] * p->C_in - hs_n[kb];
+                } else if (p->solute == 2 && x == p->nx - 1 && S.c[k][0] == -1) {
+                    v = hs[k];
+                } else if (mask[src]) {
+                    double tau_d = p->D / S.cs2 + 0.5;
+                    collide_at(p, &L, &S, mask, f, h, rho, psi, nbr(p, y, S.c[k]), fs_n, hs_n);
+                    double hin = hs_n[kb];
+                    double Cb = 2.0 * hin / (2.0 * S.w[k] + p->k_wall * tau_d / (tau_d - 0.5));
+                    v = 2.0 * S.w[k] * Cb - hin;
+                } else {
+                    collide_at(p, &L, &S, mask, f, h, rho, psi, src, fs_n, hs_n);
+                    v = hs_n[k];
+                }
+                h_out[q * S.Q + k] = v;
+            }
+        }
+    }
+    free(rho);
+    free(psi);
+}
+
+/* Forces F^s at every node of the state (solid -> 0): [ncomp][3][N]. */
+void orc_forces(const orc_params* p, const uint8_t* mask, const double* f, double* Fout) {
+    flow_lat L = make_flow(p->lattice);
+    int64_t N = nnodes(p);
+    int NC = p->ncomp;
+    double* rho = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* psi = (double*)calloc((size_t)(NC * N), sizeof(double));
+    densities(p, &L, mask, f, rho, psi);
+    for (int64_t n = 0; n < N; ++n) {
+        double F[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        if (!mask[n]) force_at(p, &L, mask, rho, psi, n, F);
+        for (int s = 0; s < NC; ++s)
+            for (int a = 0; a < 3; ++a) Fout[((int64_t)s * 3 + a) * N + n] = F[s][a];
+    }
+    free(rho);
+    free(psi);
+}
+
+/* Macroscopic fields of the current (post-streaming) state: rho_s = sum_i f,
+ * u = barycentric velocity with half force (eq:1.19, taken after streaming),
+ * C = sum_k h_k.  Solid nodes -> 0.  rho: [ncomp][N], u: [3][N], C: [N] or NULL. */
+void orc_moments(const orc_params* p, const uint8_t* mask, const double* f, const double* h,
+                 double* rho_out, double* u_out, double* C_out) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    int NC = p->ncomp;
+    double* rho = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* psi = (double*)calloc((size_t)(NC * N), sizeof(double));
+    densities(p, &L, mask, f, rho, psi);
+    for (int64_t n = 0; n < N; ++n) {
+        double u[3] = {0, 0, 0};
+        if (!mask[n]) {
+            double F[2][3];
+            force_at(p, &L, mask, rho, psi, n, F);
+            bary_u(p, &L, f, n, rho, F, u);
+        }
+        for (int s = 0; s < NC; ++s) rho_out[(int64_t)s * N + n] = mask[n] ? 0.0 : rho[(int64_t)s * N + n];
+        for (int a = 0; a < 3; ++a) u_out[(int64_t)a * N + n] = u[a];
+        if (C_out) {
+            double C = 0.0;
+            if (p->solute && !mask[n])
+                for (int k = 0; k < S.Q; ++k) C += h[(int64_t)k * N + n];
+            C_out[n] = C;
+        }
+    }
+    free(rho);
+    free(psi);
+}
