@@ -1,0 +1,200 @@
+/*
+ * mclbm.h -- C ABI of the MI355X (gfx950) multi-component Shan-Chen lattice
+ * Boltzmann solver with a coupled reactive advection-diffusion solute
+ * (CooLBM method, arXiv 2502.12955).
+ *
+ * One time step, for every fluid node and every component s, performs the
+ * paper's collide-stream update with inter-component forcing:
+ *   - component densities and pseudo-potentials      eq:1.7, eq:1.11 /
+ *                                                    pseudo-potential_multicomponent
+ *   - cohesion force between components              eq:1.14
+ *   - fluid-solid adhesion force                     eq:1.15
+ *   - external body force rho_s * accel, added to the interaction force
+ *     (Rayleigh-Taylor subsection)
+ *   - Guo forcing (eq:1.19-1.21) or the Shan-Chen velocity shift (eq:1.17-1.18)
+ *   - BGK collision with forcing term                eq:1.16, equilibrium eq:6
+ *   - streaming with halfway bounce-back at solids and periodic wrap  eq:5
+ * and for the solute (one reactive species):
+ *   - ADE-BGK collision and streaming                eq:therpop_species,
+ *                                                    eq:therpopeq_species
+ *   - Kang wet-node first-order wall reaction, one missing link at a time
+ *                                                    eq:wetnode9, eq:reactO2
+ *   - optional inlet C = C_in at x = 0 and zero-gradient outlet at x = nx-1.
+ *
+ * Conventions for every host array exchanged through this ABI:
+ *   node index n = x + nx * (y + ny * z), x fastest; N = nx * ny * nz.
+ *   Field arrays are FP64 [field][N].  Solid nodes read as 0 on output.
+ * Lattices: D2Q9 flow + D2Q5 solute (nz must be 1), or D3Q19 flow + D3Q7
+ * solute.  Velocity order is that of the paper's tables; D3Q7 uses the first
+ * seven D3Q19 vectors, D2Q5 the first five D2Q9 vectors.  Solute weights:
+ * rest J0, links (1 - J0)/6 (3-D) or (1 - J0)/4 (2-D); solute c_s^2 =
+ * (1 - J0)/3 or (1 - J0)/2; tau_d = D / c_s^2 + 1/2.
+ *
+ * Status codes: every int-returning call returns MCLBM_OK (0) or a negative
+ * MCLBM_E* code; mclbm_last_error() gives the message of the last failure on
+ * that handle.  All work is queued on the HIP stream given at init; calls
+ * that return data to the host synchronise that stream.  A handle is not
+ * thread-safe: use one handle per host thread.
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mclbm_handle mclbm_handle; /* opaque; owned by the library */
+
+enum {
+    MCLBM_OK = 0,
+    MCLBM_EINVAL = -1,    /* bad parameter, size or layout */
+    MCLBM_ENOMEM = -2,    /* caller arena too small, or allocation failed */
+    MCLBM_EHIP = -3,      /* HIP runtime error */
+    MCLBM_ESTATE = -4,    /* call out of order (e.g. step before init_fields) */
+    MCLBM_EDIVERGED = -5  /* a monitor saw a non-finite density, velocity or C */
+};
+enum { MCLBM_D2Q9 = 0, MCLBM_D3Q19 = 1 };
+enum { MCLBM_FORCING_GUO = 0, MCLBM_FORCING_SC = 1 };
+/* Population storage.  *_SHIFT stores s_i = f_i - w_i * rhobar_s (rhobar_s =
+ * fluid-mean density of component s at init_fields) in 16 bits with
+ * round-to-nearest-even; collision arithmetic is FP32.  The solute is stored
+ * unshifted.  F64 computes in FP64, the others in FP32. */
+enum { MCLBM_F64 = 0, MCLBM_F32 = 1, MCLBM_F16_SHIFT = 2, MCLBM_BF16_SHIFT = 3 };
+enum { MCLBM_SOLUTE_OFF = 0, MCLBM_SOLUTE_PERIODIC = 1, MCLBM_SOLUTE_INLET_OUTLET_X = 2 };
+/* Kernel variants for the flow sweep (mclbm_set_variant). */
+enum { MCLBM_VARIANT_FUSED = 0, MCLBM_VARIANT_TWO_PASS = 1 };
+
+typedef struct {
+    int32_t lattice;       /* MCLBM_D2Q9 or MCLBM_D3Q19 */
+    int32_t nx, ny, nz;    /* >= 1; nz == 1 for D2Q9; ny, nz <= 65535 */
+    int32_t ncomp;         /* 1 or 2 fluid components */
+    int32_t forcing;       /* MCLBM_FORCING_* */
+    int32_t solute;        /* MCLBM_SOLUTE_*; INLET_OUTLET_X needs nx >= 2 */
+    int32_t storage;       /* MCLBM_F64 ... */
+    int32_t monitor_every; /* K: monitors run after every step that is a multiple of K (>= 1) */
+    int32_t reserved;      /* must be 0 */
+    double tau[2];         /* BGK relaxation time per component, > 1/2 */
+    double G[2][2];        /* cohesion matrix G_{s t} of eq:1.14 */
+    double G_ads[2];       /* adhesion strength per component, eq:1.15 (< 0 wets) */
+    double rho0;           /* pseudo-potential reference density, > 0 */
+    double accel[3];       /* body force per unit density (force = rho_s * accel) */
+    double D;              /* solute diffusivity, > 0 when the solute is on */
+    double J0;             /* solute rest weight, in [0, 1) */
+    double k_wall;         /* first-order wall reaction rate k = A exp(-E / R_u T), >= 0 */
+    double C_in;           /* inlet concentration (INLET_OUTLET_X) */
+} mclbm_params;
+
+/* Device bytes the lattice needs for these parameters (populations A and B,
+ * link words, pseudo-potential field, residual snapshot, staging, monitor
+ * partials).  Returns MCLBM_EINVAL for invalid parameters. */
+int mclbm_required_bytes(const mclbm_params* p, size_t* bytes);
+
+/* Create a lattice.  device_arena: caller-owned device memory of at least
+ * mclbm_required_bytes() bytes, 256-byte aligned, kept alive and untouched by
+ * the caller until mclbm_destroy(); NULL makes the library allocate (and
+ * later free) its own.  hip_stream: a hipStream_t (NULL = the null stream) on
+ * which every kernel and copy of this handle is queued.  *out receives the
+ * handle.  Errors: EINVAL (parameters: tau <= 1/2, bad dimensions or enums,
+ * D <= 0 with the solute on, J0 outside [0, 1), k_wall < 0, rho0 <= 0,
+ * monitor_every < 1), ENOMEM (arena too small), EHIP. */
+int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_bytes,
+                       void* hip_stream, mclbm_handle** out);
+
+/* Set the solid geometry from a host mask of N bytes (1 = solid, 0 = fluid).
+ * Fluid voxels that have solids on both sides along one axis (and, with the
+ * inlet/outlet solute, voxels pinched against the x = 0 / x = nx-1 planes)
+ * are reclassified as solid, to a fixed point; *n_reclassified (may be NULL)
+ * receives their count.  Link words are rebuilt on the host and uploaded.
+ * Invalidates the populations (call mclbm_init_fields next).
+ * Errors: EINVAL if the mask is NULL or no fluid node remains. */
+int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_reclassified);
+
+/* Copy out the geometry as the library uses it (each pointer may be NULL):
+ * mask_out [N] bytes after reclassification; flow_links [N]: bit i set iff
+ * fluid node n has a solid upstream node n - c_i (periodic); solute_links
+ * [N]: bit k set iff solute link k of fluid node n is a wet (reactive) link,
+ * i.e. n - e_k is solid and not across the x-planes in inlet/outlet mode.
+ * Solid nodes report 0 links. */
+int mclbm_get_geometry(mclbm_handle* h, uint8_t* mask_out, uint32_t* flow_links,
+                       uint32_t* solute_links);
+
+/* Initial state at equilibrium without force term: f_i = f^eq_i(rho_s, u),
+ * h_k = h^eq_k(C, u).  rho: host FP64 [ncomp][N] (must be > 0 on fluid
+ * nodes); u: host FP64 [3][N] or NULL (rest); C: host FP64 [N] or NULL
+ * (zero).  Resets the step counter and the residual snapshot, and fixes the
+ * storage shift rhobar_s.  Errors: ESTATE before set_geometry, EINVAL. */
+int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const double* C);
+
+/* Advance n >= 0 time steps (queued on the stream).  Monitors run after
+ * every step whose index is a multiple of monitor_every; if any ran, the
+ * call synchronises and returns MCLBM_EDIVERGED when the last one counted a
+ * non-finite value.  Errors: ESTATE before init_fields, EINVAL (n < 0). */
+int mclbm_step(mclbm_handle* h, int64_t n);
+
+/* Macroscopic fields of the current (post-streaming) state: rho_s = sum_i f,
+ * u = barycentric velocity with half force (eq:1.19, evaluated after
+ * streaming), C = sum_k h_k.  rho: [ncomp][N], u: [3][N], C: [N]; any may be
+ * NULL.  dst_is_device != 0: the pointers are device memory (no host sync
+ * beyond the stream).  Solid nodes are 0. */
+int mclbm_get_moments(mclbm_handle* h, double* rho, double* u, double* C, int32_t dst_is_device);
+
+/* Latest monitor values (FP64, deterministic fixed-order reductions):
+ * out[0] step of the monitor, out[1] mass of component 0, out[2] mass of
+ * component 1 (0 if ncomp == 1), out[3] solute mass, out[4] r_u, out[5]
+ * r_phi, out[6] r_C, out[7] non-finite count, out[8] fluid node count,
+ * out[9] max(r_u, r_phi, r_C), out[10] current step; out[11..15] = 0.
+ * Residual r_a = ||a(t) - a(t-K)||_2 / ||a(t)||_2 over fluid nodes, with
+ * phi = (rho_0 - rho_1)/(rho_0 + rho_1); +inf before two monitors exist.
+ * Fields absent from the run (phi with one component, C without solute)
+ * report residual 0.  Before the first monitor out[0] = -1. */
+int mclbm_get_monitors(mclbm_handle* h, double out[16]);
+
+/* Run monitors now on the current state (as if at a monitor step). */
+int mclbm_monitor_now(mclbm_handle* h);
+
+/* Populations of the current pre-collision state.  raw == 0: FP64 decoded
+ * values [ncomp*Q + QS][N] (flow [s][i], then solute [k]; QS = 0 without
+ * solute); raw != 0: the stored bytes in the same order (8, 4 or 2 bytes per
+ * value; shifted values for *_SHIFT).  Solid nodes read 0. */
+int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw);
+
+/* Replace the pre-collision state (same layout as mclbm_get_populations; the
+ * storage shift rhobar_s is kept).  Writing back what get_populations(raw=1)
+ * returned restores the state bit for bit.  ESTATE before init_fields. */
+int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw);
+
+/* Bytes of mclbm_get_populations output for the given raw flag. */
+int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes);
+
+/* Step in chunks of monitor_every until the maximum residual at a monitor is
+ * <= tol or max_steps have been taken.  *steps_taken (may be NULL) receives
+ * the steps of this call.  Returns MCLBM_OK when converged, 1 when max_steps
+ * was reached first, or an error. */
+int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_t* steps_taken);
+
+/* Flow-sweep kernel variant (MCLBM_VARIANT_*) and tile shape of the fused
+ * kernel (tile_x in {32, 64, 128}, tile_y in {1..16}, zchunk >= 1; 0 keeps
+ * the current value).  Results do not depend on the variant or tile.  */
+int mclbm_set_variant(mclbm_handle* h, int32_t variant, int32_t tile_x, int32_t tile_y,
+                      int32_t zchunk);
+
+/* Current step counter. */
+int mclbm_get_step(mclbm_handle* h, int64_t* step);
+
+/* Block until all queued work of the handle has finished. */
+int mclbm_synchronize(mclbm_handle* h);
+
+/* Free library-owned objects (never the caller's arena).  NULL is a no-op. */
+void mclbm_destroy(mclbm_handle* h);
+
+/* Message of the last failed call on h ("" if none); h == NULL gives the
+ * message of the last failed mclbm_init_lattice / mclbm_required_bytes. */
+const char* mclbm_last_error(const mclbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCLBM_H */

@@ -1,0 +1,146 @@
+// Shared device-side definitions: lattice traits, storage policies, kernel
+// arguments and the per-node link word.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mclbm {
+
+// ---------------------------------------------------------------------------
+// Lattices.  Velocity order follows the paper's tables ("3D and 2D LBM
+// Models"): D3Q19 and D2Q9 (w_4 = 1/9).  The solute lattice takes the first
+// QS vectors of the flow lattice (D3Q7 / D2Q5), so a solute direction k and
+// the flow direction k point the same way.  Flow weights are wn[i] / 36.
+// ---------------------------------------------------------------------------
+template <int LAT>
+struct Lat;
+
+template <>
+struct Lat<0> {  // D2Q9 flow + D2Q5 solute
+    static constexpr int Q = 9, QS = 5, DIM = 2;
+    static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr int wn[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
+    static constexpr int SXP = 1, SXM = 3;      // solute +x / -x directions
+    static constexpr int WET_SHIFT = 8;          // wet bit of solute k: WET_SHIFT + k
+    static constexpr int HOP_SHIFT = 12;         // 2-hop bit of solute d: HOP_SHIFT + d
+};
+
+template <>
+struct Lat<1> {  // D3Q19 flow + D3Q7 solute
+    static constexpr int Q = 19, QS = 7, DIM = 3;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr int wn[19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+    static constexpr int SXP = 1, SXM = 2;
+    static constexpr int WET_SHIFT = 18;
+    static constexpr int HOP_SHIFT = 24;
+};
+
+// Link word, one uint32 per node:
+//   bit i (1..Q-1)        flow: upstream node n - c_i is solid
+//   bit WET_SHIFT + k     solute: link k is a wet (reactive) link of this node
+//   bit HOP_SHIFT + d     solute: neighbour n + e_d is fluid and has a wet link
+//                         in direction opp(d) (so this node writes its value)
+//   bit 31                node is solid
+constexpr uint32_t SOLID_BIT = 0x80000000u;
+
+// ---------------------------------------------------------------------------
+// Storage policies.  R = arithmetic type, T = stored type.
+// ---------------------------------------------------------------------------
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
+
+template <int ST>
+struct Store;
+
+template <>
+struct Store<ST_F64> {
+    using R = double;
+    using T = double;
+    __device__ static inline R load(const T* p, R) { return *p; }
+    __device__ static inline void store(T* p, R v, R) { *p = v; }
+    __device__ static inline R load_plain(const T* p) { return *p; }
+    __device__ static inline void store_plain(T* p, R v) { *p = v; }
+};
+
+template <>
+struct Store<ST_F32> {
+    using R = float;
+    using T = float;
+    __device__ static inline R load(const T* p, R) { return *p; }
+    __device__ static inline void store(T* p, R v, R) { *p = v; }
+    __device__ static inline R load_plain(const T* p) { return *p; }
+    __device__ static inline void store_plain(T* p, R v) { *p = v; }
+};
+
+// FP16 stores (f - shift) rounded to nearest even.
+template <>
+struct Store<ST_F16S> {
+    using R = float;
+    using T = __half;
+    __device__ static inline R load(const T* p, R shift) { return __half2float(*p) + shift; }
+    __device__ static inline void store(T* p, R v, R shift) { *p = __float2half_rn(v - shift); }
+    __device__ static inline R load_plain(const T* p) { return __half2float(*p); }
+    __device__ static inline void store_plain(T* p, R v) { *p = __float2half_rn(v); }
+};
+
+// BF16: top 16 bits of the FP32 pattern, rounded to nearest even.
+struct bf16_t {
+    uint16_t bits;
+};
+__device__ __host__ static inline float bf16_to_float(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+__device__ __host__ static inline uint16_t float_to_bf16_rne(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {            // Inf / NaN: keep, quiet the NaN
+        return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <>
+struct Store<ST_BF16S> {
+    using R = float;
+    using T = bf16_t;
+    __device__ static inline R load(const T* p, R shift) { return bf16_to_float(p->bits) + shift; }
+    __device__ static inline void store(T* p, R v, R shift) { p->bits = float_to_bf16_rne(v - shift); }
+    __device__ static inline R load_plain(const T* p) { return bf16_to_float(p->bits); }
+    __device__ static inline void store_plain(T* p, R v) { p->bits = float_to_bf16_rne(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel arguments (by value).  Pointers are device pointers into the arena.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Phys {
+    int nx, ny, nz;
+    int forcing;          // 0 Guo, 1 Shan-Chen velocity shift
+    int solute;           // 0 off, 1 periodic, 2 inlet/outlet in x
+    R inv_tau[2];         // 1 / tau_s
+    R tau[2];
+    R lam[2];             // 1 - 1/(2 tau_s)
+    R G[2][2];
+    R Gads[2];
+    R rho0, inv_rho0;
+    R accel[3];
+    R sh[2][19];          // storage shift w_i * rhobar_s per (s, i); 0 for unshifted storage
+    R Ws0, Ws;            // solute weights: rest, link
+    R inv_cs2s;           // 1 / solute c_s^2
+    R inv_tau_d;          // 1 / tau_d
+    R wet_inv_den;        // 1 / (2 W + k tau_d / (tau_d - 1/2))
+    R C_in;
+};
+
+}  // namespace mclbm

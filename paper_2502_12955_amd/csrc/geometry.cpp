@@ -1,0 +1,141 @@
+// Host-side geometry preparation: pinch-fill and per-node link words.
+//
+// Pinch-fill: a fluid voxel with blocked neighbours on both sides along one
+// axis (x, y, and z in 3-D; periodic wrap; in inlet/outlet solute mode the
+// planes beyond x = 0 and x = nx-1 count as blocked) has no fluid population
+// to reflect at a wet link, so it is made solid.  Making a voxel solid can
+// only add pinches, so the result is the least fixed point above the input
+// mask whatever the processing order; a work list reaches it in O(N).
+#include <stdint.h>
+
+#include <thread>
+#include <vector>
+
+#include "geometry.hpp"
+
+namespace mclbm {
+
+namespace {
+
+struct Grid {
+    int nx, ny, nz, dim;
+    bool seam;
+    long long idx(int x, int y, int z) const {
+        x = (x % nx + nx) % nx;
+        y = (y % ny + ny) % ny;
+        z = (z % nz + nz) % nz;
+        return (long long)x + (long long)nx * ((long long)y + (long long)ny * z);
+    }
+};
+
+bool blocked(const Grid& g, const std::vector<uint8_t>& m, int x, int y, int z) {
+    if (g.seam && (x < 0 || x >= g.nx)) return true;
+    return m[g.idx(x, y, z)] != 0;
+}
+
+bool pinched(const Grid& g, const std::vector<uint8_t>& m, int x, int y, int z) {
+    static const int ax[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int a = 0; a < g.dim; ++a)
+        if (blocked(g, m, x + ax[a][0], y + ax[a][1], z + ax[a][2]) &&
+            blocked(g, m, x - ax[a][0], y - ax[a][1], z - ax[a][2]))
+            return true;
+    return false;
+}
+
+template <class F>
+void parallel_z(int nz, F fn) {
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt == 0) nt = 1;
+    if (nt > 16) nt = 16;
+    if ((int)nt > nz) nt = (unsigned)nz;
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int z = (int)t; z < nz; z += (int)nt) fn(z);
+        });
+    for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+int64_t pinch_fill(const GeomSpec& s, std::vector<uint8_t>& mask) {
+    Grid g{s.nx, s.ny, s.nz, s.lattice == 1 ? 3 : 2, s.solute == 2};
+    std::vector<long long> work;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                long long n = g.idx(x, y, z);
+                if (!mask[n] && pinched(g, mask, x, y, z)) work.push_back(n);
+            }
+    int64_t count = 0;
+    static const int ax[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    while (!work.empty()) {
+        long long n = work.back();
+        work.pop_back();
+        if (mask[n]) continue;
+        mask[n] = 1;
+        ++count;
+        int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((long long)g.nx * g.ny));
+        for (int a = 0; a < g.dim; ++a)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                int xx = x + sgn * ax[a][0], yy = y + sgn * ax[a][1], zz = z + sgn * ax[a][2];
+                if (g.seam && (xx < 0 || xx >= g.nx)) continue;
+                long long m = g.idx(xx, yy, zz);
+                xx = (int)(m % g.nx);
+                yy = (int)((m / g.nx) % g.ny);
+                zz = (int)(m / ((long long)g.nx * g.ny));
+                if (!mask[m] && pinched(g, mask, xx, yy, zz)) work.push_back(m);
+            }
+    }
+    return count;
+}
+
+// Lattice vectors (paper tables), flow then the solute subset (first QS).
+static const int C19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                               {1, 1, 0},  {-1, -1, 0}, {1, 0, 1},  {-1, 0, -1}, {0, 1, 1},  {0, -1, -1}, {1, -1, 0},
+                               {-1, 1, 0}, {1, 0, -1}, {-1, 0, 1}, {0, 1, -1}, {0, -1, 1}};
+static const int C9[9][3] = {{0, 0, 0}, {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
+                             {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+
+void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector<uint32_t>& words,
+                std::vector<uint32_t>* flow_bits, std::vector<uint32_t>* solute_bits) {
+    Grid g{s.nx, s.ny, s.nz, s.lattice == 1 ? 3 : 2, s.solute == 2};
+    const int Q = s.lattice == 1 ? 19 : 9, QS = s.lattice == 1 ? 7 : 5;
+    const int(*c)[3] = s.lattice == 1 ? C19 : C9;
+    const int wet_shift = s.lattice == 1 ? 18 : 8, hop_shift = s.lattice == 1 ? 24 : 12;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    words.assign((size_t)N, 0u);
+    if (flow_bits) flow_bits->assign((size_t)N, 0u);
+    if (solute_bits) solute_bits->assign((size_t)N, 0u);
+    auto in_x = [&](int x) { return !g.seam || (x >= 0 && x < g.nx); };
+    parallel_z(g.nz, [&](int z) {
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                const long long n = g.idx(x, y, z);
+                if (mask[n]) {
+                    words[n] = 0x80000000u;
+                    continue;
+                }
+                uint32_t w = 0, fb = 0, sb = 0;
+                for (int i = 1; i < Q; ++i)
+                    if (mask[g.idx(x - c[i][0], y - c[i][1], z - c[i][2])]) fb |= 1u << i;
+                for (int k = 1; k < QS; ++k) {
+                    if (!in_x(x - c[k][0])) continue;
+                    if (mask[g.idx(x - c[k][0], y - c[k][1], z - c[k][2])]) sb |= 1u << k;
+                }
+                w = fb | (sb << wet_shift);
+                for (int d = 1; d < QS; ++d) {
+                    // neighbour y = n + e_d, reached without crossing a seam, fluid, whose
+                    // upstream in direction opp(d) (= n + 2 e_d) is solid and in the domain
+                    if (!in_x(x + c[d][0]) || !in_x(x + 2 * c[d][0])) continue;
+                    if (mask[g.idx(x + c[d][0], y + c[d][1], z + c[d][2])]) continue;
+                    if (mask[g.idx(x + 2 * c[d][0], y + 2 * c[d][1], z + 2 * c[d][2])]) w |= 1u << (hop_shift + d);
+                }
+                words[n] = w;
+                if (flow_bits) (*flow_bits)[n] = fb;
+                if (solute_bits) (*solute_bits)[n] = sb;
+            }
+    });
+}
+
+}  // namespace mclbm

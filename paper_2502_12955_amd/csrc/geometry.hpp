@@ -1,0 +1,24 @@
+// Host-side geometry preparation (pinch-fill, link words).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace mclbm {
+
+struct GeomSpec {
+    int lattice;  // 0 D2Q9/D2Q5, 1 D3Q19/D3Q7
+    int nx, ny, nz;
+    int solute;   // 2 = inlet/outlet seams in x
+};
+
+// Reclassify pinched fluid voxels as solid (in place); returns their count.
+int64_t pinch_fill(const GeomSpec& s, std::vector<uint8_t>& mask);
+
+// Build the per-node link words used by the kernels (bit layout in
+// common.hpp) and, optionally, the plain flow / wet-link bit masks.
+void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector<uint32_t>& words,
+                std::vector<uint32_t>* flow_bits, std::vector<uint32_t>* solute_bits);
+
+}  // namespace mclbm

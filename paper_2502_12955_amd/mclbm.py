@@ -1,0 +1,324 @@
+"""Thin ctypes binding of ``libmclbm.so`` (contract in ``include/mclbm.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides the device arena (a uint8 CUDA tensor) and the stream; numpy
+arrays carry host data.  There is no fallback: if the library is missing or
+fails to load, ``load()`` raises.
+
+The functions mirror the C names without the ``mclbm_`` prefix; ``Lattice``
+bundles a handle with its arena.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmclbm.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, EDIVERGED = 0, -1, -2, -3, -4, -5
+D2Q9, D3Q19 = 0, 1
+FORCING = {"guo": 0, "sc": 1}
+SOLUTE = {"off": 0, "periodic": 1, "inlet_outlet_x": 2}
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+LATTICE = {"D2Q9": 0, "D3Q19": 1}
+VARIANT = {"fused": 0, "two_pass": 1}
+STORE_DTYPE = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16}
+
+
+class MclbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mclbm error {code}: {msg}")
+        self.code = code
+
+
+class Params(ct.Structure):
+    _fields_ = [("lattice", ct.c_int32), ("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("ncomp", ct.c_int32), ("forcing", ct.c_int32), ("solute", ct.c_int32),
+                ("storage", ct.c_int32), ("monitor_every", ct.c_int32), ("reserved", ct.c_int32),
+                ("tau", ct.c_double * 2), ("G", (ct.c_double * 2) * 2), ("G_ads", ct.c_double * 2),
+                ("rho0", ct.c_double), ("accel", ct.c_double * 3), ("D", ct.c_double),
+                ("J0", ct.c_double), ("k_wall", ct.c_double), ("C_in", ct.c_double)]
+
+
+def _enum(v, table):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def params_from_dict(p: dict) -> Params:
+    s = Params()
+    s.lattice = _enum(p["lattice"], LATTICE)
+    s.nx, s.ny, s.nz = int(p["nx"]), int(p["ny"]), int(p.get("nz", 1))
+    s.ncomp = int(p.get("ncomp", 2))
+    s.forcing = _enum(p.get("forcing", "guo"), FORCING)
+    s.solute = _enum(p.get("solute", "off"), SOLUTE)
+    s.storage = _enum(p.get("storage", "f64"), STORAGE)
+    s.monitor_every = int(p.get("monitor_every", 100))
+    s.reserved = 0
+    tau = p.get("tau", (1.0, 1.0))
+    s.tau[0] = float(tau[0])
+    s.tau[1] = float(tau[1] if len(tau) > 1 else tau[0])
+    G = p.get("G", ((0.0, 0.0), (0.0, 0.0)))
+    for a in range(2):
+        for b in range(2):
+            s.G[a][b] = float(G[a][b])
+    ga = p.get("G_ads", (0.0, 0.0))
+    s.G_ads[0], s.G_ads[1] = float(ga[0]), float(ga[1])
+    s.rho0 = float(p.get("rho0", 1.0))
+    for a, v in enumerate(p.get("accel", (0.0, 0.0, 0.0))):
+        s.accel[a] = float(v)
+    s.D = float(p.get("D", 0.1))
+    s.J0 = float(p.get("J0", 0.1))
+    s.k_wall = float(p.get("k_wall", 0.0))
+    s.C_in = float(p.get("C_in", 0.0))
+    return s
+
+
+_lib = None
+
+EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "mclbm_get_geometry",
+           "mclbm_init_fields", "mclbm_step", "mclbm_get_moments", "mclbm_get_monitors",
+           "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
+           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_variant", "mclbm_get_step",
+           "mclbm_synchronize", "mclbm_destroy", "mclbm_last_error")
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it is not built or cannot be loaded."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2502_12955_amd/build.py")
+    lib = ct.CDLL(path)
+    vp, i32, i64, dbl, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double, ct.c_size_t
+    P = ct.POINTER(Params)
+    lib.mclbm_required_bytes.argtypes = [P, ct.POINTER(sz)]
+    lib.mclbm_init_lattice.argtypes = [P, vp, sz, vp, ct.POINTER(vp)]
+    lib.mclbm_set_geometry.argtypes = [vp, vp, ct.POINTER(i64)]
+    lib.mclbm_get_geometry.argtypes = [vp, vp, vp, vp]
+    lib.mclbm_init_fields.argtypes = [vp, vp, vp, vp]
+    lib.mclbm_step.argtypes = [vp, i64]
+    lib.mclbm_get_moments.argtypes = [vp, vp, vp, vp, i32]
+    lib.mclbm_get_monitors.argtypes = [vp, vp]
+    lib.mclbm_monitor_now.argtypes = [vp]
+    lib.mclbm_get_populations.argtypes = [vp, vp, i32]
+    lib.mclbm_set_populations.argtypes = [vp, vp, i32]
+    lib.mclbm_population_bytes.argtypes = [vp, i32, ct.POINTER(sz)]
+    lib.mclbm_run_to_residual.argtypes = [vp, dbl, i64, ct.POINTER(i64)]
+    lib.mclbm_set_variant.argtypes = [vp, i32, i32, i32, i32]
+    lib.mclbm_get_step.argtypes = [vp, ct.POINTER(i64)]
+    lib.mclbm_synchronize.argtypes = [vp]
+    lib.mclbm_destroy.argtypes = [vp]
+    lib.mclbm_destroy.restype = None
+    lib.mclbm_last_error.argtypes = [vp]
+    lib.mclbm_last_error.restype = ct.c_char_p
+    for name in EXPORTS:
+        if name not in ("mclbm_destroy", "mclbm_last_error"):
+            getattr(lib, name).restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+def last_error(handle=None) -> str:
+    return load().mclbm_last_error(handle).decode()
+
+
+def _check(rc, handle=None, allow=(OK,)):
+    if rc not in allow:
+        raise MclbmError(rc, last_error(handle))
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def required_bytes(p: dict) -> int:
+    n = ct.c_size_t()
+    s = params_from_dict(p)
+    _check(load().mclbm_required_bytes(ct.byref(s), ct.byref(n)))
+    return n.value
+
+
+def init_lattice(p: dict, arena_ptr, arena_bytes: int, stream_ptr):
+    s = params_from_dict(p)
+    h = ct.c_void_p()
+    _check(load().mclbm_init_lattice(ct.byref(s), arena_ptr, arena_bytes, stream_ptr, ct.byref(h)))
+    return h
+
+
+def set_geometry(h, mask) -> int:
+    m = np.ascontiguousarray(mask, np.uint8)
+    n = ct.c_int64()
+    _check(load().mclbm_set_geometry(h, _ptr(m), ct.byref(n)), h)
+    return n.value
+
+
+def get_geometry(h, N):
+    mask = np.zeros(N, np.uint8)
+    fb = np.zeros(N, np.uint32)
+    sb = np.zeros(N, np.uint32)
+    _check(load().mclbm_get_geometry(h, _ptr(mask), _ptr(fb), _ptr(sb)), h)
+    return mask, fb, sb
+
+
+def init_fields(h, rho, u=None, C=None):
+    r = np.ascontiguousarray(rho, np.float64)
+    uu = None if u is None else np.ascontiguousarray(u, np.float64)
+    cc = None if C is None else np.ascontiguousarray(C, np.float64)
+    _check(load().mclbm_init_fields(h, _ptr(r), _ptr(uu), _ptr(cc)), h)
+
+
+def step(h, n: int, allow_diverged=False):
+    allow = (OK, EDIVERGED) if allow_diverged else (OK,)
+    return _check(load().mclbm_step(h, int(n)), h, allow)
+
+
+def get_moments(h, ncomp, N):
+    rho = np.zeros((ncomp, N))
+    u = np.zeros((3, N))
+    C = np.zeros(N)
+    _check(load().mclbm_get_moments(h, _ptr(rho), _ptr(u), _ptr(C), 0), h)
+    return rho, u, C
+
+
+def get_moments_device(h, rho_ptr, u_ptr, C_ptr):
+    _check(load().mclbm_get_moments(h, rho_ptr, u_ptr, C_ptr, 1), h)
+
+
+def get_monitors(h):
+    out = np.zeros(16)
+    _check(load().mclbm_get_monitors(h, _ptr(out)), h)
+    return out
+
+
+def monitor_now(h, allow_diverged=False):
+    allow = (OK, EDIVERGED) if allow_diverged else (OK,)
+    return _check(load().mclbm_monitor_now(h), h, allow)
+
+
+def population_bytes(h, raw: bool) -> int:
+    n = ct.c_size_t()
+    _check(load().mclbm_population_bytes(h, int(bool(raw)), ct.byref(n)), h)
+    return n.value
+
+
+def get_populations(h, raw=False, storage="f64"):
+    nb = population_bytes(h, raw)
+    dt = np.dtype(STORE_DTYPE[_enum(storage, STORAGE)]) if raw else np.dtype(np.float64)
+    out = np.zeros(nb // dt.itemsize, dt)
+    _check(load().mclbm_get_populations(h, _ptr(out), int(bool(raw))), h)
+    return out
+
+
+def set_populations(h, src, raw=False):
+    a = np.ascontiguousarray(src)
+    if not raw:
+        a = np.ascontiguousarray(a, np.float64)
+    if a.nbytes != population_bytes(h, raw):
+        raise ValueError("population array has the wrong size")
+    _check(load().mclbm_set_populations(h, _ptr(a), int(bool(raw))), h)
+
+
+def run_to_residual(h, tol: float, max_steps: int):
+    n = ct.c_int64()
+    rc = _check(load().mclbm_run_to_residual(h, float(tol), int(max_steps), ct.byref(n)), h, (OK, 1))
+    return rc == OK, n.value
+
+
+def set_variant(h, variant="fused", tile_x=0, tile_y=0, zchunk=0):
+    _check(load().mclbm_set_variant(h, _enum(variant, VARIANT), tile_x, tile_y, zchunk), h)
+
+
+def get_step(h) -> int:
+    n = ct.c_int64()
+    _check(load().mclbm_get_step(h, ct.byref(n)), h)
+    return n.value
+
+
+def synchronize(h):
+    _check(load().mclbm_synchronize(h), h)
+
+
+def destroy(h):
+    if h:
+        load().mclbm_destroy(h)
+
+
+class Lattice:
+    """A solver handle plus the torch device arena it lives in.
+
+    ``stream``: a torch.cuda.Stream (default: the current stream).  All work is
+    queued on it.
+    """
+
+    def __init__(self, params: dict, device="cuda:0", stream=None):
+        import torch
+
+        load()
+        self.params = dict(params)
+        self.N = int(params["nx"]) * int(params["ny"]) * int(params.get("nz", 1))
+        self.ncomp = int(params.get("ncomp", 2))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = required_bytes(params)
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.arena.data_ptr()
+        aligned = (base + 255) & ~255
+        self.h = init_lattice(params, ct.c_void_p(aligned), nbytes, ct.c_void_p(self.stream.cuda_stream))
+
+    def close(self):
+        if getattr(self, "h", None):
+            destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, mask):
+        return set_geometry(self.h, np.asarray(mask).reshape(-1))
+
+    def get_geometry(self):
+        return get_geometry(self.h, self.N)
+
+    def init_fields(self, rho, u=None, C=None):
+        init_fields(self.h, np.asarray(rho).reshape(self.ncomp, self.N),
+                    None if u is None else np.asarray(u).reshape(3, self.N),
+                    None if C is None else np.asarray(C).reshape(self.N))
+
+    def step(self, n=1, allow_diverged=False):
+        return step(self.h, n, allow_diverged)
+
+    def moments(self):
+        return get_moments(self.h, self.ncomp, self.N)
+
+    def monitors(self):
+        return get_monitors(self.h)
+
+    def monitor_now(self, allow_diverged=False):
+        return monitor_now(self.h, allow_diverged)
+
+    def populations(self, raw=False):
+        return get_populations(self.h, raw, self.params.get("storage", "f64"))
+
+    def set_populations(self, src, raw=False):
+        set_populations(self.h, src, raw)
+
+    def run_to_residual(self, tol, max_steps):
+        return run_to_residual(self.h, tol, max_steps)
+
+    def set_variant(self, variant="fused", tile_x=0, tile_y=0, zchunk=0):
+        set_variant(self.h, variant, tile_x, tile_y, zchunk)
+
+    @property
+    def step_count(self):
+        return get_step(self.h)
+
+    def synchronize(self):
+        synchronize(self.h)

@@ -1,0 +1,51 @@
+"""The C-ABI library loads on the CPU and exports every symbol the header declares (no GPU calls)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2502_12955_amd import inputs, mclbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mclbm.h")).read()
+    return sorted(set(re.findall(r"\b(mclbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declarations_are_exported():
+    lib = mclbm.load()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(mclbm.EXPORTS)
+
+
+def test_required_bytes_and_validation():
+    p = inputs.porous_params(n=64)
+    nb = mclbm.required_bytes(p)
+    # two population buffers of 2 x 19 floats per node dominate
+    assert nb > 2 * 2 * 19 * 4 * 64 ** 3
+    bad = dict(p, tau=(0.5, 1.0))
+    with pytest.raises(mclbm.MclbmError) as e:
+        mclbm.required_bytes(bad)
+    assert e.value.code == mclbm.EINVAL and "tau" in mclbm.last_error()
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, lattice="D2Q9"))      # nz != 1
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, ncomp=3))
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, D=0.0))
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, solute="inlet_outlet_x", nx=1))
+
+
+def test_arena_too_small_is_rejected_before_any_device_call():
+    p = inputs.droplet_2d_params(nx=16, ny=8)
+    s = mclbm.params_from_dict(p)
+    h = ct.c_void_p()
+    rc = mclbm.load().mclbm_init_lattice(ct.byref(s), ct.c_void_p(256), 16, None, ct.byref(h))
+    assert rc == mclbm.ENOMEM and not h.value
