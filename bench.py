@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # once (2 x 19 flow + 7 solute values) plus one mask byte
 ALG_BYTES = {"f32": 2 * (2 * 19 + 7) * 4 + 1, "f64": 2 * (2 * 19 + 7) * 8 + 1,
              "f16s": 2 * (2 * 19 + 7) * 2 + 1, "bf16s": 2 * (2 * 19 + 7) * 2 + 1}
-KERNEL_SOURCES = ("paper_2502_12955_amd/csrc/fused.hip", "paper_2502_12955_amd/csrc/kernels.hip",
+KERNEL_SOURCES = ("paper_2502_12955_amd/csrc/kernels.hip", "paper_2502_12955_amd/csrc/node.hpp",
                   "paper_2502_12955_amd/csrc/common.hpp")
 
 
@@ -45,10 +45,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(storage, variant, n, nfluid):
+def traffic_from_profiles(storage, n, nfluid):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were
     taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{variant}_{storage}_{n}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{storage}_{n}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -86,8 +86,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic sphere-pack box")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
-    ap.add_argument("--variant", default="fused", choices=["fused", "two_pass"])
-    ap.add_argument("--tile", default=None, help="tile_x,tile_y,zchunk of the fused kernel")
+    ap.add_argument("--block", type=int, default=256, help="threads per workgroup of the step kernels")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -109,11 +108,7 @@ def main():
     log(f"[bench] workload generated in {time.time() - t0:.1f} s")
 
     lat = mclbm.Lattice(p)
-    if args.tile:
-        tx, ty, zc = (int(v) for v in args.tile.split(","))
-        lat.set_variant(args.variant, tx, ty, zc)
-    else:
-        lat.set_variant(args.variant)
+    lat.set_launch(args.block)
     nrc = lat.set_geometry(mask)
     gmask, _, _ = lat.get_geometry()
     nfluid = int((gmask == 0).sum())
@@ -141,10 +136,10 @@ def main():
     launch_ms = gpu_ms / args.steps
     alg_bytes = ALG_BYTES[args.storage] * nfluid
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(args.storage, args.variant, args.n, nfluid)
+    traffic = traffic_from_profiles(args.storage, args.n, nfluid)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"mcmp step ({args.variant})", "alg_bytes_per_launch": alg_bytes,
+                "kernel": "mcmp step (k_density + k_collide)", "alg_bytes_per_launch": alg_bytes,
                 "launch_ms": round(launch_ms, 4)}
 
     cpu = None
@@ -162,7 +157,7 @@ def main():
         "config": {"workload": f"D3Q19 two-component Shan-Chen + D3Q7 reactive solute, {args.n}^3 "
                                f"Boolean sphere pack porosity 0.4 R=8, Guo forcing, body force x 1e-5, "
                                f"wall reaction k=1e-3, inlet/outlet solute",
-                   "nodes": N, "fluid_nodes": nfluid, "storage": args.storage, "variant": args.variant,
+                   "nodes": N, "fluid_nodes": nfluid, "storage": args.storage, "block": args.block,
                    "mflups": round(nfluid / (ms_per_step * 1e-3) / 1e6, 1),
                    "monitor_every": p["monitor_every"], "final_residual": float(mon[9])},
         "roofline": roofline,

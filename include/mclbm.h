@@ -64,8 +64,6 @@ enum { MCLBM_FORCING_GUO = 0, MCLBM_FORCING_SC = 1 };
  * unshifted.  F64 computes in FP64, the others in FP32. */
 enum { MCLBM_F64 = 0, MCLBM_F32 = 1, MCLBM_F16_SHIFT = 2, MCLBM_BF16_SHIFT = 3 };
 enum { MCLBM_SOLUTE_OFF = 0, MCLBM_SOLUTE_PERIODIC = 1, MCLBM_SOLUTE_INLET_OUTLET_X = 2 };
-/* Kernel variants for the flow sweep (mclbm_set_variant). */
-enum { MCLBM_VARIANT_FUSED = 0, MCLBM_VARIANT_TWO_PASS = 1 };
 
 typedef struct {
     int32_t lattice;       /* MCLBM_D2Q9 or MCLBM_D3Q19 */
@@ -175,11 +173,10 @@ int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes);
  * was reached first, or an error. */
 int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_t* steps_taken);
 
-/* Flow-sweep kernel variant (MCLBM_VARIANT_*) and tile shape of the fused
- * kernel (tile_x in {32, 64, 128}, tile_y in {1..16}, zchunk >= 1; 0 keeps
- * the current value).  Results do not depend on the variant or tile.  */
-int mclbm_set_variant(mclbm_handle* h, int32_t variant, int32_t tile_x, int32_t tile_y,
-                      int32_t zchunk);
+/* Threads per workgroup of the two step kernels (64, 128 or 256; default
+ * 256).  Results do not depend on it (each fluid node is updated by one thread
+ * with the same arithmetic); it is a tuning knob for the launch. */
+int mclbm_set_launch(mclbm_handle* h, int32_t block_threads);
 
 /* Current step counter. */
 int mclbm_get_step(mclbm_handle* h, int64_t* step);

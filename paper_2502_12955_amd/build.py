@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmclbm.so")
-SOURCES = ["api.cpp", "geometry.cpp", "kernels.hip", "fused.hip"]
+SOURCES = ["api.cpp", "geometry.cpp", "kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

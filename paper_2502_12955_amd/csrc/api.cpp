@@ -100,6 +100,8 @@ struct mclbm_handle {
     // device regions
     void *fA = nullptr, *fB = nullptr, *hA = nullptr, *hB = nullptr;
     uint32_t* links = nullptr;
+    int* map = nullptr;
+    unsigned* pos = nullptr;
     void* psi = nullptr;
     void* snap = nullptr;
     double* stage = nullptr;
@@ -108,21 +110,21 @@ struct mclbm_handle {
     double* host_result = nullptr;  // pinned
     // host state
     std::vector<uint8_t> mask;
+    std::vector<unsigned> pos_host;  // box index of each fluid node, increasing
     int64_t nfluid = 0;
     bool geom_set = false, fields_set = false;
     int64_t step = 0;
     bool snap_valid = false;
     double mon[16];
     double rhobar[2] = {0, 0};
-    int variant = MCLBM_VARIANT_TWO_PASS;
-    int tile_x = 64, tile_y = 4, zchunk = 16;
+    int block = 256;
     std::string err;
 };
 
 namespace {
 
 struct Layout {
-    size_t fA, fB, hA, hB, links, psi, snap, stage, partials, result, total;
+    size_t fA, fB, hA, hB, map, pos, links, psi, snap, stage, partials, result, total;
 };
 
 Ctx base_ctx(const mclbm_params& p) {
@@ -162,17 +164,20 @@ Layout layout_for(const mclbm_params& p) {
         off = o + bytes;
         return o;
     };
-    L.fA = take((size_t)NC * Q * N * sb);
-    L.fB = take((size_t)NC * Q * N * sb);
-    const size_t hb = p.solute ? (size_t)QS * N * sb : 0;
+    // fluid-only arrays are sized for the worst case (every node fluid)
+    const size_t M = (size_t)pad64(N);
+    L.fA = take((size_t)NC * Q * M * sb);
+    L.fB = take((size_t)NC * Q * M * sb);
+    const size_t hb = p.solute ? (size_t)QS * M * sb : 0;
     L.hA = take(hb);
     L.hB = take(hb);
-    L.links = take((size_t)N * 4);
+    L.map = take((size_t)N * 4);
+    L.pos = take(M * 4);
+    L.links = take(M * 4);
     L.psi = take((size_t)NC * N * ab);
-    L.snap = take((size_t)5 * N * ab);
+    L.snap = take((size_t)5 * M * ab);
     L.stage = take((size_t)(NC + 4) * N * 8);
-    Ctx c = base_ctx(p);
-    L.partials = take(monitor_blocks(c) * MON_NV * 8);
+    L.partials = take(monitor_blocks_max(N) * MON_NV * 8);
     L.result = take(16 * 8);
     L.total = align256(off);
     return L;
@@ -281,15 +286,15 @@ Ctx make_ctx(mclbm_handle* h) {
     c.fB = h->fB;
     c.hA = h->hA;
     c.hB = h->hB;
+    c.Nf = h->nfluid;
     c.links = h->links;
+    c.pos = h->pos;
+    c.map = h->map;
     c.psi = h->psi;
     c.snap = h->snap;
     c.partials = h->partials;
     c.result = h->result;
-    c.variant = h->variant;
-    c.tile_x = h->tile_x;
-    c.tile_y = h->tile_y;
-    c.zchunk = h->zchunk;
+    c.block = h->block;
     return c;
 }
 
@@ -388,6 +393,8 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     h->hA = p->solute ? base + L.hA : nullptr;
     h->hB = p->solute ? base + L.hB : nullptr;
     h->links = (uint32_t*)(base + L.links);
+    h->map = (int*)(base + L.map);
+    h->pos = (unsigned*)(base + L.pos);
     h->psi = base + L.psi;
     h->snap = base + L.snap;
     h->stage = (double*)(base + L.stage);
@@ -419,7 +426,21 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
     }
     std::vector<uint32_t> words;
     link_words(gs, h->mask, words, nullptr, nullptr);
-    HIPCHK(h, hipMemcpyAsync(h->links, words.data(), (size_t)h->N * 4, hipMemcpyHostToDevice, h->stream));
+    // fluid numbering in increasing box index; link words of fluid nodes only
+    const long long N = h->N;
+    h->pos_host.clear();
+    h->pos_host.reserve((size_t)nf);
+    std::vector<int> map((size_t)N, -1);
+    for (long long n = 0; n < N; ++n)
+        if (!h->mask[n]) {
+            map[n] = (int)h->pos_host.size();
+            h->pos_host.push_back((unsigned)n);
+        }
+    std::vector<uint32_t> fw((size_t)nf);
+    for (int64_t k = 0; k < nf; ++k) fw[k] = words[h->pos_host[k]];
+    HIPCHK(h, hipMemcpyAsync(h->map, map.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->pos, h->pos_host.data(), (size_t)nf * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->links, fw.data(), (size_t)nf * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->nfluid = nf;
     h->geom_set = true;
@@ -541,45 +562,52 @@ int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes) {
     return MCLBM_OK;
 }
 
+// Position of (plane j, fluid node k) in a blocked fluid-only array with P planes.
+static inline size_t blk_index(size_t P, size_t j, size_t k) { return ((k >> 6) * P + j) * 64 + (k & 63); }
+
 int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw) {
     if (!h || !dst) return MCLBM_EINVAL;
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const size_t sb = store_bytes(h->p.storage);
-    const size_t nf = (size_t)h->NC * h->Q * h->N, ns = h->p.solute ? (size_t)h->QS * h->N : 0;
-    std::vector<unsigned char> tmp;
-    unsigned char* buf = (unsigned char*)dst;
-    if (!raw) {
-        tmp.resize((nf + ns) * sb);
-        buf = tmp.data();
-    }
-    HIPCHK(h, hipMemcpyAsync(buf, h->fA, nf * sb, hipMemcpyDeviceToHost, h->stream));
-    if (ns) HIPCHK(h, hipMemcpyAsync(buf + nf * sb, h->hA, ns * sb, hipMemcpyDeviceToHost, h->stream));
+    const size_t M = (size_t)pad64(h->nfluid);
+    const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
+    std::vector<unsigned char> dev((PF + PS) * M * sb);
+    HIPCHK(h, hipMemcpyAsync(dev.data(), h->fA, PF * M * sb, hipMemcpyDeviceToHost, h->stream));
+    if (PS) HIPCHK(h, hipMemcpyAsync(dev.data() + PF * M * sb, h->hA, PS * M * sb, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    const long long N = h->N;
+    const size_t N = (size_t)h->N;
     const Ctx c = make_ctx(h);
-    const size_t nplanes = (size_t)h->NC * h->Q + (h->p.solute ? h->QS : 0);
+    const size_t nplanes = PF + PS;
     if (raw) {
-        // zero the solid slots so that the output does not expose stale memory
-        for (size_t j = 0; j < nplanes; ++j)
-            for (long long n = 0; n < N; ++n)
-                if (h->mask[n]) memset(buf + (j * N + n) * sb, 0, sb);
+        unsigned char* out = (unsigned char*)dst;
+        memset(out, 0, nplanes * N * sb);
+        for (size_t j = 0; j < nplanes; ++j) {
+            const bool flow = j < PF;
+            const unsigned char* src = flow ? dev.data() : dev.data() + PF * M * sb;
+            const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
+            for (size_t k = 0; k < (size_t)h->nfluid; ++k)
+                memcpy(out + (j * N + h->pos_host[k]) * sb, src + blk_index(P, jj, k) * sb, sb);
+        }
         return MCLBM_OK;
     }
     double* out = (double*)dst;
+    memset(out, 0, nplanes * N * sizeof(double));
     for (size_t j = 0; j < nplanes; ++j) {
-        const bool flow = j < (size_t)h->NC * h->Q;
+        const bool flow = j < PF;
+        const unsigned char* src = flow ? dev.data() : dev.data() + PF * M * sb;
+        const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
         const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
         const float shift = flow ? shift_f32(c, s, i) : 0.0f;
-        for (long long n = 0; n < N; ++n) {
-            const size_t k = j * N + n;
+        for (size_t k = 0; k < (size_t)h->nfluid; ++k) {
+            const size_t q = blk_index(P, jj, k);
             double v;
             switch (h->p.storage) {
-                case MCLBM_F64: v = ((const double*)buf)[k]; break;
-                case MCLBM_F32: v = ((const float*)buf)[k]; break;
-                case MCLBM_F16_SHIFT: v = (double)(half_to_float(((const uint16_t*)buf)[k]) + shift); break;
-                default: v = (double)(bf16_to_float_h(((const uint16_t*)buf)[k]) + shift); break;
+                case MCLBM_F64: v = ((const double*)src)[q]; break;
+                case MCLBM_F32: v = ((const float*)src)[q]; break;
+                case MCLBM_F16_SHIFT: v = (double)(half_to_float(((const uint16_t*)src)[q]) + shift); break;
+                default: v = (double)(bf16_to_float_h(((const uint16_t*)src)[q]) + shift); break;
             }
-            out[k] = h->mask[n] ? 0.0 : v;
+            out[j * N + h->pos_host[k]] = v;
         }
     }
     return MCLBM_OK;
@@ -589,34 +617,34 @@ int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw) {
     if (!h || !src) return MCLBM_EINVAL;
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const size_t sb = store_bytes(h->p.storage);
-    const size_t nf = (size_t)h->NC * h->Q * h->N, ns = h->p.solute ? (size_t)h->QS * h->N : 0;
-    std::vector<unsigned char> tmp;
-    const unsigned char* buf = (const unsigned char*)src;
-    if (!raw) {
-        tmp.resize((nf + ns) * sb);
-        const double* in = (const double*)src;
-        const long long N = h->N;
-        const Ctx c = make_ctx(h);
-        const size_t nplanes = (size_t)h->NC * h->Q + (h->p.solute ? h->QS : 0);
-        for (size_t j = 0; j < nplanes; ++j) {
-            const bool flow = j < (size_t)h->NC * h->Q;
-            const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
-            const float shift = flow ? shift_f32(c, s, i) : 0.0f;
-            for (long long n = 0; n < N; ++n) {
-                const size_t k = j * N + n;
-                const double v = in[k];
-                switch (h->p.storage) {
-                    case MCLBM_F64: ((double*)tmp.data())[k] = v; break;
-                    case MCLBM_F32: ((float*)tmp.data())[k] = (float)v; break;
-                    case MCLBM_F16_SHIFT: ((uint16_t*)tmp.data())[k] = float_to_half_rne((float)v - shift); break;
-                    default: ((uint16_t*)tmp.data())[k] = float_to_bf16_rne_h((float)v - shift); break;
-                }
+    const size_t M = (size_t)pad64(h->nfluid);
+    const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
+    const size_t N = (size_t)h->N, nplanes = PF + PS;
+    std::vector<unsigned char> dev((PF + PS) * M * sb, 0);
+    const Ctx c = make_ctx(h);
+    for (size_t j = 0; j < nplanes; ++j) {
+        const bool flow = j < PF;
+        unsigned char* dstp = flow ? dev.data() : dev.data() + PF * M * sb;
+        const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
+        const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
+        const float shift = flow ? shift_f32(c, s, i) : 0.0f;
+        for (size_t k = 0; k < (size_t)h->nfluid; ++k) {
+            const size_t q = blk_index(P, jj, k), n = h->pos_host[k];
+            if (raw) {
+                memcpy(dstp + q * sb, (const unsigned char*)src + (j * N + n) * sb, sb);
+                continue;
+            }
+            const double v = ((const double*)src)[j * N + n];
+            switch (h->p.storage) {
+                case MCLBM_F64: ((double*)dstp)[q] = v; break;
+                case MCLBM_F32: ((float*)dstp)[q] = (float)v; break;
+                case MCLBM_F16_SHIFT: ((uint16_t*)dstp)[q] = float_to_half_rne((float)v - shift); break;
+                default: ((uint16_t*)dstp)[q] = float_to_bf16_rne_h((float)v - shift); break;
             }
         }
-        buf = tmp.data();
     }
-    HIPCHK(h, hipMemcpyAsync(h->fA, buf, nf * sb, hipMemcpyHostToDevice, h->stream));
-    if (ns) HIPCHK(h, hipMemcpyAsync(h->hA, buf + nf * sb, ns * sb, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->fA, dev.data(), PF * M * sb, hipMemcpyHostToDevice, h->stream));
+    if (PS) HIPCHK(h, hipMemcpyAsync(h->hA, dev.data() + PF * M * sb, PS * M * sb, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return MCLBM_OK;
 }
@@ -647,17 +675,11 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
     return rc;
 }
 
-int mclbm_set_variant(mclbm_handle* h, int32_t variant, int32_t tile_x, int32_t tile_y, int32_t zchunk) {
+int mclbm_set_launch(mclbm_handle* h, int32_t block_threads) {
     if (!h) return MCLBM_EINVAL;
-    if (variant != MCLBM_VARIANT_FUSED && variant != MCLBM_VARIANT_TWO_PASS)
-        return fail(h, MCLBM_EINVAL, "unknown variant");
-    if (tile_x && tile_x != 32 && tile_x != 64 && tile_x != 128) return fail(h, MCLBM_EINVAL, "tile_x must be 32, 64 or 128");
-    if (tile_y && (tile_y < 1 || tile_y > 16)) return fail(h, MCLBM_EINVAL, "tile_y must be in 1..16");
-    if (zchunk < 0) return fail(h, MCLBM_EINVAL, "zchunk must be >= 0");
-    h->variant = variant;
-    if (tile_x) h->tile_x = tile_x;
-    if (tile_y) h->tile_y = tile_y;
-    if (zchunk) h->zchunk = zchunk;
+    if (block_threads != 64 && block_threads != 128 && block_threads != 256)
+        return fail(h, MCLBM_EINVAL, "block_threads must be 64, 128 or 256");
+    h->block = block_threads;
     return MCLBM_OK;
 }
 

@@ -1,13 +1,20 @@
 // HIP kernels of the multi-component Shan-Chen LBM with reactive solute (gfx950).
 //
-// State: pre-collision populations in buffer A, structure of arrays
-// f[s][i][n] and h[k][n], node n = x + nx*(y + ny*z).  One step reads A and
-// writes B with push streaming (reads of a node's own populations are
-// coalesced; writes go to n + c_i, or back to n for a solid downstream node:
-// halfway bounce-back).  The caller swaps A and B after each step.
+// Storage is fluid-only.  Fluid nodes are numbered k = 0 .. Nf-1 in
+// increasing box index n = x + nx*(y + ny*z); pos[k] = n, map[n] = k (or -1
+// for solid nodes).  Populations are kept in blocks of 64 consecutive fluid
+// nodes (one wavefront): element (plane j, node k) lives at
+//   ((k >> 6) * P + j) * 64 + (k & 63),   P = planes of the array,
+// so a wavefront reads every plane of its 64 nodes as contiguous 256-byte
+// rows, and no bytes of solid nodes are ever moved.  The pseudo-potential
+// field psi[s][n] is kept dense over the box, zero on solid nodes.
 //
+// One step = two kernels, one thread per fluid node:
+//   k_density:  rho_s = sum_i f^s_i (eq:1.7), psi_s = rho0 (1 - exp(-rho_s/rho0))
+//               (eq:1.11) written to the dense psi field.
+//   k_collide:  forces, velocities, BGK collision with forcing, solute collision,
+//               push streaming into buffer B.
 // Per fluid node (paper, multi-component LBM section):
-//   rho_s = sum_i f^s_i (eq:1.7); psi_s = rho0 (1 - exp(-rho_s/rho0)) (eq:1.11)
 //   F^s = -psi_s sum_t G_st sum_i w_i psi_t(x+c_i) c_i          (eq:1.14)
 //         -G_ads,s rho_s sum_i w_i s(x+c_i) c_i                  (eq:1.15)
 //         +rho_s accel
@@ -15,6 +22,8 @@
 //   Guo: u^eq_s = u, source eq:1.21 times (1 - 1/(2 tau_s))      (eq:1.16)
 //   SC:  u^eq_s = u' + tau_s F^s/rho_s, u' of eq:1.18, no source (eq:1.17)
 //   f*_i = f_i + (f^eq_i(rho_s, u^eq_s) - f_i)/tau_s [+ source]   (eq:6, eq:1.16)
+// Streaming pushes f*_i to node n + c_i, or back into the node's own slot of
+// the opposite direction when n + c_i is solid (halfway bounce-back, eq:5).
 // Solute: C = sum_k h_k, h*_k = h_k + (W_k C (1 + e_k.u/cs2) - h_k)/tau_d
 // (eq:therpop_species); wet links get h_k = 2 W C_b - h_in with
 // C_b = 2 h_in/(2W + k tau_d/(tau_d - 1/2)) (eq:wetnode9, per missing link);
@@ -29,94 +38,178 @@
 
 namespace mclbm {
 
+// element (plane j, fluid node k) of a blocked array with P planes
+template <typename T>
+__device__ __forceinline__ T* blk(T* base, int P, int j, unsigned k) {
+    return base + ((size_t)(k >> 6) * (size_t)P + (size_t)j) * 64u + (k & 63u);
+}
+
+// XCD-aware block numbering: hardware dispatches block b to XCD b % 8; each
+// XCD gets a contiguous range of chunks so that neighbouring nodes share an L2.
+__device__ __forceinline__ int chunk_of_block(int per_xcd) {
+    const int b = blockIdx.x;
+    return (b & 7) * per_xcd + (b >> 3);
+}
+
+struct Geo {
+    int N, Nf, nblocks, per_xcd;
+    const unsigned* pos;     // [Nf] box index of fluid node k
+    const int* map;          // [N] fluid index of box node n, -1 if solid
+    const uint32_t* links;   // [Nf] link words
+};
+
+__device__ __forceinline__ void coords(const unsigned n, int nx, int ny, int& x, int& y, int& z) {
+    const unsigned nxy = (unsigned)nx * (unsigned)ny;
+    z = (int)(n / nxy);
+    const unsigned r = n - (unsigned)z * nxy;
+    y = (int)(r / (unsigned)nx);
+    x = (int)(r - (unsigned)y * (unsigned)nx);
+}
+
+// box indices of the neighbourhood positions by (cx, cy, cz) in {-1,0,1}
+struct NbIdx {
+    unsigned xo[3];   // x - 1, x, x + 1 (wrapped)
+    unsigned yo[3];   // nx * (y - 1, y, y + 1)
+    unsigned zo[3];   // nx*ny * (z - 1, z, z + 1)
+    __device__ __forceinline__ unsigned at(int cx, int cy, int cz) const { return xo[cx + 1] + yo[cy + 1] + zo[cz + 1]; }
+};
+
+__device__ __forceinline__ NbIdx make_nb(int x, int y, int z, int nx, int ny, int nz) {
+    NbIdx b;
+    b.xo[0] = x == 0 ? nx - 1 : x - 1;
+    b.xo[1] = x;
+    b.xo[2] = x + 1 == nx ? 0 : x + 1;
+    const unsigned unx = nx, unxy = (unsigned)nx * ny;
+    b.yo[0] = unx * (y == 0 ? ny - 1 : y - 1);
+    b.yo[1] = unx * y;
+    b.yo[2] = unx * (y + 1 == ny ? 0 : y + 1);
+    b.zo[0] = unxy * (z == 0 ? nz - 1 : z - 1);
+    b.zo[1] = unxy * z;
+    b.zo[2] = unxy * (z + 1 == nz ? 0 : z + 1);
+    return b;
+}
+
+#define FLUID_NODE_OR_RETURN()                                          \
+    const int c_ = chunk_of_block(g.per_xcd);                           \
+    if (c_ >= g.nblocks) return;                                        \
+    const unsigned k = (unsigned)c_ * blockDim.x + threadIdx.x;         \
+    if (k >= (unsigned)g.Nf) return;
+
 // ---------------------------------------------------------------------------
-// two-pass variant: (1) pseudo-potential field, (2) collide + push
+// density / pseudo-potential
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
-__global__ void __launch_bounds__(256) k_density_psi(Phys<typename Store<ST>::R> P, long long N,
-                                                     const typename Store<ST>::T* __restrict__ fA,
-                                                     const uint32_t* __restrict__ links,
-                                                     typename Store<ST>::R* __restrict__ psi) {
+__global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, Geo g,
+                                                 const typename Store<ST>::T* __restrict__ fA,
+                                                 typename Store<ST>::R* __restrict__ psi) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= P.nx) return;
-    const long long n = x + (long long)P.nx * (blockIdx.y + (long long)P.ny * blockIdx.z);
-    const uint32_t lw = links[n];
+    FLUID_NODE_OR_RETURN();
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
+    const unsigned n = g.pos[k];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-        R out = 0;
-        if (!(lw & SOLID_BIT)) {
-            R r = 0;
+        R r = 0;
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) r += S::load(plane(fA, N, s * L::Q + i) + n, sh[s][i]);
-            out = P.rho0 * (R(1) - exp_r<R>(-r * P.inv_rho0));
-        }
-        plane(psi, N, s)[n] = out;
+        for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
+        psi[(size_t)s * g.N + n] = P.rho0 * (R(1) - exp_r<R>(-r * P.inv_rho0));
     }
 }
 
+// ---------------------------------------------------------------------------
+// collision + push streaming
+// ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
-__global__ void __launch_bounds__(256) k_collide_push(Phys<typename Store<ST>::R> P, long long N,
-                                                      const typename Store<ST>::T* __restrict__ fA,
-                                                      typename Store<ST>::T* __restrict__ fB,
-                                                      const typename Store<ST>::T* __restrict__ hA,
-                                                      typename Store<ST>::T* __restrict__ hB,
-                                                      const uint32_t* __restrict__ links,
-                                                      const typename Store<ST>::R* __restrict__ psi) {
+__global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, Geo g,
+                                                 const typename Store<ST>::T* __restrict__ fA,
+                                                 typename Store<ST>::T* __restrict__ fB,
+                                                 const typename Store<ST>::T* __restrict__ hA,
+                                                 typename Store<ST>::T* __restrict__ hB,
+                                                 const typename Store<ST>::R* __restrict__ psi) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= P.nx) return;
-    const int y = blockIdx.y, z = blockIdx.z;
-    const long long n = x + (long long)P.nx * (y + (long long)P.ny * z);
-    const uint32_t lw = links[n];
-    if (lw & SOLID_BIT) return;
-    R sh[NC][L::Q];
+    constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
+    FLUID_NODE_OR_RETURN();
+    R sh[NC][Q];
     load_shifts<LAT, ST, NC>(P, sh);
-    R f[NC][L::Q];
+    const unsigned n = g.pos[k];
+    const uint32_t lw = g.links[k];
+    int x, y, z;
+    coords(n, P.nx, P.ny, x, y, z);
+    const NbIdx nb = make_nb(x, y, z, P.nx, P.ny, P.nz);
+
+    R f[NC][Q];
 #pragma unroll
     for (int s = 0; s < NC; ++s)
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) f[s][i] = S::load(plane(fA, N, s * L::Q + i) + n, sh[s][i]);
-    R u[3];
-    auto nb = [&](int t, int i) -> R { return plane(psi, N, t)[nb_index<LAT>(P, x, y, z, i)]; };
-    flow_collide<LAT, NC, R>(P, lw, f, nb, u);
-    flow_push<LAT, ST, NC>(P, lw, x, y, z, n, N, fB, f, sh);
+        for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
+    R h[QS];
     if (P.solute) {
-        R h[L::QS];
 #pragma unroll
-        for (int k = 0; k < L::QS; ++k) h[k] = S::load_plain(plane(hA, N, k) + n);
+        for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
+    }
+
+    auto psi_nb = [&](int t, int i) -> R {
+        return psi[(size_t)t * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
+    };
+    R u[3];
+    flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
+
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
+        unsigned kd = k;
+        if (i != 0 && !bb) kd = (unsigned)g.map[nb.at(L::cx[i], L::cy[i], L::cz[i])];
+        const int dir = bb ? L::opp[i] : i;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) S::store(blk(fB, PF, s * Q + dir, kd), f[s][i], sh[s][i]);  // w_i = w_opp(i)
+    }
+
+    if (P.solute) {
         solute_collide<LAT, R>(P, h, u);
-        solute_push<LAT, ST>(P, lw, x, y, z, n, N, hB, h);
+        S::store_plain(blk(hB, QS, 0, k), h[0]);
+        const bool seam_mode = (P.solute == 2);
+#pragma unroll
+        for (int d = 1; d < QS; ++d) {
+            const int dx = L::cx[d];
+            const bool seam = seam_mode && ((x == P.nx - 1 && dx == 1) || (x == 0 && dx == -1));
+            if (!seam && !(lw & (1u << L::opp[d]))) {
+                const unsigned kd = (unsigned)g.map[nb.at(L::cx[d], L::cy[d], L::cz[d])];
+                S::store_plain(blk(hB, QS, d, kd), h[d]);
+                if (lw & (1u << (L::HOP_SHIFT + d))) {
+                    const R Cb = R(2) * h[d] * P.wet_inv_den;
+                    S::store_plain(blk(hB, QS, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
+                }
+                if (seam_mode && d == L::SXM && x == 1)
+                    S::store_plain(blk(hB, QS, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
+            }
+            if (seam_mode && d == L::SXM && x == P.nx - 1) S::store_plain(blk(hB, QS, d, k), h[d]);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// initialisation at equilibrium (no force term); solid slots get 0
+// initialisation at equilibrium (no force term) from dense staging fields
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
-__global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, long long N,
+__global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, Geo g,
                                                  typename Store<ST>::T* __restrict__ fA,
                                                  typename Store<ST>::T* __restrict__ hA,
-                                                 const uint32_t* __restrict__ links,
                                                  const double* __restrict__ rho, const double* __restrict__ u,
                                                  const double* __restrict__ C) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= P.nx) return;
-    const long long n = x + (long long)P.nx * (blockIdx.y + (long long)P.ny * blockIdx.z);
-    const bool solid = links[n] & SOLID_BIT;
+    FLUID_NODE_OR_RETURN();
+    const size_t N = g.N;
+    const unsigned n = g.pos[k];
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
     R v[3] = {0, 0, 0};
-    if (u && !solid) {
+    if (u) {
         v[0] = (R)u[n];
         v[1] = (R)u[N + n];
         v[2] = (R)u[2 * N + n];
@@ -124,22 +217,21 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
     const R vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-        const R r = solid ? R(0) : (R)rho[s * N + n];
+        const R r = (R)rho[s * N + n];
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const R cv = R(L::cx[i]) * v[0] + R(L::cy[i]) * v[1] + R(L::cz[i]) * v[2];
             const R feq = wgt<LAT, R>(i) * r * (R(1) + R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
-            if (solid) S::store_plain(plane(fA, N, s * L::Q + i) + n, R(0));
-            else S::store(plane(fA, N, s * L::Q + i) + n, feq, sh[s][i]);
+            S::store(blk(fA, NC * L::Q, s * L::Q + i, k), feq, sh[s][i]);
         }
     }
     if (P.solute) {
-        const R c0 = (C && !solid) ? (R)C[n] : R(0);
+        const R c0 = C ? (R)C[n] : R(0);
 #pragma unroll
-        for (int k = 0; k < L::QS; ++k) {
-            const R W = (k == 0) ? P.Ws0 : P.Ws;
-            const R eu = R(L::cx[k]) * v[0] + R(L::cy[k]) * v[1] + R(L::cz[k]) * v[2];
-            S::store_plain(plane(hA, N, k) + n, solid ? R(0) : W * c0 * (R(1) + eu * P.inv_cs2s));
+        for (int q = 0; q < L::QS; ++q) {
+            const R W = (q == 0) ? P.Ws0 : P.Ws;
+            const R eu = R(L::cx[q]) * v[0] + R(L::cy[q]) * v[1] + R(L::cz[q]) * v[2];
+            S::store_plain(blk(hA, L::QS, q, k), W * c0 * (R(1) + eu * P.inv_cs2s));
         }
     }
 }
@@ -150,8 +242,7 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
 // it leaves in the local copy are discarded).
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
-__device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& P, long long N, int x, int y,
-                                             int z, long long n, uint32_t lw,
+__device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& P, const Geo& g, unsigned k,
                                              const typename Store<ST>::T* __restrict__ fA,
                                              const typename Store<ST>::T* __restrict__ hA,
                                              const typename Store<ST>::R* __restrict__ psi,
@@ -162,42 +253,57 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
     using R = typename S::R;
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
+    const unsigned n = g.pos[k];
+    const uint32_t lw = g.links[k];
+    int x, y, z;
+    coords(n, P.nx, P.ny, x, y, z);
+    const NbIdx nb = make_nb(x, y, z, P.nx, P.ny, P.nz);
     R f[NC][L::Q];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         R r = 0;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            f[s][i] = S::load(plane(fA, N, s * L::Q + i) + n, sh[s][i]);
+            f[s][i] = S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
             r += f[s][i];
         }
         rho[s] = r;
     }
-    auto nb = [&](int t, int i) -> R { return plane(psi, N, t)[nb_index<LAT>(P, x, y, z, i)]; };
-    flow_collide<LAT, NC, R>(P, lw, f, nb, u);
+    auto psi_nb = [&](int t, int i) -> R {
+        return psi[(size_t)t * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
+    };
+    flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
     C = 0;
     if (P.solute) {
 #pragma unroll
-        for (int k = 0; k < L::QS; ++k) C += S::load_plain(plane(hA, N, k) + n);
+        for (int q = 0; q < L::QS; ++q) C += S::load_plain(blk(hA, L::QS, q, k));
     }
 }
 
+__global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, long long n, double v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fill_r(R* __restrict__ p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = R(0);
+}
+
 template <int LAT, int ST, int NC>
-__global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R> P, long long N,
+__global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R> P, Geo g,
                                                      const typename Store<ST>::T* __restrict__ fA,
                                                      const typename Store<ST>::T* __restrict__ hA,
-                                                     const uint32_t* __restrict__ links,
                                                      const typename Store<ST>::R* __restrict__ psi,
                                                      double* __restrict__ rho_out, double* __restrict__ u_out,
                                                      double* __restrict__ C_out) {
     using R = typename Store<ST>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= P.nx) return;
-    const int y = blockIdx.y, z = blockIdx.z;
-    const long long n = x + (long long)P.nx * (y + (long long)P.ny * z);
-    const uint32_t lw = links[n];
-    R rho[NC] = {}, u[3] = {0, 0, 0}, C = 0;
-    if (!(lw & SOLID_BIT)) node_moments<LAT, ST, NC>(P, N, x, y, z, n, lw, fA, hA, psi, rho, u, C);
+    FLUID_NODE_OR_RETURN();
+    R rho[NC], u[3], C;
+    node_moments<LAT, ST, NC>(P, g, k, fA, hA, psi, rho, u, C);
+    const size_t N = g.N;
+    const unsigned n = g.pos[k];
     if (rho_out)
         for (int s = 0; s < NC; ++s) rho_out[s * N + n] = (double)rho[s];
     if (u_out)
@@ -218,75 +324,71 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int LAT, int ST, int NC>
-__global__ void __launch_bounds__(256) k_monitor(Phys<typename Store<ST>::R> P, long long N,
+__global__ void __launch_bounds__(256) k_monitor(Phys<typename Store<ST>::R> P, Geo g,
                                                  const typename Store<ST>::T* __restrict__ fA,
                                                  const typename Store<ST>::T* __restrict__ hA,
-                                                 const uint32_t* __restrict__ links,
                                                  const typename Store<ST>::R* __restrict__ psi,
                                                  typename Store<ST>::R* __restrict__ snap, int have_snapshot,
                                                  double* __restrict__ partials) {
     using R = typename Store<ST>::R;
     __shared__ double red[MON_NV][4];
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
+    const int c = chunk_of_block(g.per_xcd);
+    if (c >= g.nblocks) return;  // whole block: uniform
+    const unsigned k = (unsigned)c * blockDim.x + threadIdx.x;
     double v[MON_NV];
 #pragma unroll
-    for (int k = 0; k < MON_NV; ++k) v[k] = 0.0;
-    if (x < P.nx) {
-        const long long n = x + (long long)P.nx * (y + (long long)P.ny * z);
-        const uint32_t lw = links[n];
-        if (!(lw & SOLID_BIT)) {
-            R rho[NC], u[3], C;
-            node_moments<LAT, ST, NC>(P, N, x, y, z, n, lw, fA, hA, psi, rho, u, C);
-            R phi = 0;
-            if (NC == 2) {
-                const R tot = rho[0] + rho[NC - 1];
-                phi = (tot != R(0)) ? (rho[0] - rho[NC - 1]) / tot : R(0);
-            }
-            v[0] = rho[0];
-            v[1] = (NC == 2) ? (double)rho[NC - 1] : 0.0;
-            v[2] = C;
-            double uu = 0, du = 0;
-            for (int a = 0; a < 3; ++a) {
-                const double ua = u[a];
-                uu += ua * ua;
-                if (have_snapshot) {
-                    const double d = ua - (double)plane(snap, N, a)[n];
-                    du += d * d;
-                }
-                plane(snap, N, a)[n] = u[a];
-            }
-            v[3] = du;
-            v[4] = uu;
-            if (have_snapshot) {
-                const double dp = (double)phi - (double)plane(snap, N, 3)[n];
-                const double dc = (double)C - (double)plane(snap, N, 4)[n];
-                v[5] = dp * dp;
-                v[7] = dc * dc;
-            }
-            v[6] = (double)phi * (double)phi;
-            v[8] = (double)C * (double)C;
-            plane(snap, N, 3)[n] = phi;
-            plane(snap, N, 4)[n] = C;
-            bool bad = !isfinite((double)rho[0]) || !isfinite((double)rho[NC - 1]) || !isfinite((double)C) ||
-                       !isfinite((double)u[0]) || !isfinite((double)u[1]) || !isfinite((double)u[2]);
-            v[9] = bad ? 1.0 : 0.0;
-            v[10] = 1.0;
+    for (int q = 0; q < MON_NV; ++q) v[q] = 0.0;
+    if (k < (unsigned)g.Nf) {
+        R rho[NC], u[3], C;
+        node_moments<LAT, ST, NC>(P, g, k, fA, hA, psi, rho, u, C);
+        R phi = 0;
+        if (NC == 2) {
+            const R tot = rho[0] + rho[NC - 1];
+            phi = (tot != R(0)) ? (rho[0] - rho[NC - 1]) / tot : R(0);
         }
+        const size_t M = g.Nf;
+        v[0] = rho[0];
+        v[1] = (NC == 2) ? (double)rho[NC - 1] : 0.0;
+        v[2] = C;
+        double uu = 0, du = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double ua = u[a];
+            uu += ua * ua;
+            if (have_snapshot) {
+                const double d = ua - (double)snap[a * M + k];
+                du += d * d;
+            }
+            snap[a * M + k] = u[a];
+        }
+        v[3] = du;
+        v[4] = uu;
+        if (have_snapshot) {
+            const double dp = (double)phi - (double)snap[3 * M + k];
+            const double dc = (double)C - (double)snap[4 * M + k];
+            v[5] = dp * dp;
+            v[7] = dc * dc;
+        }
+        v[6] = (double)phi * (double)phi;
+        v[8] = (double)C * (double)C;
+        snap[3 * M + k] = phi;
+        snap[4 * M + k] = C;
+        const bool bad = !isfinite((double)rho[0]) || !isfinite((double)rho[NC - 1]) || !isfinite((double)C) ||
+                         !isfinite((double)u[0]) || !isfinite((double)u[1]) || !isfinite((double)u[2]);
+        v[9] = bad ? 1.0 : 0.0;
+        v[10] = 1.0;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < MON_NV; ++k) {
-        const double s = wave_sum(v[k]);
-        if (lane == 0) red[k][wid] = s;
+    for (int q = 0; q < MON_NV; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) red[q][wid] = s;
     }
     __syncthreads();
     if (threadIdx.x < MON_NV) {
         const int nw = (blockDim.x + 63) >> 6;
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
-        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-        partials[b * MON_NV + threadIdx.x] = s;
+        partials[(size_t)c * MON_NV + threadIdx.x] = s;
     }
 }
 
@@ -298,17 +400,17 @@ __global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict_
     const int t = threadIdx.x;
     double s[MON_NV];
 #pragma unroll
-    for (int k = 0; k < MON_NV; ++k) s[k] = 0.0;
+    for (int q = 0; q < MON_NV; ++q) s[q] = 0.0;
     for (long long b = t; b < nblocks; b += 256)
 #pragma unroll
-        for (int k = 0; k < MON_NV; ++k) s[k] += partials[b * MON_NV + k];
+        for (int q = 0; q < MON_NV; ++q) s[q] += partials[b * MON_NV + q];
 #pragma unroll
-    for (int k = 0; k < MON_NV; ++k) acc[t][k] = s[k];
+    for (int q = 0; q < MON_NV; ++q) acc[t][q] = s[q];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w)
 #pragma unroll
-            for (int k = 0; k < MON_NV; ++k) acc[t][k] += acc[t + w][k];
+            for (int q = 0; q < MON_NV; ++q) acc[t][q] += acc[t + w][q];
         __syncthreads();
     }
     if (t < MON_NV) result[t] = acc[0][t];
@@ -317,6 +419,16 @@ __global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict_
 // ---------------------------------------------------------------------------
 // host dispatch
 // ---------------------------------------------------------------------------
+float shift_f32(const Ctx& c, int s, int i) {
+    if (c.st < ST_F16S) return 0.0f;
+    static const int wn19[19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+    static const int wn9[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
+    if (i >= ((c.lat == 1) ? 19 : 9)) return 0.0f;
+    const int wn = (c.lat == 1) ? wn19[i] : wn9[i];
+    const float w = (float)wn / 36.0f;
+    return w * (float)c.rhobar[s];
+}
+
 template <typename R>
 Phys<R> make_phys(const Ctx& c) {
     Phys<R> P;
@@ -349,7 +461,6 @@ Phys<R> make_phys(const Ctx& c) {
     P.C_in = (R)c.C_in;
     return P;
 }
-
 template Phys<float> make_phys<float>(const Ctx&);
 template Phys<double> make_phys<double>(const Ctx&);
 
@@ -358,110 +469,107 @@ using SR = typename Store<ST>::R;
 template <int ST>
 using STT = typename Store<ST>::T;
 
-static inline dim3 node_block(const Ctx& c) { return dim3(c.nx >= 256 ? 256 : (c.nx >= 128 ? 128 : 64)); }
-static inline dim3 node_grid(const Ctx& c) {
-    const dim3 b = node_block(c);
-    return dim3((c.nx + b.x - 1) / b.x, c.ny, c.nz);
+// launch shape over the fluid nodes: bs threads per block, grid 8 * per_xcd
+static inline Geo make_geo(const Ctx& c, int bs) {
+    Geo g;
+    g.N = (int)c.N;
+    g.Nf = (int)c.Nf;
+    g.nblocks = (int)((c.Nf + bs - 1) / bs);
+    g.per_xcd = (g.nblocks + 7) / 8;
+    g.pos = c.pos;
+    g.map = c.map;
+    g.links = c.links;
+    return g;
 }
+static inline dim3 geo_grid(const Geo& g) { return dim3((unsigned)(8 * g.per_xcd > 0 ? 8 * g.per_xcd : 8)); }
 
-size_t monitor_blocks(const Ctx& c) {
-    const dim3 g = node_grid(c);
-    return (size_t)g.x * g.y * g.z;
-}
-
-float shift_f32(const Ctx& c, int s, int i) {
-    if (c.st < ST_F16S) return 0.0f;
-    static const int wn19[19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
-    static const int wn9[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
-    const int wn = (c.lat == 1) ? wn19[i] : wn9[i];
-    if (i >= ((c.lat == 1) ? 19 : 9)) return 0.0f;
-    const float w = (float)wn / 36.0f;
-    return w * (float)c.rhobar[s];
-}
+size_t monitor_blocks(const Ctx& c) { return (size_t)((c.Nf + 255) / 256); }
+size_t monitor_blocks_max(long long N) { return (size_t)((N + 255) / 256); }
 
 template <int LAT, int ST, int NC>
-static hipError_t step_two_pass(const Ctx& c) {
+static hipError_t step_t(const Ctx& c) {
     auto P = make_phys<SR<ST>>(c);
-    const dim3 b = node_block(c), g = node_grid(c);
-    hipLaunchKernelGGL((k_density_psi<LAT, ST, NC>), g, b, 0, c.stream, P, c.N, (const STT<ST>*)c.fA, c.links,
+    const int bs = c.block > 0 ? c.block : 256;
+    const Geo g = make_geo(c, bs);
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), geo_grid(g), dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_collide_push<LAT, ST, NC>), g, b, 0, c.stream, P, c.N, (const STT<ST>*)c.fA,
-                       (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, c.links, (const SR<ST>*)c.psi);
+    hipLaunchKernelGGL((k_collide<LAT, ST, NC>), geo_grid(g), dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+                       (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
     return hipGetLastError();
 }
 
 template <int LAT, int ST, int NC>
 static hipError_t init_t(const Ctx& c, const double* rho, const double* u, const double* C) {
     auto P = make_phys<SR<ST>>(c);
-    hipLaunchKernelGGL((k_init_eq<LAT, ST, NC>), node_grid(c), node_block(c), 0, c.stream, P, c.N,
-                       (STT<ST>*)c.fA, (STT<ST>*)c.hA, c.links, rho, u, C);
+    const Geo g = make_geo(c, 256);
+    // the dense psi field must read 0 on solid nodes
+    const long long np = (long long)NC * c.N;
+    hipLaunchKernelGGL((k_fill_r<SR<ST>>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, c.stream,
+                       (SR<ST>*)c.psi, np);
+    hipLaunchKernelGGL((k_init_eq<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (STT<ST>*)c.fA,
+                       (STT<ST>*)c.hA, rho, u, C);
     return hipGetLastError();
 }
 
 template <int LAT, int ST, int NC>
 static hipError_t moments_t(const Ctx& c, double* rho, double* u, double* C) {
     auto P = make_phys<SR<ST>>(c);
-    const dim3 b = node_block(c), g = node_grid(c);
-    hipLaunchKernelGGL((k_density_psi<LAT, ST, NC>), g, b, 0, c.stream, P, c.N, (const STT<ST>*)c.fA, c.links,
+    const Geo g = make_geo(c, 256);
+    auto fill = [&](double* p, long long n) {
+        if (p) hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, p, n, 0.0);
+    };
+    fill(rho, (long long)NC * c.N);
+    fill(u, 3LL * c.N);
+    fill(C, c.N);
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_moments_out<LAT, ST, NC>), g, b, 0, c.stream, P, c.N, (const STT<ST>*)c.fA,
-                       (const STT<ST>*)c.hA, c.links, (const SR<ST>*)c.psi, rho, u, C);
+    hipLaunchKernelGGL((k_moments_out<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g,
+                       (const STT<ST>*)c.fA, (const STT<ST>*)c.hA, (const SR<ST>*)c.psi, rho, u, C);
     return hipGetLastError();
 }
 
 template <int LAT, int ST, int NC>
 static hipError_t monitor_t(const Ctx& c, int have_snapshot) {
     auto P = make_phys<SR<ST>>(c);
-    const dim3 b = node_block(c), g = node_grid(c);
-    hipLaunchKernelGGL((k_density_psi<LAT, ST, NC>), g, b, 0, c.stream, P, c.N, (const STT<ST>*)c.fA, c.links,
+    const Geo g = make_geo(c, 256);
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_monitor<LAT, ST, NC>), g, b, 0, c.stream, P, c.N, (const STT<ST>*)c.fA,
-                       (const STT<ST>*)c.hA, c.links, (const SR<ST>*)c.psi, (SR<ST>*)c.snap, have_snapshot,
-                       c.partials);
+    hipLaunchKernelGGL((k_monitor<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+                       (const STT<ST>*)c.hA, (const SR<ST>*)c.psi, (SR<ST>*)c.snap, have_snapshot, c.partials);
     hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(256), 0, c.stream, (const double*)c.partials,
-                       (long long)monitor_blocks(c), c.result);
+                       (long long)g.nblocks, c.result);
     return hipGetLastError();
 }
 
-// fused kernel (defined in fused.hip)
-template <int LAT, int ST, int NC>
-hipError_t step_fused(const Ctx& c);
-
-#define MCLBM_DISPATCH(FN, ...)                                                             \
-    do {                                                                                    \
-        const int key = c.lat * 100 + c.st * 10 + c.nc;                                     \
-        switch (key) {                                                                      \
-            case 1: return FN<0, 0, 1>(__VA_ARGS__);                                        \
-            case 2: return FN<0, 0, 2>(__VA_ARGS__);                                        \
-            case 11: return FN<0, 1, 1>(__VA_ARGS__);                                       \
-            case 12: return FN<0, 1, 2>(__VA_ARGS__);                                       \
-            case 21: return FN<0, 2, 1>(__VA_ARGS__);                                       \
-            case 22: return FN<0, 2, 2>(__VA_ARGS__);                                       \
-            case 31: return FN<0, 3, 1>(__VA_ARGS__);                                       \
-            case 32: return FN<0, 3, 2>(__VA_ARGS__);                                       \
-            case 101: return FN<1, 0, 1>(__VA_ARGS__);                                      \
-            case 102: return FN<1, 0, 2>(__VA_ARGS__);                                      \
-            case 111: return FN<1, 1, 1>(__VA_ARGS__);                                      \
-            case 112: return FN<1, 1, 2>(__VA_ARGS__);                                      \
-            case 121: return FN<1, 2, 1>(__VA_ARGS__);                                      \
-            case 122: return FN<1, 2, 2>(__VA_ARGS__);                                      \
-            case 131: return FN<1, 3, 1>(__VA_ARGS__);                                      \
-            case 132: return FN<1, 3, 2>(__VA_ARGS__);                                      \
-            default: return hipErrorInvalidValue;                                           \
-        }                                                                                   \
+#define MCLBM_DISPATCH(FN, ...)                                \
+    do {                                                       \
+        const int key = c.lat * 100 + c.st * 10 + c.nc;        \
+        switch (key) {                                         \
+            case 1: return FN<0, 0, 1>(__VA_ARGS__);           \
+            case 2: return FN<0, 0, 2>(__VA_ARGS__);           \
+            case 11: return FN<0, 1, 1>(__VA_ARGS__);          \
+            case 12: return FN<0, 1, 2>(__VA_ARGS__);          \
+            case 21: return FN<0, 2, 1>(__VA_ARGS__);          \
+            case 22: return FN<0, 2, 2>(__VA_ARGS__);          \
+            case 31: return FN<0, 3, 1>(__VA_ARGS__);          \
+            case 32: return FN<0, 3, 2>(__VA_ARGS__);          \
+            case 101: return FN<1, 0, 1>(__VA_ARGS__);         \
+            case 102: return FN<1, 0, 2>(__VA_ARGS__);         \
+            case 111: return FN<1, 1, 1>(__VA_ARGS__);         \
+            case 112: return FN<1, 1, 2>(__VA_ARGS__);         \
+            case 121: return FN<1, 2, 1>(__VA_ARGS__);         \
+            case 122: return FN<1, 2, 2>(__VA_ARGS__);         \
+            case 131: return FN<1, 3, 1>(__VA_ARGS__);         \
+            case 132: return FN<1, 3, 2>(__VA_ARGS__);         \
+            default: return hipErrorInvalidValue;              \
+        }                                                      \
     } while (0)
 
 hipError_t k_init(const Ctx& c, const double* rho, const double* u, const double* C) {
     MCLBM_DISPATCH(init_t, c, rho, u, C);
 }
-
-hipError_t k_step(const Ctx& c) {
-    if (c.variant == 1) MCLBM_DISPATCH(step_two_pass, c);
-    MCLBM_DISPATCH(step_fused, c);
-}
-
+hipError_t k_step(const Ctx& c) { MCLBM_DISPATCH(step_t, c); }
 hipError_t k_moments(const Ctx& c, double* rho, double* u, double* C) { MCLBM_DISPATCH(moments_t, c, rho, u, C); }
-
 hipError_t k_monitor(const Ctx& c, int have_snapshot) { MCLBM_DISPATCH(monitor_t, c, have_snapshot); }
 
 }  // namespace mclbm

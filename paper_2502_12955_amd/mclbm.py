@@ -24,7 +24,6 @@ FORCING = {"guo": 0, "sc": 1}
 SOLUTE = {"off": 0, "periodic": 1, "inlet_outlet_x": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 LATTICE = {"D2Q9": 0, "D3Q19": 1}
-VARIANT = {"fused": 0, "two_pass": 1}
 STORE_DTYPE = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16}
 
 
@@ -81,7 +80,7 @@ _lib = None
 EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "mclbm_get_geometry",
            "mclbm_init_fields", "mclbm_step", "mclbm_get_moments", "mclbm_get_monitors",
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
-           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_variant", "mclbm_get_step",
+           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_get_step",
            "mclbm_synchronize", "mclbm_destroy", "mclbm_last_error")
 
 
@@ -108,7 +107,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_set_populations.argtypes = [vp, vp, i32]
     lib.mclbm_population_bytes.argtypes = [vp, i32, ct.POINTER(sz)]
     lib.mclbm_run_to_residual.argtypes = [vp, dbl, i64, ct.POINTER(i64)]
-    lib.mclbm_set_variant.argtypes = [vp, i32, i32, i32, i32]
+    lib.mclbm_set_launch.argtypes = [vp, i32]
     lib.mclbm_get_step.argtypes = [vp, ct.POINTER(i64)]
     lib.mclbm_synchronize.argtypes = [vp]
     lib.mclbm_destroy.argtypes = [vp]
@@ -229,8 +228,8 @@ def run_to_residual(h, tol: float, max_steps: int):
     return rc == OK, n.value
 
 
-def set_variant(h, variant="fused", tile_x=0, tile_y=0, zchunk=0):
-    _check(load().mclbm_set_variant(h, _enum(variant, VARIANT), tile_x, tile_y, zchunk), h)
+def set_launch(h, block_threads=256):
+    _check(load().mclbm_set_launch(h, int(block_threads)), h)
 
 
 def get_step(h) -> int:
@@ -313,8 +312,8 @@ class Lattice:
     def run_to_residual(self, tol, max_steps):
         return run_to_residual(self.h, tol, max_steps)
 
-    def set_variant(self, variant="fused", tile_x=0, tile_y=0, zchunk=0):
-        set_variant(self.h, variant, tile_x, tile_y, zchunk)
+    def set_launch(self, block_threads=256):
+        set_launch(self.h, block_threads)
 
     @property
     def step_count(self):

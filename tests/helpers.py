@@ -14,15 +14,12 @@ def nrel(a, b):
     return num / den if den else num
 
 
-def gpu_lattice(p, mask, rho, u=None, C=None, variant=None, tile=None):
+def gpu_lattice(p, mask, rho, u=None, C=None, block=None):
     from paper_2502_12955_amd import mclbm
 
     lat = mclbm.Lattice(p)
-    if variant is not None:
-        kw = {}
-        if tile is not None:
-            kw = dict(tile_x=tile[0], tile_y=tile[1], zchunk=tile[2])
-        lat.set_variant(variant, **kw)
+    if block is not None:
+        lat.set_launch(block)
     lat.set_geometry(mask)
     lat.init_fields(rho, u, C)
     return lat
