@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--block", type=int, default=256, help="threads per workgroup of the step kernels")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -116,6 +118,12 @@ def main():
     log(f"[bench] lattice ready: {args.n}^3, fluid {nfluid}, reclassified {nrc}")
 
     stream = lat.stream
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     lat.step(args.warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)

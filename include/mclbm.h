@@ -173,10 +173,54 @@ int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes);
  * was reached first, or an error. */
 int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_t* steps_taken);
 
-/* Threads per workgroup of the two step kernels (64, 128 or 256; default
- * 256).  Results do not depend on it (each fluid node is updated by one thread
- * with the same arithmetic); it is a tuning knob for the launch. */
-int mclbm_set_launch(mclbm_handle* h, int32_t block_threads);
+/* Launch shape of the step kernels: block_threads per workgroup (64, 128 or
+ * 256; default 256) and grid_blocks (0 = one pass over the fluid-node chunks,
+ * default; else a persistent grid of that many workgroups, a multiple of 8,
+ * that loops over the work list).  Every fluid node is updated by one thread
+ * with the same arithmetic, so results do not depend on the launch shape. */
+int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks);
+
+/* Time the step kernels over a set of launch shapes and keep the fastest.
+ * Candidates: block_threads 64, 128, 256 crossed with grid_blocks 0 (one
+ * pass) and persistent grids of 8, 16 and 32 wavefronts per compute unit.
+ * Each candidate runs 2 untimed steps, then trial_steps (>= 1) steps timed
+ * with HIP events on the handle's stream.  Needs set_geometry; it overwrites
+ * the populations (uniform rest state, density 1), so init_fields must be
+ * called afterwards (ESTATE until then).  The chosen shape is applied as by
+ * mclbm_set_launch and returned in *block_threads, *grid_blocks and
+ * *ms_per_step (any may be NULL).  The candidates' timings are written to
+ * table[3 * i + 0..2] = (block, grid, ms per step) for i < table_rows (table
+ * may be NULL); *n_rows (may be NULL) receives the number of candidates. */
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
+                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
+
+/* enable != 0: run each aligned interval of monitor_every steps (which must
+ * be even) as one replay of a captured HIP graph (the step kernels plus the
+ * monitor), on a library-owned stream ordered after the caller's stream.
+ * The graph is captured on first use, once a residual snapshot exists, and
+ * dropped by set_geometry, init_fields, set_launch or set_graph. */
+int mclbm_set_graph(mclbm_handle* h, int32_t enable);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent samples (for callers that run many small porous
+ * samples at once).  The n samples share every parameter except nx, ny, nz
+ * (EINVAL otherwise).  A batch handle accepts every call above; host arrays
+ * are the per-sample arrays concatenated in sample order (sample s occupies
+ * a block of fields * N_s values starting at fields * sum_{t<s} N_t), and
+ * set_geometry takes the concatenated masks.  mclbm_run_to_residual stops
+ * (freezes) each sample at the first monitor where its own maximum residual is
+ * <= tol, keeps running the others, and returns MCLBM_OK when every sample has
+ * converged.  mclbm_get_monitors then reports masses and counts summed over
+ * samples and residuals maximised over the samples still running.  A single
+ * lattice is a batch of one. */
+int mclbm_required_bytes_batch(const mclbm_params* p, int32_t n, size_t* bytes);
+int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_t arena_bytes,
+                     void* hip_stream, mclbm_handle** out);
+
+/* Monitors of sample s (layout of mclbm_get_monitors), plus out[11] = step
+ * at which the sample converged in run_to_residual (-1 if not) and out[12] =
+ * 1 if it is frozen. */
+int mclbm_get_sample_monitors(mclbm_handle* h, int32_t s, double out[16]);
 
 /* Current step counter. */
 int mclbm_get_step(mclbm_handle* h, int64_t* step);

@@ -8,8 +8,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "libmclbm.so")
-SOURCES = ["api.cpp", "geometry.cpp", "kernels.hip"]
+LIBS = {
+    "libmclbm.so": ["api.cpp", "geometry.cpp", "kernels.hip"],
+    "libwarmnet.so": ["warmnet.hip"],
+}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -19,11 +21,10 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = True, jobs: int = 4) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
-    procs = []
-    for src in SOURCES:
+def _build_one(hipcc, out_name, sources, verbose, jobs):
+    out = os.path.join(HERE, out_name)
+    objs, procs = [], []
+    for src in sources:
         obj = os.path.join(CSRC, src + ".o")
         cmd = [hipcc] + [f for f in HIPCC_FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
@@ -33,20 +34,25 @@ def build(verbose: bool = True, jobs: int = 4) -> str:
         procs.append(subprocess.Popen(cmd))
         objs.append(obj)
         if len(procs) >= jobs:
-            p = procs.pop(0)
-            if p.wait() != 0:
+            if procs.pop(0).wait() != 0:
                 raise RuntimeError("hipcc failed")
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", OUT + ".tmp"] + objs
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out + ".tmp"] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)
-    os.replace(OUT + ".tmp", OUT)
+    os.replace(out + ".tmp", out)
     for o in objs:
         os.remove(o)
-    return OUT
+    return out
+
+
+def build(verbose: bool = True, jobs: int = 4) -> list:
+    """Compile every HIP library (always, also when up to date)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    return [_build_one(hipcc, name, srcs, verbose, jobs) for name, srcs in LIBS.items()]
 
 
 if __name__ == "__main__":

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mclbm.h"
+#include "mclbm.h"
 #include "geometry.hpp"
 #include "kernels.hpp"
 
@@ -89,10 +89,27 @@ uint16_t float_to_bf16_rne_h(float f) {
 
 }  // namespace
 
+struct SampleHost {
+    int nx, ny, nz;
+    long long N;      // box nodes
+    long long dbase;  // first box node in the concatenated dense arrays
+    long long kbase;  // first fluid index (multiple of 64)
+    long long nf;     // fluid nodes
+    std::vector<uint8_t> mask;
+    std::vector<unsigned> pos;  // box index of each fluid node, increasing
+    bool frozen = false;        // converged and excluded from the work list
+    long long conv_step = -1;
+    double mon[16];
+};
+
 struct mclbm_handle {
-    mclbm_params p{};
+    mclbm_params p{};  // physics (sample 0's dimensions)
     int Q = 0, QS = 0, NC = 0;
-    long long N = 0;
+    int S = 0;
+    std::vector<SampleHost> smp;
+    long long Ntot = 0;      // box nodes of all samples
+    long long Mmax = 0;      // fluid-node capacity (sum of padded box sizes)
+    long long nchunks = 0;   // chunks of the current fluid numbering
     hipStream_t stream = nullptr;
     void* arena = nullptr;
     bool own_arena = false;
@@ -107,24 +124,32 @@ struct mclbm_handle {
     double* stage = nullptr;
     double* partials = nullptr;
     double* result = nullptr;
-    double* host_result = nullptr;  // pinned
-    // host state
-    std::vector<uint8_t> mask;
-    std::vector<unsigned> pos_host;  // box index of each fluid node, increasing
-    int64_t nfluid = 0;
+    SampleDev* smp_dev = nullptr;
+    int* chunk_sample = nullptr;
+    int* work = nullptr;
+    int* nwork = nullptr;
+    double* host_result = nullptr;  // pinned [S][16]
+    int* host_nwork = nullptr;      // pinned
+    // state
     bool geom_set = false, fields_set = false;
     int64_t step = 0;
     bool snap_valid = false;
     double mon[16];
     double rhobar[2] = {0, 0};
-    int block = 256;
+    int block = 256, grid = 0;
+    // graph replay of monitor_every steps (one per A/B parity)
+    bool use_graph = false;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     std::string err;
 };
 
 namespace {
 
 struct Layout {
-    size_t fA, fB, hA, hB, map, pos, links, psi, snap, stage, partials, result, total;
+    size_t fA, fB, hA, hB, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample, work, nwork,
+        total;
 };
 
 Ctx base_ctx(const mclbm_params& p) {
@@ -133,10 +158,6 @@ Ctx base_ctx(const mclbm_params& p) {
     c.lat = p.lattice;
     c.st = p.storage;
     c.nc = p.ncomp;
-    c.nx = p.nx;
-    c.ny = p.ny;
-    c.nz = p.nz;
-    c.N = (long long)p.nx * p.ny * p.nz;
     c.forcing = p.forcing;
     c.solute = p.solute;
     for (int s = 0; s < 2; ++s) {
@@ -153,10 +174,17 @@ Ctx base_ctx(const mclbm_params& p) {
     return c;
 }
 
-Layout layout_for(const mclbm_params& p) {
-    const long long N = (long long)p.nx * p.ny * p.nz;
+Layout layout_for(const mclbm_params* ps, int n) {
+    const mclbm_params& p = ps[0];
     const int Q = flow_q(p.lattice), QS = solute_q(p.lattice), NC = p.ncomp;
     const size_t sb = store_bytes(p.storage), ab = arith_bytes(p.storage);
+    long long Ntot = 0, M = 0;
+    for (int s = 0; s < n; ++s) {
+        const long long N = (long long)ps[s].nx * ps[s].ny * ps[s].nz;
+        Ntot += N;
+        M += pad64(N);  // capacity: every node fluid
+    }
+    const size_t nch = (size_t)(M / 64);
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -164,26 +192,28 @@ Layout layout_for(const mclbm_params& p) {
         off = o + bytes;
         return o;
     };
-    // fluid-only arrays are sized for the worst case (every node fluid)
-    const size_t M = (size_t)pad64(N);
     L.fA = take((size_t)NC * Q * M * sb);
     L.fB = take((size_t)NC * Q * M * sb);
     const size_t hb = p.solute ? (size_t)QS * M * sb : 0;
     L.hA = take(hb);
     L.hB = take(hb);
-    L.map = take((size_t)N * 4);
-    L.pos = take(M * 4);
-    L.links = take(M * 4);
-    L.psi = take((size_t)NC * N * ab);
+    L.map = take((size_t)Ntot * 4);
+    L.pos = take((size_t)M * 4);
+    L.links = take((size_t)M * 4);
+    L.psi = take((size_t)NC * Ntot * ab);
     L.snap = take((size_t)5 * M * ab);
-    L.stage = take((size_t)(NC + 4) * N * 8);
-    L.partials = take(monitor_blocks_max(N) * MON_NV * 8);
-    L.result = take(16 * 8);
+    L.stage = take((size_t)(NC + 4) * Ntot * 8);
+    L.partials = take(nch * MON_NV * 8);
+    L.result = take((size_t)n * 16 * 8);
+    L.smp = take((size_t)n * sizeof(SampleDev));
+    L.chunk_sample = take(nch * 4);
+    L.work = take(nch * 4);
+    L.nwork = take(64);
     L.total = align256(off);
     return L;
 }
 
-bool validate(const mclbm_params* p, std::string& why) {
+bool validate_one(const mclbm_params* p, std::string& why) {
     char buf[256];
     if (!p) {
         why = "params is NULL";
@@ -199,10 +229,6 @@ bool validate(const mclbm_params* p, std::string& why) {
     }
     if (p->lattice == MCLBM_D2Q9 && p->nz != 1) {
         why = "D2Q9 needs nz == 1";
-        return false;
-    }
-    if ((long long)p->nx * p->ny * p->nz >= (1LL << 31)) {
-        why = "lattice has more than 2^31 - 1 nodes";
         return false;
     }
     if (p->ncomp != 1 && p->ncomp != 2) {
@@ -260,6 +286,38 @@ bool validate(const mclbm_params* p, std::string& why) {
     return true;
 }
 
+// every sample valid, same physics as sample 0, sizes within the 32-bit indexing
+bool validate(const mclbm_params* p, int n, std::string& why) {
+    if (!p || n < 1) {
+        why = "need at least one sample";
+        return false;
+    }
+    long long Ntot = 0, M = 0;
+    for (int s = 0; s < n; ++s) {
+        if (!validate_one(&p[s], why)) {
+            if (n > 1) why = "sample " + std::to_string(s) + ": " + why;
+            return false;
+        }
+        mclbm_params a = p[0], b = p[s];
+        a.nx = b.nx;
+        a.ny = b.ny;
+        a.nz = b.nz;
+        if (memcmp(&a, &b, sizeof(a)) != 0) {
+            why = "sample " + std::to_string(s) + " differs from sample 0 in more than its dimensions";
+            return false;
+        }
+        const long long N = (long long)p[s].nx * p[s].ny * p[s].nz;
+        Ntot += N;
+        M += pad64(N);
+    }
+    const int Q = flow_q(p[0].lattice);
+    if (M * (long long)(p[0].ncomp * Q) >= (1LL << 32) || Ntot >= (1LL << 31)) {
+        why = "lattice too large for 32-bit node indexing";
+        return false;
+    }
+    return true;
+}
+
 int fail(mclbm_handle* h, int code, const std::string& msg) {
     if (h) h->err = msg;
     else g_global_error = msg;
@@ -271,72 +329,198 @@ int hip_fail(mclbm_handle* h, hipError_t e, const char* what) {
     return fail(h, MCLBM_EHIP, m);
 }
 
-#define HIPCHK(h, expr)                                     \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
+#define HIPCHK(h, expr)                                      \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
         if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
     } while (0)
 
-Ctx make_ctx(mclbm_handle* h) {
+Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     Ctx c = base_ctx(h->p);
+    c.nsamples = h->S;
+    c.Ntot = h->Ntot;
+    c.nchunks = h->nchunks;
     c.rhobar[0] = h->rhobar[0];
     c.rhobar[1] = h->rhobar[1];
-    c.stream = h->stream;
+    c.stream = stream;
     c.fA = h->fA;
     c.fB = h->fB;
     c.hA = h->hA;
     c.hB = h->hB;
-    c.Nf = h->nfluid;
-    c.links = h->links;
+    c.smp = h->smp_dev;
+    c.chunk_sample = h->chunk_sample;
     c.pos = h->pos;
     c.map = h->map;
+    c.links = h->links;
     c.psi = h->psi;
     c.snap = h->snap;
+    c.work = h->work;
+    c.nwork = h->nwork;
     c.partials = h->partials;
     c.result = h->result;
     c.block = h->block;
+    c.grid = h->grid;
     return c;
 }
+Ctx make_ctx(mclbm_handle* h) { return make_ctx(h, h->stream); }
 
 double ratio(double num, double den) {
     if (den == 0.0) return num == 0.0 ? 0.0 : INFINITY;
     return sqrt(num / den);
 }
 
-// read the monitor result into h->mon; returns 1 if it counted non-finite values
-int collect_monitor(mclbm_handle* h, bool had_snapshot) {
-    const double* r = h->host_result;
-    for (int k = 0; k < 16; ++k) h->mon[k] = 0.0;
-    h->mon[0] = (double)h->step;
-    h->mon[1] = r[0];
-    h->mon[2] = h->NC == 2 ? r[1] : 0.0;
-    h->mon[3] = r[2];
-    if (had_snapshot) {
-        h->mon[4] = ratio(r[3], r[4]);
-        h->mon[5] = ratio(r[5], r[6]);
-        h->mon[6] = ratio(r[7], r[8]);
-    } else {
-        h->mon[4] = h->mon[5] = h->mon[6] = INFINITY;
-        if (h->NC == 1) h->mon[5] = 0.0;
-        if (!h->p.solute) h->mon[6] = 0.0;
-    }
-    if (h->NC == 1) h->mon[5] = 0.0;
-    if (!h->p.solute) h->mon[6] = 0.0;
-    h->mon[7] = r[9];
-    h->mon[8] = r[10];
-    h->mon[9] = std::max(h->mon[4], std::max(h->mon[5], h->mon[6]));
-    h->mon[10] = (double)h->step;
-    return r[9] != 0.0 || !isfinite(r[0]) || !isfinite(r[2]);
+void drop_graphs(mclbm_handle* h) {
+    for (auto& g : h->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
 }
 
-int run_monitor(mclbm_handle* h) {
-    Ctx c = make_ctx(h);
-    const bool had = h->snap_valid;
-    HIPCHK(h, k_monitor(c, had ? 1 : 0));
-    HIPCHK(h, hipMemcpyAsync(h->host_result, h->result, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    h->snap_valid = true;
+// Monitor values of one sample from the raw sums r[0..10].
+void sample_monitor(mclbm_handle* h, SampleHost& sm, const double* r, bool had) {
+    double* m = sm.mon;
+    for (int k = 0; k < 16; ++k) m[k] = 0.0;
+    m[0] = (double)h->step;
+    m[1] = r[0];
+    m[2] = h->NC == 2 ? r[1] : 0.0;
+    m[3] = r[2];
+    m[4] = had ? ratio(r[3], r[4]) : INFINITY;
+    m[5] = (h->NC == 1) ? 0.0 : (had ? ratio(r[5], r[6]) : INFINITY);
+    m[6] = (!h->p.solute) ? 0.0 : (had ? ratio(r[7], r[8]) : INFINITY);
+    m[7] = r[9];
+    m[8] = r[10];
+    m[9] = std::max(m[4], std::max(m[5], m[6]));
+    m[10] = (double)h->step;
+    m[11] = (double)sm.conv_step;
+    m[12] = sm.frozen ? 1.0 : 0.0;
+}
+
+// Aggregate over samples: masses and counts summed, residuals the maximum over
+// the samples still running (all samples if none is frozen).
+void aggregate_monitor(mclbm_handle* h) {
+    double* m = h->mon;
+    for (int k = 0; k < 16; ++k) m[k] = 0.0;
+    m[0] = h->smp[0].mon[0];
+    bool any_active = false;
+    for (auto& s : h->smp) any_active |= !s.frozen;
+    for (auto& s : h->smp) {
+        for (int k : {1, 2, 3, 7, 8}) m[k] += s.mon[k];
+        if (!any_active || !s.frozen)
+            for (int k : {4, 5, 6, 9}) m[k] = std::max(m[k], s.mon[k]);
+    }
+    m[10] = (double)h->step;
+}
+
+// Read the monitor results of the last monitor launch (stream already ordered).
+int collect_monitor(mclbm_handle* h, bool had) {
+    HIPCHK(h, hipMemcpyAsync(h->host_result, h->result, (size_t)h->S * 16 * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (collect_monitor(h, had)) return fail(h, MCLBM_EDIVERGED, "non-finite value at a monitor");
+    bool bad = false;
+    for (int s = 0; s < h->S; ++s) {
+        SampleHost& sm = h->smp[s];
+        if (sm.frozen) continue;
+        const double* r = h->host_result + (size_t)s * 16;
+        sample_monitor(h, sm, r, had);
+        bad |= r[9] != 0.0 || !isfinite(r[0]) || !isfinite(r[2]);
+    }
+    aggregate_monitor(h);
+    if (bad) return fail(h, MCLBM_EDIVERGED, "non-finite value at a monitor");
+    return MCLBM_OK;
+}
+
+// Upload the list of chunks of the samples that are not frozen.
+int upload_work(mclbm_handle* h) {
+    std::vector<int> w;
+    w.reserve((size_t)h->nchunks);
+    for (auto& s : h->smp) {
+        if (s.frozen) continue;
+        const long long c0 = s.kbase / 64, nc = (s.nf + 63) / 64;
+        for (long long c = 0; c < nc; ++c) w.push_back((int)(c0 + c));
+    }
+    *h->host_nwork = (int)w.size();
+    if (!w.empty())
+        HIPCHK(h, hipMemcpyAsync(h->work, w.data(), w.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->nwork, h->host_nwork, 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MCLBM_OK;
+}
+
+// Copy a frozen sample's current state into buffer B as well, so that later
+// A/B swaps keep presenting its final state.
+int mirror_sample(mclbm_handle* h, const SampleHost& s) {
+    const size_t sb = store_bytes(h->p.storage);
+    const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
+    const size_t c0 = (size_t)(s.kbase / 64), nc = (size_t)((s.nf + 63) / 64);
+    HIPCHK(h, hipMemcpyAsync((char*)h->fB + c0 * PF * 64 * sb, (char*)h->fA + c0 * PF * 64 * sb, nc * PF * 64 * sb,
+                             hipMemcpyDeviceToDevice, h->stream));
+    if (PS)
+        HIPCHK(h, hipMemcpyAsync((char*)h->hB + c0 * PS * 64 * sb, (char*)h->hA + c0 * PS * 64 * sb,
+                                 nc * PS * 64 * sb, hipMemcpyDeviceToDevice, h->stream));
+    return MCLBM_OK;
+}
+
+// Launch one step (density + collide) on `stream` and swap A/B.
+int launch_step(mclbm_handle* h, hipStream_t stream) {
+    Ctx c = make_ctx(h, stream);
+    HIPCHK(h, k_step(c));
+    std::swap(h->fA, h->fB);
+    std::swap(h->hA, h->hB);
+    ++h->step;
+    return MCLBM_OK;
+}
+
+// Capture monitor_every steps plus the monitor into a graph for the current
+// A/B parity (requires an even monitor_every so that the parity returns).
+int graph_for_parity(mclbm_handle* h, int parity, hipGraphExec_t* out) {
+    if (h->gexec[parity]) {
+        *out = h->gexec[parity];
+        return MCLBM_OK;
+    }
+    if (!h->gstream) {
+        HIPCHK(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        HIPCHK(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+        HIPCHK(h, hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+    }
+    const int K = h->p.monitor_every;
+    const int64_t step0 = h->step;
+    void *fA = h->fA, *fB = h->fB, *hA = h->hA, *hB = h->hB;
+    HIPCHK(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < K && e == hipSuccess; ++s) {
+        Ctx c = make_ctx(h, h->gstream);
+        e = k_step(c);
+        std::swap(h->fA, h->fB);
+        std::swap(h->hA, h->hB);
+    }
+    if (e == hipSuccess) e = k_monitor(make_ctx(h, h->gstream), 1);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(h->gstream, &graph);
+    h->fA = fA, h->fB = fB, h->hA = hA, h->hB = hB;
+    h->step = step0;
+    if (e != hipSuccess) return hip_fail(h, e, "capture");
+    if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
+    hipError_t e3 = hipGraphInstantiate(&h->gexec[parity], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return hip_fail(h, e3, "hipGraphInstantiate");
+    *out = h->gexec[parity];
+    return MCLBM_OK;
+}
+
+// Run one full monitor interval through the graph (caller checks alignment).
+int replay_interval(mclbm_handle* h) {
+    // which of the two arena buffers currently holds the state selects the graph
+    const int p = h->fA < h->fB ? 0 : 1;
+    hipGraphExec_t ge = nullptr;
+    int rc = graph_for_parity(h, p, &ge);
+    if (rc != MCLBM_OK) return rc;
+    HIPCHK(h, hipEventRecord(h->ev_in, h->stream));
+    HIPCHK(h, hipStreamWaitEvent(h->gstream, h->ev_in, 0));
+    HIPCHK(h, hipGraphLaunch(ge, h->gstream));
+    HIPCHK(h, hipEventRecord(h->ev_out, h->gstream));
+    HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_out, 0));
+    h->step += h->p.monitor_every;  // K even: A/B assignment unchanged
     return MCLBM_OK;
 }
 
@@ -344,21 +528,23 @@ int run_monitor(mclbm_handle* h) {
 
 extern "C" {
 
-int mclbm_required_bytes(const mclbm_params* p, size_t* bytes) {
+int mclbm_required_bytes_batch(const mclbm_params* p, int32_t n, size_t* bytes) {
     std::string why;
-    if (!validate(p, why)) return fail(nullptr, MCLBM_EINVAL, why);
+    if (!validate(p, n, why)) return fail(nullptr, MCLBM_EINVAL, why);
     if (!bytes) return fail(nullptr, MCLBM_EINVAL, "bytes is NULL");
-    *bytes = layout_for(*p).total;
+    *bytes = layout_for(p, n).total;
     return MCLBM_OK;
 }
 
-int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_bytes, void* hip_stream,
-                       mclbm_handle** out) {
+int mclbm_required_bytes(const mclbm_params* p, size_t* bytes) { return mclbm_required_bytes_batch(p, 1, bytes); }
+
+int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_t arena_bytes, void* hip_stream,
+                     mclbm_handle** out) {
     std::string why;
     if (!out) return fail(nullptr, MCLBM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!validate(p, why)) return fail(nullptr, MCLBM_EINVAL, why);
-    Layout L = layout_for(*p);
+    if (!validate(p, n, why)) return fail(nullptr, MCLBM_EINVAL, why);
+    Layout L = layout_for(p, n);
     if (device_arena && arena_bytes < L.total) {
         char buf[160];
         snprintf(buf, sizeof buf, "arena of %zu bytes is smaller than the %zu bytes required", arena_bytes, L.total);
@@ -367,11 +553,28 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     if (device_arena && ((uintptr_t)device_arena & 255u))
         return fail(nullptr, MCLBM_EINVAL, "arena must be 256-byte aligned");
     mclbm_handle* h = new mclbm_handle();
-    h->p = *p;
-    h->Q = flow_q(p->lattice);
-    h->QS = solute_q(p->lattice);
-    h->NC = p->ncomp;
-    h->N = (long long)p->nx * p->ny * p->nz;
+    h->p = p[0];
+    h->Q = flow_q(p[0].lattice);
+    h->QS = solute_q(p[0].lattice);
+    h->NC = p[0].ncomp;
+    h->S = n;
+    h->smp.resize(n);
+    long long dbase = 0;
+    for (int s = 0; s < n; ++s) {
+        SampleHost& sm = h->smp[s];
+        sm.nx = p[s].nx;
+        sm.ny = p[s].ny;
+        sm.nz = p[s].nz;
+        sm.N = (long long)sm.nx * sm.ny * sm.nz;
+        sm.dbase = dbase;
+        sm.kbase = 0;
+        sm.nf = 0;
+        for (int k = 0; k < 16; ++k) sm.mon[k] = 0.0;
+        sm.mon[0] = -1.0;
+        dbase += sm.N;
+        h->Mmax += pad64(sm.N);
+    }
+    h->Ntot = dbase;
     h->stream = (hipStream_t)hip_stream;
     for (int k = 0; k < 16; ++k) h->mon[k] = 0.0;
     h->mon[0] = -1.0;
@@ -390,18 +593,24 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     char* base = (char*)h->arena;
     h->fA = base + L.fA;
     h->fB = base + L.fB;
-    h->hA = p->solute ? base + L.hA : nullptr;
-    h->hB = p->solute ? base + L.hB : nullptr;
-    h->links = (uint32_t*)(base + L.links);
+    h->hA = p[0].solute ? base + L.hA : nullptr;
+    h->hB = p[0].solute ? base + L.hB : nullptr;
     h->map = (int*)(base + L.map);
     h->pos = (unsigned*)(base + L.pos);
+    h->links = (uint32_t*)(base + L.links);
     h->psi = base + L.psi;
     h->snap = base + L.snap;
     h->stage = (double*)(base + L.stage);
     h->partials = (double*)(base + L.partials);
     h->result = (double*)(base + L.result);
-    hipError_t e = hipHostMalloc((void**)&h->host_result, 16 * sizeof(double), hipHostMallocDefault);
+    h->smp_dev = (SampleDev*)(base + L.smp);
+    h->chunk_sample = (int*)(base + L.chunk_sample);
+    h->work = (int*)(base + L.work);
+    h->nwork = (int*)(base + L.nwork);
+    hipError_t e = hipHostMalloc((void**)&h->host_result, (size_t)n * 16 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_nwork, 64, hipHostMallocDefault);
     if (e != hipSuccess) {
+        if (h->host_result) (void)hipHostFree(h->host_result);
         if (h->own_arena) (void)hipFree(h->arena);
         delete h;
         return fail(nullptr, MCLBM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
@@ -410,54 +619,84 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     return MCLBM_OK;
 }
 
+int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_bytes, void* hip_stream,
+                       mclbm_handle** out) {
+    return mclbm_init_batch(p, 1, device_arena, arena_bytes, hip_stream, out);
+}
+
 int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_reclassified) {
     if (!h) return MCLBM_EINVAL;
     if (!solid_mask) return fail(h, MCLBM_EINVAL, "solid_mask is NULL");
-    h->mask.assign(solid_mask, solid_mask + h->N);
-    for (auto& m : h->mask) m = m ? 1 : 0;
-    GeomSpec gs{h->p.lattice, h->p.nx, h->p.ny, h->p.nz, h->p.solute};
-    const int64_t nrc = pinch_fill(gs, h->mask);
-    int64_t nf = 0;
-    for (auto m : h->mask) nf += (m == 0);
-    if (n_reclassified) *n_reclassified = nrc;
-    if (nf == 0) {
-        h->geom_set = false;
-        return fail(h, MCLBM_EINVAL, "no fluid node left after reclassification");
-    }
-    std::vector<uint32_t> words;
-    link_words(gs, h->mask, words, nullptr, nullptr);
-    // fluid numbering in increasing box index; link words of fluid nodes only
-    const long long N = h->N;
-    h->pos_host.clear();
-    h->pos_host.reserve((size_t)nf);
-    std::vector<int> map((size_t)N, -1);
-    for (long long n = 0; n < N; ++n)
-        if (!h->mask[n]) {
-            map[n] = (int)h->pos_host.size();
-            h->pos_host.push_back((unsigned)n);
+    drop_graphs(h);
+    h->geom_set = h->fields_set = false;
+    int64_t nrc = 0;
+    long long kbase = 0;
+    std::vector<int> map((size_t)h->Ntot, -1);
+    std::vector<unsigned> pos;
+    std::vector<uint32_t> links;
+    std::vector<int> chunk_sample;
+    std::vector<SampleDev> sd(h->S);
+    for (int s = 0; s < h->S; ++s) {
+        SampleHost& sm = h->smp[s];
+        sm.mask.assign(solid_mask + sm.dbase, solid_mask + sm.dbase + sm.N);
+        for (auto& m : sm.mask) m = m ? 1 : 0;
+        GeomSpec gs{h->p.lattice, sm.nx, sm.ny, sm.nz, h->p.solute};
+        nrc += pinch_fill(gs, sm.mask);
+        std::vector<uint32_t> words;
+        link_words(gs, sm.mask, words, nullptr, nullptr);
+        sm.pos.clear();
+        for (long long n = 0; n < sm.N; ++n)
+            if (!sm.mask[n]) {
+                map[(size_t)(sm.dbase + n)] = (int)(kbase + (long long)sm.pos.size());
+                sm.pos.push_back((unsigned)n);
+            }
+        sm.nf = (long long)sm.pos.size();
+        if (sm.nf == 0) {
+            char buf[96];
+            snprintf(buf, sizeof buf, "sample %d has no fluid node left after reclassification", s);
+            return fail(h, MCLBM_EINVAL, buf);
         }
-    std::vector<uint32_t> fw((size_t)nf);
-    for (int64_t k = 0; k < nf; ++k) fw[k] = words[h->pos_host[k]];
-    HIPCHK(h, hipMemcpyAsync(h->map, map.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->pos, h->pos_host.data(), (size_t)nf * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->links, fw.data(), (size_t)nf * 4, hipMemcpyHostToDevice, h->stream));
+        sm.kbase = kbase;
+        const long long padded = pad64(sm.nf);
+        pos.resize((size_t)(kbase + padded), 0u);
+        links.resize((size_t)(kbase + padded), 0x80000000u);
+        for (long long k = 0; k < sm.nf; ++k) {
+            pos[(size_t)(kbase + k)] = sm.pos[k];
+            links[(size_t)(kbase + k)] = words[sm.pos[k]];
+        }
+        for (long long c = 0; c < padded / 64; ++c) chunk_sample.push_back(s);
+        sd[s] = SampleDev{sm.nx, sm.ny, sm.nz, (int)sm.nf, (int)sm.N, (int)sm.dbase, (int)sm.kbase, 0};
+        sm.frozen = false;
+        sm.conv_step = -1;
+        kbase += padded;
+    }
+    h->nchunks = kbase / 64;
+    if (n_reclassified) *n_reclassified = nrc;
+    HIPCHK(h, hipMemcpyAsync(h->map, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->links, links.data(), links.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->smp_dev, sd.data(), sd.size() * sizeof(SampleDev), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->chunk_sample, chunk_sample.data(), chunk_sample.size() * 4, hipMemcpyHostToDevice,
+                             h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    h->nfluid = nf;
+    int rc = upload_work(h);
+    if (rc != MCLBM_OK) return rc;
     h->geom_set = true;
-    h->fields_set = false;
     return MCLBM_OK;
 }
 
 int mclbm_get_geometry(mclbm_handle* h, uint8_t* mask_out, uint32_t* flow_links, uint32_t* solute_links) {
     if (!h) return MCLBM_EINVAL;
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
-    if (mask_out) memcpy(mask_out, h->mask.data(), (size_t)h->N);
-    if (flow_links || solute_links) {
-        std::vector<uint32_t> words, fb, sb;
-        GeomSpec gs{h->p.lattice, h->p.nx, h->p.ny, h->p.nz, h->p.solute};
-        link_words(gs, h->mask, words, &fb, &sb);
-        if (flow_links) memcpy(flow_links, fb.data(), (size_t)h->N * 4);
-        if (solute_links) memcpy(solute_links, sb.data(), (size_t)h->N * 4);
+    for (auto& sm : h->smp) {
+        if (mask_out) memcpy(mask_out + sm.dbase, sm.mask.data(), (size_t)sm.N);
+        if (flow_links || solute_links) {
+            std::vector<uint32_t> words, fb, sb;
+            GeomSpec gs{h->p.lattice, sm.nx, sm.ny, sm.nz, h->p.solute};
+            link_words(gs, sm.mask, words, &fb, &sb);
+            if (flow_links) memcpy(flow_links + sm.dbase, fb.data(), (size_t)sm.N * 4);
+            if (solute_links) memcpy(solute_links + sm.dbase, sb.data(), (size_t)sm.N * 4);
+        }
     }
     return MCLBM_OK;
 }
@@ -466,23 +705,37 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     if (!h) return MCLBM_EINVAL;
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
     if (!rho) return fail(h, MCLBM_EINVAL, "rho is NULL");
-    const long long N = h->N;
+    drop_graphs(h);
+    long long nf_tot = 0;
+    for (auto& sm : h->smp) nf_tot += sm.nf;
     for (int s = 0; s < h->NC; ++s) {
         double sum = 0.0;
-        for (long long n = 0; n < N; ++n) {
-            if (h->mask[n]) continue;
-            const double r = rho[s * N + n];
-            if (!(r > 0.0) || !isfinite(r)) return fail(h, MCLBM_EINVAL, "rho must be > 0 and finite on fluid nodes");
-            sum += r;
+        for (auto& sm : h->smp) {
+            const double* r = rho + (size_t)h->NC * sm.dbase + (size_t)s * sm.N;
+            for (long long n = 0; n < sm.N; ++n) {
+                if (sm.mask[n]) continue;
+                if (!(r[n] > 0.0) || !isfinite(r[n]))
+                    return fail(h, MCLBM_EINVAL, "rho must be > 0 and finite on fluid nodes");
+                sum += r[n];
+            }
         }
-        h->rhobar[s] = sum / (double)h->nfluid;
+        h->rhobar[s] = sum / (double)nf_tot;
     }
+    const long long N = h->Ntot;
     double* st_rho = h->stage;
     double* st_u = h->stage + (size_t)h->NC * N;
     double* st_C = h->stage + (size_t)(h->NC + 3) * N;
     HIPCHK(h, hipMemcpyAsync(st_rho, rho, (size_t)h->NC * N * 8, hipMemcpyHostToDevice, h->stream));
     if (u) HIPCHK(h, hipMemcpyAsync(st_u, u, (size_t)3 * N * 8, hipMemcpyHostToDevice, h->stream));
     if (C && h->p.solute) HIPCHK(h, hipMemcpyAsync(st_C, C, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
+    for (auto& sm : h->smp) {
+        sm.frozen = false;
+        sm.conv_step = -1;
+        for (int k = 0; k < 16; ++k) sm.mon[k] = 0.0;
+        sm.mon[0] = -1.0;
+    }
+    int rc = upload_work(h);
+    if (rc != MCLBM_OK) return rc;
     Ctx c = make_ctx(h);
     HIPCHK(h, k_init(c, st_rho, u ? st_u : nullptr, (C && h->p.solute) ? st_C : nullptr));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -500,39 +753,45 @@ int mclbm_step(mclbm_handle* h, int64_t n) {
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const int K = h->p.monitor_every;
     bool monitored = false, had = false;
-    for (int64_t s = 0; s < n; ++s) {
-        Ctx c = make_ctx(h);
-        HIPCHK(h, k_step(c));
-        std::swap(h->fA, h->fB);
-        std::swap(h->hA, h->hB);
-        ++h->step;
+    int64_t left = n;
+    while (left > 0) {
+        // a whole aligned interval through the graph when possible
+        if (h->use_graph && h->snap_valid && (K % 2 == 0) && h->step % K == 0 && left >= K) {
+            int rc = replay_interval(h);
+            if (rc != MCLBM_OK) return rc;
+            left -= K;
+            had = true;
+            monitored = true;
+            continue;
+        }
+        int rc = launch_step(h, h->stream);
+        if (rc != MCLBM_OK) return rc;
+        --left;
         if (h->step % K == 0) {
-            Ctx cm = make_ctx(h);
             had = h->snap_valid;
-            HIPCHK(h, k_monitor(cm, had ? 1 : 0));
+            HIPCHK(h, k_monitor(make_ctx(h), had ? 1 : 0));
             h->snap_valid = true;
             monitored = true;
         }
     }
-    if (monitored) {
-        HIPCHK(h, hipMemcpyAsync(h->host_result, h->result, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        if (collect_monitor(h, had)) return fail(h, MCLBM_EDIVERGED, "non-finite value at a monitor");
-    }
+    if (monitored) return collect_monitor(h, had);
     return MCLBM_OK;
 }
 
 int mclbm_monitor_now(mclbm_handle* h) {
     if (!h) return MCLBM_EINVAL;
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
-    return run_monitor(h);
+    const bool had = h->snap_valid;
+    HIPCHK(h, k_monitor(make_ctx(h), had ? 1 : 0));
+    h->snap_valid = true;
+    return collect_monitor(h, had);
 }
 
 int mclbm_get_moments(mclbm_handle* h, double* rho, double* u, double* C, int32_t dst_is_device) {
     if (!h) return MCLBM_EINVAL;
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     Ctx c = make_ctx(h);
-    const long long N = h->N;
+    const long long N = h->Ntot;
     if (dst_is_device) {
         HIPCHK(h, k_moments(c, rho, u, C));
         return MCLBM_OK;
@@ -555,59 +814,64 @@ int mclbm_get_monitors(mclbm_handle* h, double out[16]) {
     return MCLBM_OK;
 }
 
+int mclbm_get_sample_monitors(mclbm_handle* h, int32_t s, double out[16]) {
+    if (!h || !out) return MCLBM_EINVAL;
+    if (s < 0 || s >= h->S) return fail(h, MCLBM_EINVAL, "sample index out of range");
+    for (int k = 0; k < 16; ++k) out[k] = h->smp[s].mon[k];
+    out[10] = (double)h->step;
+    out[11] = (double)h->smp[s].conv_step;
+    out[12] = h->smp[s].frozen ? 1.0 : 0.0;
+    return MCLBM_OK;
+}
+
 int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes) {
     if (!h || !bytes) return MCLBM_EINVAL;
-    const size_t nval = (size_t)(h->NC * h->Q + (h->p.solute ? h->QS : 0)) * (size_t)h->N;
+    const size_t nval = (size_t)(h->NC * h->Q + (h->p.solute ? h->QS : 0)) * (size_t)h->Ntot;
     *bytes = nval * (raw ? store_bytes(h->p.storage) : 8);
     return MCLBM_OK;
 }
 
-// Position of (plane j, fluid node k) in a blocked fluid-only array with P planes.
+// Position of (plane j, fluid node k) in a chunked fluid-only array with P planes.
 static inline size_t blk_index(size_t P, size_t j, size_t k) { return ((k >> 6) * P + j) * 64 + (k & 63); }
 
 int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw) {
     if (!h || !dst) return MCLBM_EINVAL;
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const size_t sb = store_bytes(h->p.storage);
-    const size_t M = (size_t)pad64(h->nfluid);
+    const size_t M = (size_t)h->nchunks * 64;
     const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
     std::vector<unsigned char> dev((PF + PS) * M * sb);
     HIPCHK(h, hipMemcpyAsync(dev.data(), h->fA, PF * M * sb, hipMemcpyDeviceToHost, h->stream));
     if (PS) HIPCHK(h, hipMemcpyAsync(dev.data() + PF * M * sb, h->hA, PS * M * sb, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    const size_t N = (size_t)h->N;
     const Ctx c = make_ctx(h);
-    const size_t nplanes = PF + PS;
-    if (raw) {
-        unsigned char* out = (unsigned char*)dst;
-        memset(out, 0, nplanes * N * sb);
+    const size_t nplanes = PF + PS, ob = raw ? sb : 8;
+    memset(dst, 0, nplanes * (size_t)h->Ntot * ob);
+    for (auto& sm : h->smp) {
+        const size_t N = (size_t)sm.N;
+        unsigned char* out = (unsigned char*)dst + nplanes * (size_t)sm.dbase * ob;
         for (size_t j = 0; j < nplanes; ++j) {
             const bool flow = j < PF;
             const unsigned char* src = flow ? dev.data() : dev.data() + PF * M * sb;
             const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
-            for (size_t k = 0; k < (size_t)h->nfluid; ++k)
-                memcpy(out + (j * N + h->pos_host[k]) * sb, src + blk_index(P, jj, k) * sb, sb);
-        }
-        return MCLBM_OK;
-    }
-    double* out = (double*)dst;
-    memset(out, 0, nplanes * N * sizeof(double));
-    for (size_t j = 0; j < nplanes; ++j) {
-        const bool flow = j < PF;
-        const unsigned char* src = flow ? dev.data() : dev.data() + PF * M * sb;
-        const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
-        const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
-        const float shift = flow ? shift_f32(c, s, i) : 0.0f;
-        for (size_t k = 0; k < (size_t)h->nfluid; ++k) {
-            const size_t q = blk_index(P, jj, k);
-            double v;
-            switch (h->p.storage) {
-                case MCLBM_F64: v = ((const double*)src)[q]; break;
-                case MCLBM_F32: v = ((const float*)src)[q]; break;
-                case MCLBM_F16_SHIFT: v = (double)(half_to_float(((const uint16_t*)src)[q]) + shift); break;
-                default: v = (double)(bf16_to_float_h(((const uint16_t*)src)[q]) + shift); break;
+            const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
+            const float shift = flow ? shift_f32(c, s, i) : 0.0f;
+            for (size_t k = 0; k < (size_t)sm.nf; ++k) {
+                const size_t q = blk_index(P, jj, (size_t)sm.kbase + k);
+                const size_t o = j * N + sm.pos[k];
+                if (raw) {
+                    memcpy(out + o * sb, src + q * sb, sb);
+                    continue;
+                }
+                double v;
+                switch (h->p.storage) {
+                    case MCLBM_F64: v = ((const double*)src)[q]; break;
+                    case MCLBM_F32: v = ((const float*)src)[q]; break;
+                    case MCLBM_F16_SHIFT: v = (double)(half_to_float(((const uint16_t*)src)[q]) + shift); break;
+                    default: v = (double)(bf16_to_float_h(((const uint16_t*)src)[q]) + shift); break;
+                }
+                ((double*)out)[o] = v;
             }
-            out[j * N + h->pos_host[k]] = v;
         }
     }
     return MCLBM_OK;
@@ -617,29 +881,34 @@ int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw) {
     if (!h || !src) return MCLBM_EINVAL;
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const size_t sb = store_bytes(h->p.storage);
-    const size_t M = (size_t)pad64(h->nfluid);
+    const size_t M = (size_t)h->nchunks * 64;
     const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
-    const size_t N = (size_t)h->N, nplanes = PF + PS;
+    const size_t nplanes = PF + PS, ib = raw ? sb : 8;
     std::vector<unsigned char> dev((PF + PS) * M * sb, 0);
     const Ctx c = make_ctx(h);
-    for (size_t j = 0; j < nplanes; ++j) {
-        const bool flow = j < PF;
-        unsigned char* dstp = flow ? dev.data() : dev.data() + PF * M * sb;
-        const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
-        const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
-        const float shift = flow ? shift_f32(c, s, i) : 0.0f;
-        for (size_t k = 0; k < (size_t)h->nfluid; ++k) {
-            const size_t q = blk_index(P, jj, k), n = h->pos_host[k];
-            if (raw) {
-                memcpy(dstp + q * sb, (const unsigned char*)src + (j * N + n) * sb, sb);
-                continue;
-            }
-            const double v = ((const double*)src)[j * N + n];
-            switch (h->p.storage) {
-                case MCLBM_F64: ((double*)dstp)[q] = v; break;
-                case MCLBM_F32: ((float*)dstp)[q] = (float)v; break;
-                case MCLBM_F16_SHIFT: ((uint16_t*)dstp)[q] = float_to_half_rne((float)v - shift); break;
-                default: ((uint16_t*)dstp)[q] = float_to_bf16_rne_h((float)v - shift); break;
+    for (auto& sm : h->smp) {
+        const size_t N = (size_t)sm.N;
+        const unsigned char* in = (const unsigned char*)src + nplanes * (size_t)sm.dbase * ib;
+        for (size_t j = 0; j < nplanes; ++j) {
+            const bool flow = j < PF;
+            unsigned char* dstp = flow ? dev.data() : dev.data() + PF * M * sb;
+            const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
+            const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
+            const float shift = flow ? shift_f32(c, s, i) : 0.0f;
+            for (size_t k = 0; k < (size_t)sm.nf; ++k) {
+                const size_t q = blk_index(P, jj, (size_t)sm.kbase + k);
+                const size_t o = j * N + sm.pos[k];
+                if (raw) {
+                    memcpy(dstp + q * sb, in + o * sb, sb);
+                    continue;
+                }
+                const double v = ((const double*)in)[o];
+                switch (h->p.storage) {
+                    case MCLBM_F64: ((double*)dstp)[q] = v; break;
+                    case MCLBM_F32: ((float*)dstp)[q] = (float)v; break;
+                    case MCLBM_F16_SHIFT: ((uint16_t*)dstp)[q] = float_to_half_rne((float)v - shift); break;
+                    default: ((uint16_t*)dstp)[q] = float_to_bf16_rne_h((float)v - shift); break;
+                }
             }
         }
     }
@@ -666,20 +935,129 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
             if (steps_taken) *steps_taken = taken;
             return e;
         }
-        if (h->step % K == 0 && h->mon[0] == (double)h->step && h->mon[9] <= tol) {
+        if (h->step % K != 0) continue;
+        bool all = true, changed = false;
+        for (auto& sm : h->smp) {
+            if (sm.frozen) continue;
+            if (sm.mon[0] == (double)h->step && sm.mon[9] <= tol) {
+                sm.frozen = true;
+                sm.conv_step = h->step;
+                sm.mon[11] = (double)sm.conv_step;
+                sm.mon[12] = 1.0;
+                changed = true;
+                if (h->S > 1) {
+                    int m = mirror_sample(h, sm);
+                    if (m != MCLBM_OK) return m;
+                }
+            } else {
+                all = false;
+            }
+        }
+        if (all) {
             rc = MCLBM_OK;
             break;
+        }
+        if (changed) {
+            int u = upload_work(h);
+            if (u != MCLBM_OK) return u;
         }
     }
     if (steps_taken) *steps_taken = taken;
     return rc;
 }
 
-int mclbm_set_launch(mclbm_handle* h, int32_t block_threads) {
+int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks) {
     if (!h) return MCLBM_EINVAL;
     if (block_threads != 64 && block_threads != 128 && block_threads != 256)
         return fail(h, MCLBM_EINVAL, "block_threads must be 64, 128 or 256");
+    if (grid_blocks < 0 || (grid_blocks % 8) != 0)
+        return fail(h, MCLBM_EINVAL, "grid_blocks must be 0 or a positive multiple of 8");
+    drop_graphs(h);
     h->block = block_threads;
+    h->grid = grid_blocks;
+    return MCLBM_OK;
+}
+
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
+                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
+    if (trial_steps < 1) return fail(h, MCLBM_EINVAL, "trial_steps must be >= 1");
+    {
+        std::vector<double> rho((size_t)h->NC * h->Ntot, 1.0);
+        int rc = mclbm_init_fields(h, rho.data(), nullptr, nullptr);
+        if (rc != MCLBM_OK) return rc;
+    }
+    int dev = 0, cus = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<std::pair<int, int>> cand;
+    for (int b : {64, 128, 256}) {
+        cand.push_back({b, 0});
+        for (int w : {8, 16, 32}) {
+            const int g = (cus * w / (b / 64) + 7) / 8 * 8;
+            if (g > 0) cand.push_back({b, g});
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(h, MCLBM_EHIP, "hipEventCreate failed");
+    }
+    const int old_block = h->block, old_grid = h->grid;
+    double best = INFINITY;
+    int bb = old_block, bg = old_grid, rc = MCLBM_OK;
+    for (size_t i = 0; i < cand.size() && rc == MCLBM_OK; ++i) {
+        h->block = cand[i].first;
+        h->grid = cand[i].second;
+        for (int s = 0; s < 2 && rc == MCLBM_OK; ++s) rc = launch_step(h, h->stream);
+        if (rc != MCLBM_OK) break;
+        hipError_t e = hipEventRecord(e0, h->stream);
+        for (int s = 0; s < trial_steps && rc == MCLBM_OK && e == hipSuccess; ++s) rc = launch_step(h, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess && rc == MCLBM_OK) rc = hip_fail(h, e, "autotune timing");
+        if (rc != MCLBM_OK) break;
+        const double per = (double)ms / trial_steps;
+        if (table && (int)i < table_rows) {
+            table[3 * i + 0] = cand[i].first;
+            table[3 * i + 1] = cand[i].second;
+            table[3 * i + 2] = per;
+        }
+        if (per < best) {
+            best = per;
+            bb = cand[i].first;
+            bg = cand[i].second;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->fields_set = false;
+    h->step = 0;
+    h->snap_valid = false;
+    if (rc != MCLBM_OK) {
+        h->block = old_block;
+        h->grid = old_grid;
+        return rc;
+    }
+    h->block = bb;
+    h->grid = bg;
+    if (block_threads) *block_threads = bb;
+    if (grid_blocks) *grid_blocks = bg;
+    if (ms_per_step) *ms_per_step = best;
+    if (n_rows) *n_rows = (int32_t)cand.size();
+    return MCLBM_OK;
+}
+
+int mclbm_set_graph(mclbm_handle* h, int32_t enable) {
+    if (!h) return MCLBM_EINVAL;
+    if (enable && (h->p.monitor_every % 2) != 0)
+        return fail(h, MCLBM_EINVAL, "graph replay needs an even monitor_every");
+    drop_graphs(h);
+    h->use_graph = enable != 0;
     return MCLBM_OK;
 }
 
@@ -698,7 +1076,13 @@ int mclbm_synchronize(mclbm_handle* h) {
 void mclbm_destroy(mclbm_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    if (h->gstream) (void)hipStreamSynchronize(h->gstream);
+    drop_graphs(h);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
     if (h->host_result) (void)hipHostFree(h->host_result);
+    if (h->host_nwork) (void)hipHostFree(h->host_nwork);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     delete h;
 }

@@ -125,7 +125,6 @@ struct Store<ST_BF16S> {
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Phys {
-    int nx, ny, nz;
     int forcing;          // 0 Guo, 1 Shan-Chen velocity shift
     int solute;           // 0 off, 1 periodic, 2 inlet/outlet in x
     R inv_tau[2];         // 1 / tau_s

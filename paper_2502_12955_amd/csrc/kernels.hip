@@ -1,13 +1,23 @@
 // HIP kernels of the multi-component Shan-Chen LBM with reactive solute (gfx950).
 //
-// Storage is fluid-only.  Fluid nodes are numbered k = 0 .. Nf-1 in
-// increasing box index n = x + nx*(y + ny*z); pos[k] = n, map[n] = k (or -1
-// for solid nodes).  Populations are kept in blocks of 64 consecutive fluid
-// nodes (one wavefront): element (plane j, node k) lives at
+// A handle holds a batch of independent samples (a single lattice is a batch
+// of one).  Storage is fluid-only: the fluid nodes of sample s are numbered
+// k = kbase_s .. kbase_s + Nf_s - 1 in increasing box index (kbase_s is a
+// multiple of 64, so no 64-node chunk straddles two samples); pos[k] is the
+// box index within the sample and map[dbase_s + n] the fluid index (or -1 for
+// a solid node).  Populations are kept in chunks of 64 fluid nodes (one
+// wavefront): element (plane j, node k) lives at
 //   ((k >> 6) * P + j) * 64 + (k & 63),   P = planes of the array,
 // so a wavefront reads every plane of its 64 nodes as contiguous 256-byte
-// rows, and no bytes of solid nodes are ever moved.  The pseudo-potential
-// field psi[s][n] is kept dense over the box, zero on solid nodes.
+// rows, and no byte of a solid node is moved.  The pseudo-potential field is
+// dense over each sample's box, zero on solid nodes.
+//
+// Work distribution: each wavefront processes one chunk at a time, taken from
+// a device-side list of active chunks (samples that have converged are left
+// out) or from all chunks; the grid is either one pass over the chunks or a
+// fixed persistent grid that loops.  Logical blocks are remapped so that each
+// XCD (hardware dispatches block b to XCD b % 8) works on a contiguous range
+// of chunks, keeping neighbour gathers in one L2.
 //
 // One step = two kernels, one thread per fluid node:
 //   k_density:  rho_s = sum_i f^s_i (eq:1.7), psi_s = rho0 (1 - exp(-rho_s/rho0))
@@ -38,25 +48,39 @@
 
 namespace mclbm {
 
-// element (plane j, fluid node k) of a blocked array with P planes
+// element (plane j, fluid node k) of a chunked array with P planes
 template <typename T>
 __device__ __forceinline__ T* blk(T* base, int P, int j, unsigned k) {
     return base + ((size_t)(k >> 6) * (size_t)P + (size_t)j) * 64u + (k & 63u);
 }
 
-// XCD-aware block numbering: hardware dispatches block b to XCD b % 8; each
-// XCD gets a contiguous range of chunks so that neighbouring nodes share an L2.
-__device__ __forceinline__ int chunk_of_block(int per_xcd) {
-    const int b = blockIdx.x;
-    return (b & 7) * per_xcd + (b >> 3);
-}
-
 struct Geo {
-    int N, Nf, nblocks, per_xcd;
-    const unsigned* pos;     // [Nf] box index of fluid node k
-    const int* map;          // [N] fluid index of box node n, -1 if solid
-    const uint32_t* links;   // [Nf] link words
+    const SampleDev* smp;
+    const int* chunk_sample;
+    const unsigned* pos;
+    const int* map;
+    const uint32_t* links;
+    const int* work;   // nullptr: every chunk
+    const int* nwork;
+    int nchunks;
 };
+
+// Calls body(chunk) for every work item of this wavefront.
+template <class Body>
+__device__ __forceinline__ void for_each_chunk(const Geo& g, Body body) {
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int G = gridDim.x;  // multiple of 8
+    const int b = blockIdx.x;
+    const int lb0 = (b & 7) * (G >> 3) + (b >> 3);
+    const int nitems = g.work ? *g.nwork : g.nchunks;
+    for (int it = 0;; ++it) {
+        const int item = (it * G + lb0) * wpb + wave;
+        if (item >= nitems) break;
+        const int ch = g.work ? __builtin_amdgcn_readfirstlane(g.work[item]) : item;
+        body(ch);
+    }
+}
 
 __device__ __forceinline__ void coords(const unsigned n, int nx, int ny, int& x, int& y, int& z) {
     const unsigned nxy = (unsigned)nx * (unsigned)ny;
@@ -89,12 +113,6 @@ __device__ __forceinline__ NbIdx make_nb(int x, int y, int z, int nx, int ny, in
     return b;
 }
 
-#define FLUID_NODE_OR_RETURN()                                          \
-    const int c_ = chunk_of_block(g.per_xcd);                           \
-    if (c_ >= g.nblocks) return;                                        \
-    const unsigned k = (unsigned)c_ * blockDim.x + threadIdx.x;         \
-    if (k >= (unsigned)g.Nf) return;
-
 // ---------------------------------------------------------------------------
 // density / pseudo-potential
 // ---------------------------------------------------------------------------
@@ -105,17 +123,22 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    FLUID_NODE_OR_RETURN();
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
-    const unsigned n = g.pos[k];
+    for_each_chunk(g, [&](int ch) {
+        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+        const unsigned n = g.pos[k];
+        R* ps = psi + (size_t)NC * sd.dbase;
 #pragma unroll
-    for (int s = 0; s < NC; ++s) {
-        R r = 0;
+        for (int s = 0; s < NC; ++s) {
+            R r = 0;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
-        psi[(size_t)s * g.N + n] = P.rho0 * (R(1) - exp_r<R>(-r * P.inv_rho0));
-    }
+            for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
+            ps[(size_t)s * sd.N + n] = P.rho0 * (R(1) - exp_r<R>(-r * P.inv_rho0));
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -132,67 +155,72 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
     using S = Store<ST>;
     using R = typename S::R;
     constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
-    FLUID_NODE_OR_RETURN();
     R sh[NC][Q];
     load_shifts<LAT, ST, NC>(P, sh);
-    const unsigned n = g.pos[k];
-    const uint32_t lw = g.links[k];
-    int x, y, z;
-    coords(n, P.nx, P.ny, x, y, z);
-    const NbIdx nb = make_nb(x, y, z, P.nx, P.ny, P.nz);
+    for_each_chunk(g, [&](int ch) {
+        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+        const unsigned n = g.pos[k];
+        const uint32_t lw = g.links[k];
+        int x, y, z;
+        coords(n, sd.nx, sd.ny, x, y, z);
+        const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
+        const int* mp = g.map + sd.dbase;
+        const R* ps = psi + (size_t)NC * sd.dbase;
 
-    R f[NC][Q];
+        R f[NC][Q];
 #pragma unroll
-    for (int s = 0; s < NC; ++s)
+        for (int s = 0; s < NC; ++s)
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
-    R h[QS];
-    if (P.solute) {
+            for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
+        R h[QS];
+        if (P.solute) {
 #pragma unroll
-        for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
-    }
-
-    auto psi_nb = [&](int t, int i) -> R {
-        return psi[(size_t)t * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
-    };
-    R u[3];
-    flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
-
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
-        unsigned kd = k;
-        if (i != 0 && !bb) kd = (unsigned)g.map[nb.at(L::cx[i], L::cy[i], L::cz[i])];
-        const int dir = bb ? L::opp[i] : i;
-#pragma unroll
-        for (int s = 0; s < NC; ++s) S::store(blk(fB, PF, s * Q + dir, kd), f[s][i], sh[s][i]);  // w_i = w_opp(i)
-    }
-
-    if (P.solute) {
-        solute_collide<LAT, R>(P, h, u);
-        S::store_plain(blk(hB, QS, 0, k), h[0]);
-        const bool seam_mode = (P.solute == 2);
-#pragma unroll
-        for (int d = 1; d < QS; ++d) {
-            const int dx = L::cx[d];
-            const bool seam = seam_mode && ((x == P.nx - 1 && dx == 1) || (x == 0 && dx == -1));
-            if (!seam && !(lw & (1u << L::opp[d]))) {
-                const unsigned kd = (unsigned)g.map[nb.at(L::cx[d], L::cy[d], L::cz[d])];
-                S::store_plain(blk(hB, QS, d, kd), h[d]);
-                if (lw & (1u << (L::HOP_SHIFT + d))) {
-                    const R Cb = R(2) * h[d] * P.wet_inv_den;
-                    S::store_plain(blk(hB, QS, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
-                }
-                if (seam_mode && d == L::SXM && x == 1)
-                    S::store_plain(blk(hB, QS, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
-            }
-            if (seam_mode && d == L::SXM && x == P.nx - 1) S::store_plain(blk(hB, QS, d, k), h[d]);
+            for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
         }
-    }
+
+        auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)t * sd.N + nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
+        R u[3];
+        flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
+
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
+            unsigned kd = k;
+            if (i != 0 && !bb) kd = (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])];
+            const int dir = bb ? L::opp[i] : i;
+#pragma unroll
+            for (int s = 0; s < NC; ++s) S::store(blk(fB, PF, s * Q + dir, kd), f[s][i], sh[s][i]);  // w_i = w_opp(i)
+        }
+
+        if (P.solute) {
+            solute_collide<LAT, R>(P, h, u);
+            S::store_plain(blk(hB, QS, 0, k), h[0]);
+            const bool seam_mode = (P.solute == 2);
+#pragma unroll
+            for (int d = 1; d < QS; ++d) {
+                const int dx = L::cx[d];
+                const bool seam = seam_mode && ((x == sd.nx - 1 && dx == 1) || (x == 0 && dx == -1));
+                if (!seam && !(lw & (1u << L::opp[d]))) {
+                    const unsigned kd = (unsigned)mp[nb.at(L::cx[d], L::cy[d], L::cz[d])];
+                    S::store_plain(blk(hB, QS, d, kd), h[d]);
+                    if (lw & (1u << (L::HOP_SHIFT + d))) {
+                        const R Cb = R(2) * h[d] * P.wet_inv_den;
+                        S::store_plain(blk(hB, QS, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
+                    }
+                    if (seam_mode && d == L::SXM && x == 1)
+                        S::store_plain(blk(hB, QS, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
+                }
+                if (seam_mode && d == L::SXM && x == sd.nx - 1) S::store_plain(blk(hB, QS, d, k), h[d]);
+            }
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
 // initialisation at equilibrium (no force term) from dense staging fields
+// laid out per sample: rho [nc][N_s], u [3][N_s], C [N_s], samples concatenated
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
 __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, Geo g,
@@ -203,37 +231,43 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    FLUID_NODE_OR_RETURN();
-    const size_t N = g.N;
-    const unsigned n = g.pos[k];
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
-    R v[3] = {0, 0, 0};
-    if (u) {
-        v[0] = (R)u[n];
-        v[1] = (R)u[N + n];
-        v[2] = (R)u[2 * N + n];
-    }
-    const R vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-#pragma unroll
-    for (int s = 0; s < NC; ++s) {
-        const R r = (R)rho[s * N + n];
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const R cv = R(L::cx[i]) * v[0] + R(L::cy[i]) * v[1] + R(L::cz[i]) * v[2];
-            const R feq = wgt<LAT, R>(i) * r * (R(1) + R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
-            S::store(blk(fA, NC * L::Q, s * L::Q + i, k), feq, sh[s][i]);
+    for_each_chunk(g, [&](int ch) {
+        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+        const size_t N = sd.N;
+        const unsigned n = g.pos[k];
+        R v[3] = {0, 0, 0};
+        if (u) {
+            const double* us = u + (size_t)3 * sd.dbase;
+            v[0] = (R)us[n];
+            v[1] = (R)us[N + n];
+            v[2] = (R)us[2 * N + n];
         }
-    }
-    if (P.solute) {
-        const R c0 = C ? (R)C[n] : R(0);
+        const R vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double* rs = rho + (size_t)NC * sd.dbase;
 #pragma unroll
-        for (int q = 0; q < L::QS; ++q) {
-            const R W = (q == 0) ? P.Ws0 : P.Ws;
-            const R eu = R(L::cx[q]) * v[0] + R(L::cy[q]) * v[1] + R(L::cz[q]) * v[2];
-            S::store_plain(blk(hA, L::QS, q, k), W * c0 * (R(1) + eu * P.inv_cs2s));
+        for (int s = 0; s < NC; ++s) {
+            const R r = (R)rs[s * N + n];
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const R cv = R(L::cx[i]) * v[0] + R(L::cy[i]) * v[1] + R(L::cz[i]) * v[2];
+                const R feq = wgt<LAT, R>(i) * r * (R(1) + R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
+                S::store(blk(fA, NC * L::Q, s * L::Q + i, k), feq, sh[s][i]);
+            }
         }
-    }
+        if (P.solute) {
+            const R c0 = C ? (R)C[(size_t)sd.dbase + n] : R(0);
+#pragma unroll
+            for (int q = 0; q < L::QS; ++q) {
+                const R W = (q == 0) ? P.Ws0 : P.Ws;
+                const R eu = R(L::cx[q]) * v[0] + R(L::cy[q]) * v[1] + R(L::cz[q]) * v[2];
+                S::store_plain(blk(hA, L::QS, q, k), W * c0 * (R(1) + eu * P.inv_cs2s));
+            }
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -242,7 +276,8 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
 // it leaves in the local copy are discarded).
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
-__device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& P, const Geo& g, unsigned k,
+__device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& P, const Geo& g,
+                                             const SampleDev& sd, unsigned k,
                                              const typename Store<ST>::T* __restrict__ fA,
                                              const typename Store<ST>::T* __restrict__ hA,
                                              const typename Store<ST>::R* __restrict__ psi,
@@ -256,8 +291,9 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
     const unsigned n = g.pos[k];
     const uint32_t lw = g.links[k];
     int x, y, z;
-    coords(n, P.nx, P.ny, x, y, z);
-    const NbIdx nb = make_nb(x, y, z, P.nx, P.ny, P.nz);
+    coords(n, sd.nx, sd.ny, x, y, z);
+    const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
+    const R* ps = psi + (size_t)NC * sd.dbase;
     R f[NC][L::Q];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
@@ -269,9 +305,7 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
         }
         rho[s] = r;
     }
-    auto psi_nb = [&](int t, int i) -> R {
-        return psi[(size_t)t * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
-    };
+    auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)t * sd.N + nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
     flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
     C = 0;
     if (P.solute) {
@@ -299,20 +333,25 @@ __global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R>
                                                      double* __restrict__ rho_out, double* __restrict__ u_out,
                                                      double* __restrict__ C_out) {
     using R = typename Store<ST>::R;
-    FLUID_NODE_OR_RETURN();
-    R rho[NC], u[3], C;
-    node_moments<LAT, ST, NC>(P, g, k, fA, hA, psi, rho, u, C);
-    const size_t N = g.N;
-    const unsigned n = g.pos[k];
-    if (rho_out)
-        for (int s = 0; s < NC; ++s) rho_out[s * N + n] = (double)rho[s];
-    if (u_out)
-        for (int a = 0; a < 3; ++a) u_out[a * N + n] = (double)u[a];
-    if (C_out) C_out[n] = (double)C;
+    for_each_chunk(g, [&](int ch) {
+        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+        R rho[NC], u[3], C;
+        node_moments<LAT, ST, NC>(P, g, sd, k, fA, hA, psi, rho, u, C);
+        const size_t N = sd.N;
+        const unsigned n = g.pos[k];
+        if (rho_out)
+            for (int s = 0; s < NC; ++s) rho_out[(size_t)NC * sd.dbase + s * N + n] = (double)rho[s];
+        if (u_out)
+            for (int a = 0; a < 3; ++a) u_out[(size_t)3 * sd.dbase + a * N + n] = (double)u[a];
+        if (C_out) C_out[(size_t)sd.dbase + n] = (double)C;
+    });
 }
 
 // ---------------------------------------------------------------------------
-// monitors: FP64 block partials, fixed-order reduction
+// monitors: FP64 per-chunk partials (one wavefront each), then a fixed-order
+// reduction per sample.
 //   v[0] mass_0  v[1] mass_1  v[2] mass_C  v[3] |du|^2  v[4] |u|^2
 //   v[5] dphi^2  v[6] phi^2   v[7] dC^2    v[8] C^2     v[9] non-finite
 //   v[10] fluid nodes
@@ -328,82 +367,76 @@ __global__ void __launch_bounds__(256) k_monitor(Phys<typename Store<ST>::R> P, 
                                                  const typename Store<ST>::T* __restrict__ fA,
                                                  const typename Store<ST>::T* __restrict__ hA,
                                                  const typename Store<ST>::R* __restrict__ psi,
-                                                 typename Store<ST>::R* __restrict__ snap, int have_snapshot,
-                                                 double* __restrict__ partials) {
+                                                 typename Store<ST>::R* __restrict__ snap, size_t M,
+                                                 int have_snapshot, double* __restrict__ partials) {
     using R = typename Store<ST>::R;
-    __shared__ double red[MON_NV][4];
-    const int c = chunk_of_block(g.per_xcd);
-    if (c >= g.nblocks) return;  // whole block: uniform
-    const unsigned k = (unsigned)c * blockDim.x + threadIdx.x;
-    double v[MON_NV];
+    for_each_chunk(g, [&](int ch) {
+        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+        double v[MON_NV];
 #pragma unroll
-    for (int q = 0; q < MON_NV; ++q) v[q] = 0.0;
-    if (k < (unsigned)g.Nf) {
-        R rho[NC], u[3], C;
-        node_moments<LAT, ST, NC>(P, g, k, fA, hA, psi, rho, u, C);
-        R phi = 0;
-        if (NC == 2) {
-            const R tot = rho[0] + rho[NC - 1];
-            phi = (tot != R(0)) ? (rho[0] - rho[NC - 1]) / tot : R(0);
-        }
-        const size_t M = g.Nf;
-        v[0] = rho[0];
-        v[1] = (NC == 2) ? (double)rho[NC - 1] : 0.0;
-        v[2] = C;
-        double uu = 0, du = 0;
-        for (int a = 0; a < 3; ++a) {
-            const double ua = u[a];
-            uu += ua * ua;
-            if (have_snapshot) {
-                const double d = ua - (double)snap[a * M + k];
-                du += d * d;
+        for (int q = 0; q < MON_NV; ++q) v[q] = 0.0;
+        if ((int)(k - (unsigned)sd.kbase) < sd.Nf) {
+            R rho[NC], u[3], C;
+            node_moments<LAT, ST, NC>(P, g, sd, k, fA, hA, psi, rho, u, C);
+            R phi = 0;
+            if (NC == 2) {
+                const R tot = rho[0] + rho[NC - 1];
+                phi = (tot != R(0)) ? (rho[0] - rho[NC - 1]) / tot : R(0);
             }
-            snap[a * M + k] = u[a];
+            v[0] = rho[0];
+            v[1] = (NC == 2) ? (double)rho[NC - 1] : 0.0;
+            v[2] = C;
+            double uu = 0, du = 0;
+            for (int a = 0; a < 3; ++a) {
+                const double ua = u[a];
+                uu += ua * ua;
+                if (have_snapshot) {
+                    const double d = ua - (double)snap[a * M + k];
+                    du += d * d;
+                }
+                snap[a * M + k] = u[a];
+            }
+            v[3] = du;
+            v[4] = uu;
+            if (have_snapshot) {
+                const double dp = (double)phi - (double)snap[3 * M + k];
+                const double dc = (double)C - (double)snap[4 * M + k];
+                v[5] = dp * dp;
+                v[7] = dc * dc;
+            }
+            v[6] = (double)phi * (double)phi;
+            v[8] = (double)C * (double)C;
+            snap[3 * M + k] = phi;
+            snap[4 * M + k] = C;
+            const bool bad = !isfinite((double)rho[0]) || !isfinite((double)rho[NC - 1]) || !isfinite((double)C) ||
+                             !isfinite((double)u[0]) || !isfinite((double)u[1]) || !isfinite((double)u[2]);
+            v[9] = bad ? 1.0 : 0.0;
+            v[10] = 1.0;
         }
-        v[3] = du;
-        v[4] = uu;
-        if (have_snapshot) {
-            const double dp = (double)phi - (double)snap[3 * M + k];
-            const double dc = (double)C - (double)snap[4 * M + k];
-            v[5] = dp * dp;
-            v[7] = dc * dc;
-        }
-        v[6] = (double)phi * (double)phi;
-        v[8] = (double)C * (double)C;
-        snap[3 * M + k] = phi;
-        snap[4 * M + k] = C;
-        const bool bad = !isfinite((double)rho[0]) || !isfinite((double)rho[NC - 1]) || !isfinite((double)C) ||
-                         !isfinite((double)u[0]) || !isfinite((double)u[1]) || !isfinite((double)u[2]);
-        v[9] = bad ? 1.0 : 0.0;
-        v[10] = 1.0;
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < MON_NV; ++q) {
-        const double s = wave_sum(v[q]);
-        if (lane == 0) red[q][wid] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < MON_NV) {
-        const int nw = (blockDim.x + 63) >> 6;
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
-        partials[(size_t)c * MON_NV + threadIdx.x] = s;
-    }
+        for (int q = 0; q < MON_NV; ++q) {
+            const double s = wave_sum(v[q]);
+            if ((threadIdx.x & 63) == 0) partials[(size_t)ch * MON_NV + q] = s;
+        }
+    });
 }
 
-// one block of 256 threads: thread t sums rows b = t, t+256, ... in order,
-// then a fixed tree over the 256 threads
-__global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict__ partials, long long nblocks,
+// one block of 256 threads per sample: thread t sums the sample's chunks
+// t, t+256, ... in order, then a fixed tree over the 256 threads
+__global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict__ partials,
+                                                       const SampleDev* __restrict__ smp,
                                                        double* __restrict__ result) {
     __shared__ double acc[256][MON_NV + 1];
+    const SampleDev sd = smp[blockIdx.x];
+    const long long c0 = sd.kbase >> 6, nch = (sd.Nf + 63) >> 6;
     const int t = threadIdx.x;
     double s[MON_NV];
 #pragma unroll
     for (int q = 0; q < MON_NV; ++q) s[q] = 0.0;
-    for (long long b = t; b < nblocks; b += 256)
+    for (long long b = t; b < nch; b += 256)
 #pragma unroll
-        for (int q = 0; q < MON_NV; ++q) s[q] += partials[b * MON_NV + q];
+        for (int q = 0; q < MON_NV; ++q) s[q] += partials[(c0 + b) * MON_NV + q];
 #pragma unroll
     for (int q = 0; q < MON_NV; ++q) acc[t][q] = s[q];
     __syncthreads();
@@ -413,7 +446,7 @@ __global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict_
             for (int q = 0; q < MON_NV; ++q) acc[t][q] += acc[t + w][q];
         __syncthreads();
     }
-    if (t < MON_NV) result[t] = acc[0][t];
+    if (t < MON_NV) result[(size_t)blockIdx.x * 16 + t] = acc[0][t];
 }
 
 // ---------------------------------------------------------------------------
@@ -432,9 +465,6 @@ float shift_f32(const Ctx& c, int s, int i) {
 template <typename R>
 Phys<R> make_phys(const Ctx& c) {
     Phys<R> P;
-    P.nx = c.nx;
-    P.ny = c.ny;
-    P.nz = c.nz;
     P.forcing = c.forcing;
     P.solute = c.solute;
     for (int s = 0; s < 2; ++s) {
@@ -469,31 +499,37 @@ using SR = typename Store<ST>::R;
 template <int ST>
 using STT = typename Store<ST>::T;
 
-// launch shape over the fluid nodes: bs threads per block, grid 8 * per_xcd
-static inline Geo make_geo(const Ctx& c, int bs) {
+static inline Geo make_geo(const Ctx& c, bool use_work) {
     Geo g;
-    g.N = (int)c.N;
-    g.Nf = (int)c.Nf;
-    g.nblocks = (int)((c.Nf + bs - 1) / bs);
-    g.per_xcd = (g.nblocks + 7) / 8;
+    g.smp = c.smp;
+    g.chunk_sample = c.chunk_sample;
     g.pos = c.pos;
     g.map = c.map;
     g.links = c.links;
+    g.work = use_work ? c.work : nullptr;
+    g.nwork = c.nwork;
+    g.nchunks = (int)c.nchunks;
     return g;
 }
-static inline dim3 geo_grid(const Geo& g) { return dim3((unsigned)(8 * g.per_xcd > 0 ? 8 * g.per_xcd : 8)); }
 
-size_t monitor_blocks(const Ctx& c) { return (size_t)((c.Nf + 255) / 256); }
-size_t monitor_blocks_max(long long N) { return (size_t)((N + 255) / 256); }
+// grid: blocks of bs threads (bs/64 chunks per pass), multiple of 8 for the XCD remap
+static inline dim3 grid_for(const Ctx& c, int bs, bool persistent) {
+    const long long wpb = bs / 64;
+    long long nb = (c.nchunks + wpb - 1) / wpb;
+    if (persistent && c.grid > 0 && c.grid < nb) nb = c.grid;
+    nb = (nb + 7) & ~7LL;
+    return dim3((unsigned)(nb > 0 ? nb : 8));
+}
 
 template <int LAT, int ST, int NC>
 static hipError_t step_t(const Ctx& c) {
     auto P = make_phys<SR<ST>>(c);
     const int bs = c.block > 0 ? c.block : 256;
-    const Geo g = make_geo(c, bs);
-    hipLaunchKernelGGL((k_density<LAT, ST, NC>), geo_grid(g), dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+    const Geo g = make_geo(c, true);
+    const dim3 grid = grid_for(c, bs, true);
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_collide<LAT, ST, NC>), geo_grid(g), dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+    hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
     return hipGetLastError();
 }
@@ -501,43 +537,46 @@ static hipError_t step_t(const Ctx& c) {
 template <int LAT, int ST, int NC>
 static hipError_t init_t(const Ctx& c, const double* rho, const double* u, const double* C) {
     auto P = make_phys<SR<ST>>(c);
-    const Geo g = make_geo(c, 256);
+    const Geo g = make_geo(c, false);
     // the dense psi field must read 0 on solid nodes
-    const long long np = (long long)NC * c.N;
+    const long long np = (long long)NC * c.Ntot;
     hipLaunchKernelGGL((k_fill_r<SR<ST>>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, c.stream,
                        (SR<ST>*)c.psi, np);
-    hipLaunchKernelGGL((k_init_eq<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (STT<ST>*)c.fA,
-                       (STT<ST>*)c.hA, rho, u, C);
+    hipLaunchKernelGGL((k_init_eq<LAT, ST, NC>), grid_for(c, 256, false), dim3(256), 0, c.stream, P, g,
+                       (STT<ST>*)c.fA, (STT<ST>*)c.hA, rho, u, C);
     return hipGetLastError();
 }
 
 template <int LAT, int ST, int NC>
 static hipError_t moments_t(const Ctx& c, double* rho, double* u, double* C) {
     auto P = make_phys<SR<ST>>(c);
-    const Geo g = make_geo(c, 256);
+    const Geo g = make_geo(c, false);
+    const dim3 grid = grid_for(c, 256, false);
     auto fill = [&](double* p, long long n) {
         if (p) hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, p, n, 0.0);
     };
-    fill(rho, (long long)NC * c.N);
-    fill(u, 3LL * c.N);
-    fill(C, c.N);
-    hipLaunchKernelGGL((k_density<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+    fill(rho, (long long)NC * c.Ntot);
+    fill(u, 3LL * c.Ntot);
+    fill(C, c.Ntot);
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_moments_out<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g,
-                       (const STT<ST>*)c.fA, (const STT<ST>*)c.hA, (const SR<ST>*)c.psi, rho, u, C);
+    hipLaunchKernelGGL((k_moments_out<LAT, ST, NC>), grid, dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+                       (const STT<ST>*)c.hA, (const SR<ST>*)c.psi, rho, u, C);
     return hipGetLastError();
 }
 
 template <int LAT, int ST, int NC>
 static hipError_t monitor_t(const Ctx& c, int have_snapshot) {
     auto P = make_phys<SR<ST>>(c);
-    const Geo g = make_geo(c, 256);
-    hipLaunchKernelGGL((k_density<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+    const Geo g = make_geo(c, true);
+    const dim3 grid = grid_for(c, 256, true);
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_monitor<LAT, ST, NC>), geo_grid(g), dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
-                       (const STT<ST>*)c.hA, (const SR<ST>*)c.psi, (SR<ST>*)c.snap, have_snapshot, c.partials);
-    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(256), 0, c.stream, (const double*)c.partials,
-                       (long long)g.nblocks, c.result);
+    hipLaunchKernelGGL((k_monitor<LAT, ST, NC>), grid, dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+                       (const STT<ST>*)c.hA, (const SR<ST>*)c.psi, (SR<ST>*)c.snap, (size_t)c.nchunks * 64,
+                       have_snapshot, c.partials);
+    hipLaunchKernelGGL(k_monitor_final, dim3(c.nsamples), dim3(256), 0, c.stream, (const double*)c.partials, c.smp,
+                       c.result);
     return hipGetLastError();
 }
 

@@ -9,33 +9,44 @@
 
 namespace mclbm {
 
+// Geometry of one sample of a batch (a single lattice is a batch of one).
+struct SampleDev {
+    int nx, ny, nz;   // box dimensions
+    int Nf;           // fluid nodes
+    int N;            // box nodes
+    int dbase;        // first box node of the sample in the concatenated dense arrays
+    int kbase;        // first fluid index of the sample (multiple of 64)
+    int pad_;
+};
+
 struct Ctx {
     int lat, st, nc;            // lattice (0 D2Q9, 1 D3Q19), storage, components
-    int nx, ny, nz;
-    long long N;                // box nodes
-    long long Nf;               // fluid nodes
+    int nsamples;
+    long long Ntot;             // box nodes of all samples
+    long long nchunks;          // 64-node chunks of the fluid numbering (with per-sample padding)
     int forcing, solute;
     double tau[2], G[2][2], Gads[2], rho0, accel[3];
     double D, J0, k_wall, C_in;
     double rhobar[2];           // storage shift (used by *_SHIFT storage only)
     hipStream_t stream;
-    void *fA, *fB, *hA, *hB;    // populations (current state in A)
-    const unsigned* pos;        // [Nf] box index of fluid node k
-    const int* map;             // [N] fluid index of box node n, -1 if solid
-    const uint32_t* links;      // [Nf] link words
-    void* psi;                  // pseudo-potential field [nc][N] (arith type, 0 on solids)
-    void* snap;                 // residual snapshot [5][Nf] (arith type)
-    double* partials;           // monitor block partials
-    double* result;             // monitor result [16]
-    int block;                  // threads per block of the step kernels (64..256)
+    void *fA, *fB, *hA, *hB;    // populations (current state in A), blocks of 64 fluid nodes
+    const SampleDev* smp;       // [nsamples]
+    const int* chunk_sample;    // [nchunks] sample owning each 64-node chunk
+    const unsigned* pos;        // [nchunks*64] box index (within its sample) of fluid node k
+    const int* map;             // [Ntot] fluid index of box node, -1 if solid
+    const uint32_t* links;      // [nchunks*64] link words
+    void* psi;                  // pseudo-potential, per sample [nc][N_s] (arith type, 0 on solids)
+    void* snap;                 // residual snapshot [5][nchunks*64] (arith type)
+    const int* work;            // active chunk list (device) or nullptr = every chunk
+    const int* nwork;           // device count of `work`
+    double* partials;           // [nchunks][MON_NV] per-chunk monitor partials
+    double* result;             // [nsamples][16] per-sample monitor sums
+    int block;                  // threads per block of the step kernels (64, 128, 256)
+    int grid;                   // persistent grid (blocks, multiple of 8); 0 = one pass over the chunks
 };
 
 constexpr int MON_NV = 11;      // values reduced per monitor
 
-// Number of monitor blocks (partials rows) for this lattice, and its bound for N nodes.
-size_t monitor_blocks(const Ctx& c);
-size_t monitor_blocks_max(long long N);
-// Padded fluid count: populations are stored in blocks of 64 nodes.
 inline long long pad64(long long n) { return (n + 63) & ~63LL; }
 // Population-shift value of component s, direction i, exactly as the kernels use it.
 float shift_f32(const Ctx& c, int s, int i);

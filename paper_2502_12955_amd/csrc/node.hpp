@@ -1,6 +1,6 @@
-// Per-node device arithmetic shared by every flow kernel: neighbour indexing,
-// the flow collision with interaction forces, the solute collision and the
-// push streaming rules.  See kernels.hip for the equations.
+// Per-node device arithmetic shared by the flow kernels: the flow collision
+// with interaction forces, the solute collision and the storage shifts.  See
+// kernels.hip for the equations.
 #pragma once
 
 #include <math.h>
@@ -12,17 +12,6 @@ namespace mclbm {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-
-template <int LAT, typename R>
-__device__ __forceinline__ long long nb_index(const Phys<R>& P, int x, int y, int z, int i) {
-    using L = Lat<LAT>;
-    int xx = wrapc(x + L::cx[i], P.nx);
-    int yy = wrapc(y + L::cy[i], P.ny);
-    int zz = (LAT == 1) ? wrapc(z + L::cz[i], P.nz) : z;
-    return (long long)xx + (long long)P.nx * ((long long)yy + (long long)P.ny * zz);
-}
-
 template <typename R>
 __device__ __forceinline__ R exp_r(R v);
 template <>
@@ -32,9 +21,6 @@ __device__ __forceinline__ float exp_r<float>(float v) { return expf(v); }
 
 template <int LAT, typename R>
 __device__ __forceinline__ R wgt(int i) { return R(Lat<LAT>::wn[i]) / R(36); }
-
-template <typename T>
-__device__ __forceinline__ T* plane(T* base, long long N, int j) { return base + (long long)j * N; }
 
 // ---------------------------------------------------------------------------
 // per-node flow collision (shared by all flow kernels)
@@ -240,54 +226,6 @@ __device__ __forceinline__ void solute_collide(const Phys<R>& P, R (&h)[Lat<LAT>
         const R eu = R(L::cx[k]) * u[0] + R(L::cy[k]) * u[1] + R(L::cz[k]) * u[2];
         const R heq = W * C * (R(1) + eu * P.inv_cs2s);
         h[k] = h[k] + P.inv_tau_d * (heq - h[k]);
-    }
-}
-
-// push streaming of the flow populations of node n
-template <int LAT, int ST, int NC>
-__device__ __forceinline__ void flow_push(const Phys<typename Store<ST>::R>& P, uint32_t lw, int x, int y,
-                                          int z, long long n, long long N,
-                                          typename Store<ST>::T* __restrict__ fB,
-                                          const typename Store<ST>::R (&f)[NC][Lat<LAT>::Q],
-                                          const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q]) {
-    using L = Lat<LAT>;
-    using S = Store<ST>;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
-        const long long m = (i == 0 || bb) ? n : nb_index<LAT>(P, x, y, z, i);
-        const int dir = bb ? L::opp[i] : i;
-#pragma unroll
-        for (int s = 0; s < NC; ++s) S::store(plane(fB, N, s * L::Q + dir) + m, f[s][i], sh[s][i]);  // w_i = w_opp(i)
-    }
-}
-
-// push streaming of the solute populations of node n (see file header)
-template <int LAT, int ST>
-__device__ __forceinline__ void solute_push(const Phys<typename Store<ST>::R>& P, uint32_t lw, int x, int y,
-                                            int z, long long n, long long N,
-                                            typename Store<ST>::T* __restrict__ hB,
-                                            const typename Store<ST>::R (&h)[Lat<LAT>::QS]) {
-    using L = Lat<LAT>;
-    using S = Store<ST>;
-    using R = typename S::R;
-    S::store_plain(plane(hB, N, 0) + n, h[0]);
-    const bool seam_mode = (P.solute == 2);
-#pragma unroll
-    for (int d = 1; d < L::QS; ++d) {
-        const int dx = L::cx[d];
-        const bool seam = seam_mode && ((x == P.nx - 1 && dx == 1) || (x == 0 && dx == -1));
-        if (!seam && !(lw & (1u << L::opp[d]))) {
-            const long long m = nb_index<LAT>(P, x, y, z, d);
-            S::store_plain(plane(hB, N, d) + m, h[d]);
-            if (lw & (1u << (L::HOP_SHIFT + d))) {
-                const R Cb = R(2) * h[d] * P.wet_inv_den;
-                S::store_plain(plane(hB, N, L::opp[d]) + m, R(2) * P.Ws * Cb - h[d]);
-            }
-            if (seam_mode && d == L::SXM && x == 1)
-                S::store_plain(plane(hB, N, L::SXP) + m, R(2) * P.Ws * P.C_in - h[d]);
-        }
-        if (seam_mode && d == L::SXM && x == P.nx - 1) S::store_plain(plane(hB, N, d) + n, h[d]);
     }
 }
 

@@ -80,8 +80,9 @@ _lib = None
 EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "mclbm_get_geometry",
            "mclbm_init_fields", "mclbm_step", "mclbm_get_moments", "mclbm_get_monitors",
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
-           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_get_step",
-           "mclbm_synchronize", "mclbm_destroy", "mclbm_last_error")
+           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
+           "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
+           "mclbm_synchronize", "mclbm_autotune", "mclbm_destroy", "mclbm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -107,9 +108,15 @@ def load(path: str = LIB_PATH):
     lib.mclbm_set_populations.argtypes = [vp, vp, i32]
     lib.mclbm_population_bytes.argtypes = [vp, i32, ct.POINTER(sz)]
     lib.mclbm_run_to_residual.argtypes = [vp, dbl, i64, ct.POINTER(i64)]
-    lib.mclbm_set_launch.argtypes = [vp, i32]
+    lib.mclbm_set_launch.argtypes = [vp, i32, i32]
+    lib.mclbm_set_graph.argtypes = [vp, i32]
+    lib.mclbm_required_bytes_batch.argtypes = [P, i32, ct.POINTER(sz)]
+    lib.mclbm_init_batch.argtypes = [P, i32, vp, sz, vp, ct.POINTER(vp)]
+    lib.mclbm_get_sample_monitors.argtypes = [vp, i32, vp]
     lib.mclbm_get_step.argtypes = [vp, ct.POINTER(i64)]
     lib.mclbm_synchronize.argtypes = [vp]
+    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp, i32,
+                                   ct.POINTER(i32)]
     lib.mclbm_destroy.argtypes = [vp]
     lib.mclbm_destroy.restype = None
     lib.mclbm_last_error.argtypes = [vp]
@@ -228,8 +235,50 @@ def run_to_residual(h, tol: float, max_steps: int):
     return rc == OK, n.value
 
 
-def set_launch(h, block_threads=256):
-    _check(load().mclbm_set_launch(h, int(block_threads)), h)
+def set_launch(h, block_threads=256, grid_blocks=0):
+    _check(load().mclbm_set_launch(h, int(block_threads), int(grid_blocks)), h)
+
+
+def autotune(h, trial_steps=20):
+    """Native launch-shape tuner; returns (block, grid, ms_per_step, table rows)."""
+    b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    ms = ct.c_double()
+    table = np.zeros((64, 3))
+    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(b), ct.byref(g), ct.byref(ms), _ptr(table), 64,
+                                 ct.byref(n)), h)
+    return b.value, g.value, ms.value, table[: n.value].tolist()
+
+
+def tune_key(plist):
+    """Cache key of a launch-shape choice: physics class and box-node size class (powers of 2)."""
+    p = plist[0]
+    nodes = sum(int(q["nx"]) * int(q["ny"]) * int(q.get("nz", 1)) for q in plist)
+    return (f"{p.get('lattice', 'D3Q19')}-{p.get('storage', 'f64')}-nc{p.get('ncomp', 2)}-"
+            f"{p.get('solute', 'off')}-{p.get('forcing', 'guo')}-n2^{int(round(np.log2(max(nodes, 1))))}")
+
+
+def set_graph(h, enable=True):
+    _check(load().mclbm_set_graph(h, int(bool(enable))), h)
+
+
+def required_bytes_batch(plist) -> int:
+    arr = (Params * len(plist))(*[params_from_dict(p) for p in plist])
+    n = ct.c_size_t()
+    _check(load().mclbm_required_bytes_batch(arr, len(plist), ct.byref(n)))
+    return n.value
+
+
+def init_batch(plist, arena_ptr, arena_bytes, stream_ptr):
+    arr = (Params * len(plist))(*[params_from_dict(p) for p in plist])
+    h = ct.c_void_p()
+    _check(load().mclbm_init_batch(arr, len(plist), arena_ptr, arena_bytes, stream_ptr, ct.byref(h)))
+    return h
+
+
+def get_sample_monitors(h, s):
+    out = np.zeros(16)
+    _check(load().mclbm_get_sample_monitors(h, int(s), _ptr(out)), h)
+    return out
 
 
 def get_step(h) -> int:
@@ -312,8 +361,35 @@ class Lattice:
     def run_to_residual(self, tol, max_steps):
         return run_to_residual(self.h, tol, max_steps)
 
-    def set_launch(self, block_threads=256):
-        set_launch(self.h, block_threads)
+    def set_launch(self, block_threads=256, grid_blocks=0):
+        set_launch(self.h, block_threads, grid_blocks)
+
+    def set_graph(self, enable=True):
+        set_graph(self.h, enable)
+
+    def autotune(self, trial_steps=20, cache_path=None):
+        """Choose the launch shape (after set_geometry; init_fields must follow).
+
+        With ``cache_path`` (a JSON file), a shape already chosen for the same
+        physics and size class is reused without timing, and new choices are
+        added to the file.  Returns (block, grid, ms_per_step or None if cached)."""
+        import json
+
+        key = tune_key(getattr(self, "plist", [self.params]))
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if key in cache:
+            b, g = cache[key]["block"], cache[key]["grid"]
+            self.set_launch(b, g)
+            return b, g, None
+        b, g, ms, table = autotune(self.h, trial_steps)
+        if cache_path:
+            cache[key] = dict(block=b, grid=g, ms_per_step=ms, table=table)
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        return b, g, ms
 
     @property
     def step_count(self):
@@ -321,3 +397,58 @@ class Lattice:
 
     def synchronize(self):
         synchronize(self.h)
+
+
+class Batch(Lattice):
+    """A batch of independent samples sharing the physics (dimensions may differ).
+
+    Host arrays are per-sample arrays concatenated in sample order; the helpers
+    ``concat``/``split`` convert between lists of per-sample arrays and that layout.
+    """
+
+    def __init__(self, plist, device="cuda:0", stream=None):
+        import torch
+
+        load()
+        self.plist = [dict(p) for p in plist]
+        self.params = dict(plist[0])
+        self.sizes = [int(p["nx"]) * int(p["ny"]) * int(p.get("nz", 1)) for p in plist]
+        self.N = sum(self.sizes)
+        self.ncomp = int(plist[0].get("ncomp", 2))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = required_bytes_batch(self.plist)
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.arena.data_ptr() + 255) & ~255
+        self.h = init_batch(self.plist, ct.c_void_p(aligned), nbytes, ct.c_void_p(self.stream.cuda_stream))
+
+    def concat(self, per_sample, fields):
+        """List of arrays [fields][N_s] (any shape with N_s trailing values) -> flat batch array."""
+        return np.concatenate([np.asarray(a, np.float64).reshape(fields, n).ravel()
+                               for a, n in zip(per_sample, self.sizes)])
+
+    def split(self, flat, fields):
+        out, off = [], 0
+        for n in self.sizes:
+            out.append(np.asarray(flat[off:off + fields * n]).reshape(fields, n))
+            off += fields * n
+        return out
+
+    def set_geometry(self, masks):
+        flat = np.concatenate([np.asarray(m, np.uint8).reshape(-1) for m in masks])
+        return set_geometry(self.h, flat)
+
+    def init_fields(self, rhos, us=None, Cs=None):
+        init_fields(self.h, self.concat(rhos, self.ncomp),
+                    None if us is None else self.concat(us, 3),
+                    None if Cs is None else self.concat(Cs, 1))
+
+    def moments(self):
+        rho = np.zeros(self.ncomp * self.N)
+        u = np.zeros(3 * self.N)
+        C = np.zeros(self.N)
+        _check(load().mclbm_get_moments(self.h, _ptr(rho), _ptr(u), _ptr(C), 0), self.h)
+        return self.split(rho, self.ncomp), self.split(u, 3), self.split(C, 1)
+
+    def sample_monitors(self, s):
+        return get_sample_monitors(self.h, s)

@@ -1,0 +1,167 @@
+"""GPU: batches of independent samples, persistent grids, graph replay and run-to-residual.
+
+Every fluid node is updated by one thread with the same arithmetic whatever
+the batch composition, launch shape or replay mechanism, so all of these are
+required to be bit-identical to the plain single-lattice run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_12955_amd import inputs, mclbm
+
+from helpers import gpu_lattice, nrel, split_pops
+
+pytestmark = pytest.mark.gpu
+
+
+def _samples(n=4, seed=0, storage="f32", k_wall=0.02):
+    cases = []
+    shapes = [(12, 14, 18), (9, 20, 16), (16, 10, 12), (10, 10, 10), (14, 9, 21)]
+    for s in range(n):
+        shape = shapes[s % len(shapes)]
+        p, mask, rho, u, C = inputs.porous_case(shape=shape, porosity=0.5, radius=3, blob_radius=2,
+                                               config=3, sample=seed + s, storage=storage)
+        p.update(k_wall=k_wall, monitor_every=10)
+        rng = inputs.SplitMix64(inputs.seed_for(3, 100 + s))
+        C = 0.3 * rng.uniform(int(np.prod(shape))).reshape(shape)
+        cases.append((p, mask, rho, C))
+    return cases
+
+
+def _batch(cases, **launch):
+    b = mclbm.Batch([c[0] for c in cases])
+    if launch:
+        b.set_launch(**launch)
+    b.set_geometry([c[1] for c in cases])
+    b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
+    return b
+
+
+def _single_pops(case, steps):
+    p, mask, rho, C = case
+    lat = gpu_lattice(p, mask, rho, None, C)
+    lat.step(steps)
+    out = lat.populations(raw=True)
+    lat.close()
+    return out
+
+
+def test_batch_samples_bit_identical_to_single_runs():
+    cases = _samples(4)
+    b = _batch(cases)
+    b.step(25)
+    pops = b.populations(raw=True)
+    nplanes = 2 * 19 + 7
+    off = 0
+    for c, n in zip(cases, b.sizes):
+        mine = pops[off: off + nplanes * n]
+        off += nplanes * n
+        assert np.array_equal(mine, _single_pops(c, 25))
+    b.close()
+
+
+def test_persistent_grid_and_block_sizes_bit_identical():
+    cases = _samples(3, seed=7)
+    ref = _batch(cases)
+    ref.step(20)
+    want = ref.populations(raw=True)
+    ref.close()
+    for launch in (dict(block_threads=64, grid_blocks=8), dict(block_threads=128, grid_blocks=16),
+                   dict(block_threads=256, grid_blocks=0)):
+        b = _batch(cases, **launch)
+        b.step(20)
+        assert np.array_equal(b.populations(raw=True), want), launch
+        b.close()
+
+
+def test_graph_replay_matches_eager_steps():
+    """Replays interleaved with eager steps and host reads; each compared bitwise."""
+    cases = _samples(3, seed=11)
+    eager = _batch(cases)
+    graph = _batch(cases)
+    graph.set_graph(True)
+    for rep in range(4):
+        eager.step(10)
+        graph.step(10)          # first interval eager (no snapshot yet), then graph replays
+        a = eager.populations(raw=True)
+        g = graph.populations(raw=True)
+        assert np.array_equal(a, g), rep
+        assert np.array_equal(eager.monitors(), graph.monitors()), rep
+    # an odd number of eager steps flips the A/B parity: the other graph is used
+    eager.step(3)
+    graph.step(3)
+    eager.step(20)
+    graph.step(20)
+    assert np.array_equal(eager.populations(raw=True), graph.populations(raw=True))
+    eager.close()
+    graph.close()
+
+
+def test_run_to_residual_freezes_each_sample():
+    """Samples stop at their own convergence step; the batch result equals each
+    sample run alone to the same tolerance.  FP64 storage: at this flow speed
+    (|u| ~ 1e-4) FP32 round-off alone keeps the relative velocity change near
+    1e-5, so the tolerance would test the arithmetic rather than the freezing."""
+    cases = _samples(3, seed=21, k_wall=0.0, storage="f64")
+    for p, *_ in cases:
+        p.update(ncomp=1, G=((0, 0), (0, 0)), G_ads=(0, 0), solute="off", monitor_every=20,
+                 accel=(1e-5, 0.0, 0.0))
+    cases = [(p, m, r[:1] * 0 + 1.0, C) for p, m, r, C in cases]
+    tol = 1e-5
+    b = _batch(cases)
+    ok, steps = b.run_to_residual(tol, 20000)
+    assert ok
+    conv = [int(b.sample_monitors(s)[11]) for s in range(3)]
+    assert all(c > 0 for c in conv) and max(conv) == steps
+    pops = b.populations(raw=True)
+    nplanes = 19
+    off = 0
+    for s, (c, n) in enumerate(zip(cases, b.sizes)):
+        p, mask, rho, C = c
+        lat = gpu_lattice(p, mask, rho)
+        ok1, st1 = lat.run_to_residual(tol, 20000)
+        assert ok1 and st1 == conv[s]
+        assert np.array_equal(pops[off: off + nplanes * n], lat.populations(raw=True))
+        off += nplanes * n
+        lat.close()
+    b.close()
+
+
+def test_batch_fp64_matches_oracle_per_sample():
+    cases = _samples(2, seed=31, storage="f64")
+    b = _batch(cases)
+    b.step(15)
+    rhos, us, Cs = b.moments()
+    for s, (p, mask, rho, C) in enumerate(cases):
+        m, _ = oracle.pinch_fill(p, mask)
+        f, h = oracle.init(p, m, rho, None, C)
+        oracle.step(p, m, f, h, 15)
+        ro, uo, Co = oracle.moments(p, m, f, h)
+        assert nrel(rhos[s], ro) < 1e-12
+        assert nrel(us[s], uo) < 1e-12
+        assert nrel(Cs[s][0], Co) < 1e-12
+    b.close()
+
+
+def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
+    cases = _samples(3, seed=41)
+    b = mclbm.Batch([c[0] for c in cases])
+    b.set_geometry([c[1] for c in cases])
+    cache = str(tmp_path / "tune.json")
+    blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
+    assert blk in (64, 128, 256) and grid % 8 == 0 and ms > 0
+    with pytest.raises(mclbm.MclbmError) as e:      # populations were overwritten
+        b.step(1)
+    assert e.value.code == mclbm.ESTATE
+    b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
+    b.step(12)
+    ref = _batch(cases)
+    ref.step(12)
+    assert np.array_equal(b.populations(raw=True), ref.populations(raw=True))
+    # a second handle of the same class takes the cached shape without timing
+    b2 = mclbm.Batch([c[0] for c in cases])
+    b2.set_geometry([c[1] for c in cases])
+    assert b2.autotune(trial_steps=4, cache_path=cache) == (blk, grid, None)
+    for x in (b, b2, ref):
+        x.close()
