@@ -1,0 +1,534 @@
+// Warm-start network layers on gfx950 (declarations and contract in include/warmnet.h).
+//
+// 3-D convolutions are implicit GEMMs on the BF16 matrix cores:
+//   forward  Y[v][o]  = sum_{k,i} X[v + off_k][i] W[o][k][i]      M = voxels, N = c_out, K = 27 c_in
+//   dgrad    dX[v][i] = sum_{k,o} dY[v - off_k][o] W[o][k][i]     M = voxels, N = c_in,  K = 27 c_out
+//   wgrad    dW[o][k][i] = sum_v dY[v][o] X[v + off_k][i]         M = c_out,  N = c_in,  K = voxels
+// with v_mfma_f32_16x16x16_bf16: per wavefront a 16x16 FP32 tile, operands of
+// 16x16 BF16 values.  Lane l (q = l / 16, r = l % 16) supplies A[r][4q..4q+3]
+// and B[4q..4q+3][r] and receives D[4q + j][r], j = 0..3.  Operands are FP32
+// tensors rounded to BF16 (nearest even) on load; accumulation stays FP32.
+// The weight gradient splits the voxel sum into fixed chunks whose partial
+// tiles are summed in chunk order by a second kernel (deterministic).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "warmnet.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+struct Grid3 {
+    int n, d, h, w;
+    __device__ __forceinline__ int shift(int v, int dz, int dy, int dx) const {
+        int x = v % w;
+        int t = v / w;
+        int y = t % h;
+        t /= h;
+        int z = t % d;
+        int b = t / d;
+        x += dx;
+        x = x < 0 ? x + w : (x >= w ? x - w : x);
+        y += dy;
+        y = y < 0 ? y + h : (y >= h ? y - h : y);
+        z += dz;
+        z = z < 0 ? z + d : (z >= d ? z - d : z);
+        return ((b * d + z) * h + y) * w + x;
+    }
+};
+
+__device__ __forceinline__ void koff(int kk, int k, int& dz, int& dy, int& dx) {
+    const int r = k / 2;
+    dx = kk % k - r;
+    dy = (kk / k) % k - r;
+    dz = kk / (k * k) - r;
+}
+
+// ---------------------------------------------------------------------------
+// forward: one wavefront per (16 voxels, 16 output channels) tile
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) conv_fwd(const float* __restrict__ X, Grid3 g, int V, int ci,
+                                                const float* __restrict__ W, const float* __restrict__ bias, int co,
+                                                int k, int relu, float* __restrict__ Y) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int nco = (co + 15) >> 4;
+    const int vt = tile / nco, ot = tile % nco;
+    if (vt * 16 >= V) return;
+    const int v0 = vt * 16, o0 = ot * 16;
+    const int K3 = k * k * k;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int va = v0 + r;   // voxel of this lane's A row
+    const int ob = o0 + r;   // output channel of this lane's B column
+    for (int kk = 0; kk < K3; ++kk) {
+        int dz, dy, dx;
+        koff(kk, k, dz, dy, dx);
+        const int vs = g.shift(va, dz, dy, dx);
+        for (int c0 = 0; c0 < ci; c0 += 16) {
+            bf16x4 a, b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = c0 + 4 * q + j;
+                a[j] = to_bf16(c < ci ? X[(size_t)vs * ci + c] : 0.f);
+                b[j] = to_bf16((c < ci && ob < co) ? W[((size_t)ob * K3 + kk) * ci + c] : 0.f);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    }
+    if (ob < co) {
+        const float bb = bias ? bias[ob] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + 4 * q + j;
+            float y = acc[j] + bb;
+            if (relu) y = y > 0.f ? y : 0.f;
+            Y[(size_t)v * co + ob] = y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// data gradient: one wavefront per (16 voxels, 16 input channels) tile
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) conv_dgrad(const float* __restrict__ dY, Grid3 g, int V, int co,
+                                                  const float* __restrict__ W, int ci, int k,
+                                                  float* __restrict__ dX) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int nci = (ci + 15) >> 4;
+    const int vt = tile / nci, it = tile % nci;
+    if (vt * 16 >= V) return;
+    const int v0 = vt * 16, i0 = it * 16;
+    const int K3 = k * k * k;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int va = v0 + r;
+    const int ib = i0 + r;
+    for (int kk = 0; kk < K3; ++kk) {
+        int dz, dy, dx;
+        koff(kk, k, dz, dy, dx);
+        const int vs = g.shift(va, -dz, -dy, -dx);
+        for (int c0 = 0; c0 < co; c0 += 16) {
+            bf16x4 a, b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = c0 + 4 * q + j;
+                a[j] = to_bf16(o < co ? dY[(size_t)vs * co + o] : 0.f);
+                b[j] = to_bf16((o < co && ib < ci) ? W[((size_t)o * K3 + kk) * ci + ib] : 0.f);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    }
+    if (ib < ci) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dX[(size_t)(v0 + 4 * q + j) * ci + ib] = acc[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: one wavefront per (16 out ch, 16 in ch, offset, voxel chunk)
+// tile; partial[chunk][o][kk][i]
+// ---------------------------------------------------------------------------
+constexpr int WG_CHUNK = 4096;
+
+__global__ void __launch_bounds__(256) conv_wgrad_part(const float* __restrict__ X, const float* __restrict__ dY,
+                                                       Grid3 g, int V, int ci, int co, int k,
+                                                       float* __restrict__ part) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const int K3 = k * k * k;
+    const int nco = (co + 15) >> 4, nci = (ci + 15) >> 4;
+    const int nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
+    const long long tile = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const long long ntile = (long long)nco * nci * K3 * nchunk;
+    if (tile >= ntile) return;
+    long long t = tile;
+    const int ot = (int)(t % nco);
+    t /= nco;
+    const int it = (int)(t % nci);
+    t /= nci;
+    const int kk = (int)(t % K3);
+    const int ch = (int)(t / K3);
+    int dz, dy, dx;
+    koff(kk, k, dz, dy, dx);
+    const int o0 = ot * 16, i0 = it * 16;
+    const int vend = min(V, (ch + 1) * WG_CHUNK);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int oa = o0 + r, ib = i0 + r;
+    for (int v0 = ch * WG_CHUNK; v0 < vend; v0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + 4 * q + j;
+            a[j] = to_bf16(oa < co ? dY[(size_t)v * co + oa] : 0.f);
+            const int vs = g.shift(v, dz, dy, dx);
+            b[j] = to_bf16(ib < ci ? X[(size_t)vs * ci + ib] : 0.f);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    if (ib < ci) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = o0 + 4 * q + j;
+            if (o < co) part[(((size_t)ch * co + o) * K3 + kk) * ci + ib] = acc[j];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) sum_chunks(const float* __restrict__ part, int nchunk, long long n,
+                                                  float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
+    out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// small layers
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) bias_grad_k(const float* __restrict__ dy, long long V, int co,
+                                                   float* __restrict__ db) {
+    __shared__ float red[256];
+    const int o = blockIdx.x;
+    float s = 0.f;
+    for (long long v = threadIdx.x; v < V; v += 256) s += dy[(size_t)v * co + o];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] = red[0];
+}
+
+__global__ void __launch_bounds__(256) relu_bwd_k(const float* __restrict__ y, float* __restrict__ g, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(y[i] > 0.f)) g[i] = 0.f;
+}
+
+__global__ void __launch_bounds__(256) add_k(const float* __restrict__ x, float* __restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
+
+__global__ void __launch_bounds__(256) pool2_fwd_k(const float* __restrict__ x, int n, int d, int h, int w, int c,
+                                                   float* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int d2 = d / 2, h2 = h / 2, w2 = w / 2;
+    const long long tot = (long long)n * d2 * h2 * w2 * c;
+    if (i >= tot) return;
+    long long t = i;
+    const int ch = (int)(t % c);
+    t /= c;
+    const int xx = (int)(t % w2);
+    t /= w2;
+    const int yy = (int)(t % h2);
+    t /= h2;
+    const int zz = (int)(t % d2);
+    const int b = (int)(t / d2);
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb)
+            for (int cc = 0; cc < 2; ++cc)
+                s += x[((((size_t)b * d + 2 * zz + a) * h + 2 * yy + bb) * w + 2 * xx + cc) * c + ch];
+    y[i] = s * 0.125f;
+}
+
+__global__ void __launch_bounds__(256) pool2_bwd_k(const float* __restrict__ dy, int n, int d, int h, int w, int c,
+                                                   float* __restrict__ dx) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * d * h * w * c;
+    if (i >= tot) return;
+    long long t = i;
+    const int ch = (int)(t % c);
+    t /= c;
+    const int xx = (int)(t % w);
+    t /= w;
+    const int yy = (int)(t % h);
+    t /= h;
+    const int zz = (int)(t % d);
+    const int b = (int)(t / d);
+    dx[i] = 0.125f * dy[((((size_t)b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2) * c + ch];
+}
+
+__global__ void __launch_bounds__(256) up2_fwd_k(const float* __restrict__ x, int n, int d, int h, int w, int c,
+                                                 float* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int D = 2 * d, Hh = 2 * h, Ww = 2 * w;
+    const long long tot = (long long)n * D * Hh * Ww * c;
+    if (i >= tot) return;
+    long long t = i;
+    const int ch = (int)(t % c);
+    t /= c;
+    const int xx = (int)(t % Ww);
+    t /= Ww;
+    const int yy = (int)(t % Hh);
+    t /= Hh;
+    const int zz = (int)(t % D);
+    const int b = (int)(t / D);
+    y[i] = x[((((size_t)b * d + zz / 2) * h + yy / 2) * w + xx / 2) * c + ch];
+}
+
+__global__ void __launch_bounds__(256) up2_bwd_k(const float* __restrict__ dy, int n, int d, int h, int w, int c,
+                                                 float* __restrict__ dx) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * d * h * w * c;
+    if (i >= tot) return;
+    long long t = i;
+    const int ch = (int)(t % c);
+    t /= c;
+    const int xx = (int)(t % w);
+    t /= w;
+    const int yy = (int)(t % h);
+    t /= h;
+    const int zz = (int)(t % d);
+    const int b = (int)(t / d);
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb)
+            for (int cc = 0; cc < 2; ++cc)
+                s += dy[((((size_t)b * 2 * d + 2 * zz + a) * 2 * h + 2 * yy + bb) * 2 * w + 2 * xx + cc) * c + ch];
+    dx[i] = s;
+}
+
+__global__ void __launch_bounds__(256) concat_k(const float* __restrict__ a, int ca, const float* __restrict__ b,
+                                                int cb, long long V, float* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = ca + cb;
+    if (i >= V * c) return;
+    const long long v = i / c;
+    const int ch = (int)(i % c);
+    y[i] = ch < ca ? a[v * ca + ch] : b[v * cb + ch - ca];
+}
+
+__global__ void __launch_bounds__(256) split_k(const float* __restrict__ y, long long V, int ca, int cb,
+                                               float* __restrict__ a, float* __restrict__ b) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = ca + cb;
+    if (i >= V * c) return;
+    const long long v = i / c;
+    const int ch = (int)(i % c);
+    if (ch < ca) {
+        if (a) a[v * ca + ch] = y[i];
+    } else if (b) {
+        b[v * cb + ch - ca] = y[i];
+    }
+}
+
+// loss: per-block partial sums then one block in fixed order
+__global__ void __launch_bounds__(256) mse_k(const float* __restrict__ y, const float* __restrict__ t,
+                                             const float* __restrict__ wt, int c, long long n,
+                                             float* __restrict__ grad, float* __restrict__ part) {
+    __shared__ float red[256];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    float s = 0.f;
+    if (i < n) {
+        const float wi = wt ? wt[i % c] : 1.f;
+        const float e = y[i] - t[i];
+        s = wi * e * e;
+        grad[i] = 2.f * wi * e / (float)n;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) mse_final_k(const float* __restrict__ part, int nb, long long n,
+                                                   float* __restrict__ loss) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (float)n;
+}
+
+__global__ void __launch_bounds__(256) adam_k(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, long long n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+int err(int code, const char* msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_result(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_err = std::string(what) + ": " + hipGetErrorString(e);
+        return -3;
+    }
+    return 0;
+}
+
+dim3 blocks_for(long long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+bool shape_ok(int n, int d, int h, int w, int c) {
+    if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1) return false;
+    const long long V = (long long)n * d * h * w;
+    return V % 16 == 0 && V * c < (1LL << 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+int wn_conv3d_fwd(const float* x, int n, int d, int h, int w, int ci, const float* W, const float* b, int co, int k,
+                  int relu, float* y, void* stream) {
+    if (!x || !W || !y || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || co < 1)
+        return err(-1, "wn_conv3d_fwd: bad arguments");
+    const int V = n * d * h * w;
+    const long long tiles = (long long)(V / 16) * ((co + 15) / 16);
+    hipLaunchKernelGGL(conv_fwd, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, (hipStream_t)stream, x,
+                       Grid3{n, d, h, w}, V, ci, W, b, co, k, relu, y);
+    return hip_result("conv_fwd");
+}
+
+int wn_conv3d_dgrad(const float* dy, int n, int d, int h, int w, int co, const float* W, int ci, int k, float* dx,
+                    void* stream) {
+    if (!dy || !W || !dx || (k != 1 && k != 3) || !shape_ok(n, d, h, w, co) || ci < 1)
+        return err(-1, "wn_conv3d_dgrad: bad arguments");
+    const int V = n * d * h * w;
+    const long long tiles = (long long)(V / 16) * ((ci + 15) / 16);
+    hipLaunchKernelGGL(conv_dgrad, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, (hipStream_t)stream, dy,
+                       Grid3{n, d, h, w}, V, co, W, ci, k, dx);
+    return hip_result("conv_dgrad");
+}
+
+size_t wn_wgrad_workspace_bytes(int n, int d, int h, int w, int ci, int co, int k) {
+    const long long V = (long long)n * d * h * w;
+    const long long nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
+    return (size_t)nchunk * co * k * k * k * ci * sizeof(float);
+}
+
+int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w, int ci, int co, int k, float* dW,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+    if (!x || !dy || !dW || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || co < 1)
+        return err(-1, "wn_conv3d_wgrad: bad arguments");
+    if (!workspace || workspace_bytes < wn_wgrad_workspace_bytes(n, d, h, w, ci, co, k))
+        return err(-1, "wn_conv3d_wgrad: workspace too small");
+    const int V = n * d * h * w;
+    const int K3 = k * k * k;
+    const int nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
+    const long long tiles = (long long)((co + 15) / 16) * ((ci + 15) / 16) * K3 * nchunk;
+    hipLaunchKernelGGL(conv_wgrad_part, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, (hipStream_t)stream, x, dy,
+                       Grid3{n, d, h, w}, V, ci, co, k, (float*)workspace);
+    const long long nw = (long long)co * K3 * ci;
+    hipLaunchKernelGGL(sum_chunks, blocks_for(nw), dim3(256), 0, (hipStream_t)stream, (const float*)workspace,
+                       nchunk, nw, dW);
+    return hip_result("conv_wgrad");
+}
+
+int wn_bias_grad(const float* dy, long long V, int co, float* db, void* stream) {
+    if (!dy || !db || V < 1 || co < 1) return err(-1, "wn_bias_grad: bad arguments");
+    hipLaunchKernelGGL(bias_grad_k, dim3(co), dim3(256), 0, (hipStream_t)stream, dy, V, co, db);
+    return hip_result("bias_grad");
+}
+
+int wn_relu_bwd(const float* y, float* g, long long count, void* stream) {
+    if (!y || !g || count < 0) return err(-1, "wn_relu_bwd: bad arguments");
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(relu_bwd_k, blocks_for(count), dim3(256), 0, (hipStream_t)stream, y, g, count);
+    return hip_result("relu_bwd");
+}
+
+int wn_add(const float* x, float* y, long long count, void* stream) {
+    if (!x || !y || count < 0) return err(-1, "wn_add: bad arguments");
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(add_k, blocks_for(count), dim3(256), 0, (hipStream_t)stream, x, y, count);
+    return hip_result("add");
+}
+
+int wn_pool2_fwd(const float* x, int n, int d, int h, int w, int c, float* y, void* stream) {
+    if (!x || !y || n < 1 || c < 1 || d < 2 || h < 2 || w < 2 || (d | h | w) & 1) return err(-1, "wn_pool2_fwd: bad arguments");
+    hipLaunchKernelGGL(pool2_fwd_k, blocks_for((long long)n * (d / 2) * (h / 2) * (w / 2) * c), dim3(256), 0,
+                       (hipStream_t)stream, x, n, d, h, w, c, y);
+    return hip_result("pool2_fwd");
+}
+
+int wn_pool2_bwd(const float* dy, int n, int d, int h, int w, int c, float* dx, void* stream) {
+    if (!dy || !dx || n < 1 || c < 1 || d < 2 || h < 2 || w < 2 || (d | h | w) & 1) return err(-1, "wn_pool2_bwd: bad arguments");
+    hipLaunchKernelGGL(pool2_bwd_k, blocks_for((long long)n * d * h * w * c), dim3(256), 0, (hipStream_t)stream, dy,
+                       n, d, h, w, c, dx);
+    return hip_result("pool2_bwd");
+}
+
+int wn_up2_fwd(const float* x, int n, int d, int h, int w, int c, float* y, void* stream) {
+    if (!x || !y || n < 1 || c < 1 || d < 1 || h < 1 || w < 1) return err(-1, "wn_up2_fwd: bad arguments");
+    hipLaunchKernelGGL(up2_fwd_k, blocks_for((long long)n * 8 * d * h * w * c), dim3(256), 0, (hipStream_t)stream, x,
+                       n, d, h, w, c, y);
+    return hip_result("up2_fwd");
+}
+
+int wn_up2_bwd(const float* dy, int n, int d, int h, int w, int c, float* dx, void* stream) {
+    if (!dy || !dx || n < 1 || c < 1 || d < 1 || h < 1 || w < 1) return err(-1, "wn_up2_bwd: bad arguments");
+    hipLaunchKernelGGL(up2_bwd_k, blocks_for((long long)n * d * h * w * c), dim3(256), 0, (hipStream_t)stream, dy, n,
+                       d, h, w, c, dx);
+    return hip_result("up2_bwd");
+}
+
+int wn_concat(const float* a, int ca, const float* b, int cb, long long V, float* y, void* stream) {
+    if (!a || !b || !y || ca < 1 || cb < 1 || V < 1) return err(-1, "wn_concat: bad arguments");
+    hipLaunchKernelGGL(concat_k, blocks_for(V * (ca + cb)), dim3(256), 0, (hipStream_t)stream, a, ca, b, cb, V, y);
+    return hip_result("concat");
+}
+
+int wn_split(const float* y, long long V, int ca, int cb, float* a, float* b, void* stream) {
+    if (!y || ca < 1 || cb < 1 || V < 1) return err(-1, "wn_split: bad arguments");
+    hipLaunchKernelGGL(split_k, blocks_for(V * (ca + cb)), dim3(256), 0, (hipStream_t)stream, y, V, ca, cb, a, b);
+    return hip_result("split");
+}
+
+int wn_mse(const float* y, const float* t, const float* wt, int c, long long count, float* loss, float* grad,
+           float* workspace, void* stream) {
+    if (!y || !t || !loss || !grad || !workspace || count < 1 || c < 1) return err(-1, "wn_mse: bad arguments");
+    const long long nb = (count + 255) / 256;
+    hipLaunchKernelGGL(mse_k, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, y, t, wt, c, count, grad,
+                       workspace);
+    hipLaunchKernelGGL(mse_final_k, dim3(1), dim3(256), 0, (hipStream_t)stream, (const float*)workspace, (int)nb,
+                       count, loss);
+    return hip_result("mse");
+}
+
+int wn_adam(float* p, const float* g, float* m, float* v, long long count, float lr, float beta1, float beta2,
+            float eps, int step, void* stream) {
+    if (!p || !g || !m || !v || count < 1 || step < 1) return err(-1, "wn_adam: bad arguments");
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(adam_k, blocks_for(count), dim3(256), 0, (hipStream_t)stream, p, g, m, v, count, lr, beta1,
+                       beta2, eps, c1, c2);
+    return hip_result("adam");
+}
+
+const char* wn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

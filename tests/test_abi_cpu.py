@@ -49,3 +49,18 @@ def test_arena_too_small_is_rejected_before_any_device_call():
     h = ct.c_void_p()
     rc = mclbm.load().mclbm_init_lattice(ct.byref(s), ct.c_void_p(256), 16, None, ct.byref(h))
     assert rc == mclbm.ENOMEM and not h.value
+
+
+def test_warmnet_header_declarations_are_exported():
+    from paper_2502_12955_amd import warmnet
+
+    lib = warmnet.load()
+    src = open(os.path.join(ROOT, "include", "warmnet.h")).read()
+    names = sorted(set(re.findall(r"\b(wn_[a-z0-9_]+)\s*\(", src)))
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    # argument checks happen before any device call
+    assert lib.wn_conv3d_fwd(None, 1, 4, 4, 4, 2, None, None, 4, 3, 0, None, None) == -1
+    assert b"bad arguments" in lib.wn_last_error()
+    assert lib.wn_wgrad_workspace_bytes(1, 16, 16, 32, 3, 5, 3) == 2 * 5 * 27 * 3 * 4
