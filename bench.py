@@ -19,7 +19,6 @@ update), and the CPU oracle timed on this host's cores on a bounded sample
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,18 +32,6 @@ HBM_PEAK_GBS = 8000.0
 # once (2 x 19 flow + 7 solute values) plus one mask byte
 ALG_BYTES = {"f32": 2 * (2 * 19 + 7) * 4 + 1, "f64": 2 * (2 * 19 + 7) * 8 + 1,
              "f16s": 2 * (2 * 19 + 7) * 2 + 1, "bf16s": 2 * (2 * 19 + 7) * 2 + 1}
-KERNEL_SOURCES = ("paper_2502_12955_amd/csrc/kernels.hip", "paper_2502_12955_amd/csrc/node.hpp",
-                  "paper_2502_12955_amd/csrc/common.hpp")
-
-
-def kernel_hash():
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(storage, n, nfluid):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were
     taken on the current kernel source; else None."""
@@ -53,6 +40,8 @@ def traffic_from_profiles(storage, n, nfluid):
         return None
     with open(path) as fh:
         d = json.load(fh)
+    from paper_2502_12955_amd.profile_summary import kernel_hash
+
     if d.get("kernel_hash") != kernel_hash():
         return None
     return d.get("bytes_per_launch")
@@ -86,7 +75,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic sphere-pack box")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
-    ap.add_argument("--block", type=int, default=256, help="threads per workgroup of the step kernels")
+    ap.add_argument("--block", type=int, default=0,
+                    help="threads per workgroup of the step kernels (0: autotune the launch shape)")
+    ap.add_argument("--grid", type=int, default=0, help="persistent grid blocks with --block (0: one pass)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -110,8 +101,13 @@ def main():
     log(f"[bench] workload generated in {time.time() - t0:.1f} s")
 
     lat = mclbm.Lattice(p)
-    lat.set_launch(args.block)
     nrc = lat.set_geometry(mask)
+    if args.block:
+        lat.set_launch(args.block, args.grid)
+        shape = (args.block, args.grid, None)
+    else:
+        shape = lat.autotune(trial_steps=10)
+        log(f"[bench] autotuned launch shape: block {shape[0]}, grid {shape[1]} ({shape[2]:.3f} ms/step)")
     gmask, _, _ = lat.get_geometry()
     nfluid = int((gmask == 0).sum())
     lat.init_fields(rho, None, C)
@@ -165,7 +161,8 @@ def main():
         "config": {"workload": f"D3Q19 two-component Shan-Chen + D3Q7 reactive solute, {args.n}^3 "
                                f"Boolean sphere pack porosity 0.4 R=8, Guo forcing, body force x 1e-5, "
                                f"wall reaction k=1e-3, inlet/outlet solute",
-                   "nodes": N, "fluid_nodes": nfluid, "storage": args.storage, "block": args.block,
+                   "nodes": N, "fluid_nodes": nfluid, "storage": args.storage,
+                   "launch": {"block": shape[0], "grid": shape[1]},
                    "mflups": round(nfluid / (ms_per_step * 1e-3) / 1e6, 1),
                    "monitor_every": p["monitor_every"], "final_residual": float(mon[9])},
         "roofline": roofline,

@@ -1,0 +1,207 @@
+"""Measurement studies beyond the single-lattice benchmark.
+
+    python -m paper_2502_12955_amd.reports precision [--n 384 --steps 20000]
+        Reduced-precision storage (FP16 / BF16 shifted, FP32) against an FP64
+        run on the GPU from the same state: per-field max-abs and RMS error
+        over fluid nodes after ``steps``, throughput of each storage, and the
+        residual history of each storage on a smaller box (steps to the
+        tolerance, or the floor reached).
+
+    python -m paper_2502_12955_amd.reports batch [--count 64]
+        A batch of samples with independent per-axis edges in {32, 48, 64,
+        96, 128}: aggregate throughput of the batched, graph-replayed run
+        against the samples run one after another, and the run to a residual
+        tolerance with per-sample convergence.
+
+Each prints one JSON line (and writes it to --out if given).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import inputs, mclbm
+
+FIELDS = ("rho1", "rho2", "phi", "u_x", "u_y", "u_z", "|u|", "C")
+
+
+def _fields(rho, u, C, fluid):
+    r0, r1 = rho[0][fluid], rho[1][fluid]
+    tot = r0 + r1
+    ux, uy, uz = u[0][fluid], u[1][fluid], u[2][fluid]
+    return dict(rho1=r0, rho2=r1, phi=(r0 - r1) / tot, u_x=ux, u_y=uy, u_z=uz,
+                **{"|u|": np.sqrt(ux * ux + uy * uy + uz * uz)}, C=C[0][fluid] if C.ndim > 1 else C[fluid])
+
+
+def _timed_steps(lat, steps):
+    import torch
+
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    return max(e0.elapsed_time(e1), (time.perf_counter() - t0) * 1e3)
+
+
+def _residual_history(p, mask, rho, C, tol, cap):
+    lat = mclbm.Lattice(p)
+    lat.set_graph(True)
+    lat.set_geometry(mask)
+    lat.init_fields(rho, None, C)
+    K = p["monitor_every"]
+    hist, reached, floor = [], None, np.inf
+    t0 = time.perf_counter()
+    done = 0
+    while done < cap:
+        lat.step(K)
+        done += K
+        m = lat.monitors()
+        r = float(m[9])
+        if done > K:
+            floor = min(floor, r)
+            if done % (10 * K) == 0:
+                hist.append((done, r, float(m[4]), float(m[5]), float(m[6])))
+            if r <= tol and reached is None:
+                reached = done
+                break
+    lat.synchronize()
+    wall = time.perf_counter() - t0
+    lat.close()
+    return dict(steps_to_tol=reached, floor=floor, wall_s=wall, history=hist)
+
+
+def precision(args):
+    out = dict(study="reduced-precision storage", n=args.n, steps=args.steps)
+    p, mask, rho, _, C = inputs.porous_case(n=args.n, config=3)
+    ref = None
+    res = {}
+    for storage in ["f64"] + args.storages:
+        q = dict(p, storage=storage)
+        lat = mclbm.Lattice(q)
+        lat.set_geometry(mask)
+        gmask, _, _ = lat.get_geometry()
+        fluid = gmask.reshape(-1) == 0
+        lat.init_fields(rho, None, C)
+        ms = _timed_steps(lat, args.steps)
+        r, u, c = lat.moments()
+        lat.close()
+        f = _fields(r.reshape(2, -1), u.reshape(3, -1), c.reshape(1, -1), fluid)
+        entry = dict(ms_per_step=ms / args.steps, mlups=args.n ** 3 / (ms / args.steps * 1e-3) / 1e6)
+        if ref is None:
+            ref = f
+        else:
+            err = {}
+            for k in FIELDS:
+                d = f[k] - ref[k]
+                scale = float(np.abs(ref[k]).max())
+                err[k] = dict(max_abs=float(np.abs(d).max()), rms=float(np.sqrt(np.mean(d * d))),
+                              max_rel_to_field_max=float(np.abs(d).max() / scale) if scale else None)
+            entry["error_vs_f64"] = err
+        res[storage] = entry
+        print(f"[precision] {storage}: {entry['ms_per_step']:.3f} ms/step", flush=True)
+    out["runs"] = res
+    # residual histories on a smaller box
+    p2, mask2, rho2, _, C2 = inputs.porous_case(n=args.res_n, config=3, sample=1)
+    out["residual"] = dict(n=args.res_n, tol=args.tol, cap=args.cap)
+    for storage in ["f64"] + args.storages:
+        out["residual"][storage] = _residual_history(dict(p2, storage=storage), mask2, rho2, C2, args.tol, args.cap)
+        print(f"[precision] residual {storage}: {out['residual'][storage]['steps_to_tol']} "
+              f"floor {out['residual'][storage]['floor']:.3e}", flush=True)
+    return out
+
+
+def batch(args):
+    edges = inputs.batch_edges(args.count)
+    cases = []
+    for s, (ez, ey, ex) in enumerate(edges):
+        por = 0.3 + 0.2 * inputs.SplitMix64(inputs.seed_for(4, 1000 + s)).uniform(1)[0]
+        p, mask, rho, _, C = inputs.porous_case(shape=(ez, ey, ex), porosity=por, config=4, sample=s,
+                                               storage=args.storage)
+        cases.append((p, mask, rho, C))
+    nodes = sum(int(np.prod(c[1].shape)) for c in cases)
+    out = dict(study="batch of uneven samples", count=args.count, box_nodes=nodes, storage=args.storage,
+               edges=edges)
+
+    b = mclbm.Batch([c[0] for c in cases])
+    b.set_geometry([c[1] for c in cases])
+    shape = b.autotune(trial_steps=5)
+    b.set_graph(True)
+    b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
+    b.step(args.steps)  # warm-up and graph capture
+    fluid = int(b.monitors()[8])
+    ms = _timed_steps(b, args.steps)
+    out["fluid_nodes"] = fluid
+    out["batched"] = dict(launch=shape[:2], ms_per_step=ms / args.steps,
+                          mlups=nodes / (ms / args.steps * 1e-3) / 1e6,
+                          mflups=fluid / (ms / args.steps * 1e-3) / 1e6)
+    b.close()
+    print(f"[batch] batched: {ms / args.steps:.3f} ms/step", flush=True)
+
+    seq_ms = 0.0
+    for p, mask, rho, C in cases:
+        lat = mclbm.Lattice(p)
+        lat.set_graph(True)
+        lat.set_geometry(mask)
+        lat.init_fields(rho, None, C)
+        lat.step(min(args.steps, 200))
+        seq_ms += _timed_steps(lat, args.steps)
+        lat.close()
+    out["sequential"] = dict(ms_per_step=seq_ms / args.steps, mlups=nodes / (seq_ms / args.steps * 1e-3) / 1e6,
+                             mflups=fluid / (seq_ms / args.steps * 1e-3) / 1e6)
+    print(f"[batch] sequential: {seq_ms / args.steps:.3f} ms/step", flush=True)
+
+    b = mclbm.Batch([c[0] for c in cases])
+    b.set_geometry([c[1] for c in cases])
+    b.set_launch(*shape[:2])
+    b.set_graph(True)
+    b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
+    b.synchronize()
+    t0 = time.perf_counter()
+    ok, steps = b.run_to_residual(args.tol, args.cap)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    conv = [int(b.sample_monitors(s)[11]) if b.sample_monitors(s)[12] else -1 for s in range(args.count)]
+    b.close()
+    done = [c for c in conv if c > 0]
+    out["to_residual"] = dict(tol=args.tol, cap=args.cap, all_converged=bool(ok), steps=int(steps), wall_s=wall,
+                              converged=len(done), conv_steps=conv,
+                              median_conv_step=float(np.median(done)) if done else None)
+    print(f"[batch] to residual: {len(done)}/{args.count} converged, {steps} steps, {wall:.1f} s", flush=True)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("precision")
+    a.add_argument("--n", type=int, default=384)
+    a.add_argument("--steps", type=int, default=20000)
+    a.add_argument("--storages", nargs="+", default=["f32", "f16s", "bf16s"])
+    a.add_argument("--res-n", type=int, default=128)
+    a.add_argument("--tol", type=float, default=1e-6)
+    a.add_argument("--cap", type=int, default=30000)
+    a.add_argument("--out", default=None)
+    b = sub.add_parser("batch")
+    b.add_argument("--count", type=int, default=64)
+    b.add_argument("--steps", type=int, default=500)
+    b.add_argument("--storage", default="f32")
+    b.add_argument("--tol", type=float, default=1e-6)
+    b.add_argument("--cap", type=int, default=20000)
+    b.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    rep = precision(args) if args.what == "precision" else batch(args)
+    line = json.dumps(rep)
+    print(line)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,90 @@
+"""GPU: the full 256^3 two-phase porous workload with reactive solute, as benchmarked.
+
+The oracle cannot step 16.8 M nodes in seconds, so the GPU state after some
+steps is read back and the oracle computes one further step at sampled nodes
+(random fluid nodes, nodes with bounce-back links, wet solute links, the inlet
+and outlet planes); the GPU's next step must agree there.  FP64 storage is
+held to 1e-12 of the population scale, FP32 to 2e-6 (FP32 arithmetic on the
+same FP32 state).  Every launch shape the autotuner may pick gives bit-identical
+populations after a step at this size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_12955_amd import inputs, mclbm
+
+from helpers import split_pops
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def workload():
+    p, mask, rho, u, C = inputs.porous_case(n=256)
+    m, _ = oracle.pinch_fill(p, mask)
+    return p, mask, m, rho, C
+
+
+def _sample_nodes(p, m, lat, count=3000):
+    nx = p["nx"]
+    fluid = np.flatnonzero(m.reshape(-1) == 0)
+    rng = inputs.SplitMix64(inputs.seed_for(2, 77))
+    pick = [fluid[rng.integers(count, fluid.size)]]
+    _, flow_links, sol_links = lat.get_geometry()
+    walled = np.flatnonzero((flow_links != 0) & (m.reshape(-1) == 0))
+    pick.append(walled[rng.integers(count // 3, walled.size)])
+    wet = np.flatnonzero((sol_links != 0) & (m.reshape(-1) == 0))
+    pick.append(wet[rng.integers(count // 3, wet.size)])
+    x = fluid % nx
+    for plane in (0, 1, nx - 2, nx - 1):
+        on = fluid[x == plane]
+        pick.append(on[rng.integers(count // 6, on.size)])
+    return np.unique(np.concatenate(pick))
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_full_size_sampled_step_matches_oracle(workload, storage, tol):
+    p0, mask, m, rho, C = workload
+    p = dict(p0, storage=storage, k_wall=0.02)
+    lat = mclbm.Lattice(p)
+    lat.set_geometry(mask)
+    rng = inputs.SplitMix64(inputs.seed_for(2, 78))
+    C0 = 0.5 * rng.uniform(C.size).reshape(C.shape)
+    lat.init_fields(rho, None, C0)
+    lat.step(6)
+    nodes = _sample_nodes(p, m, lat)
+    f, h = split_pops(p, lat.populations())
+    f = np.asarray(f, np.float64)
+    h = np.asarray(h, np.float64)
+    fo, ho = oracle.step_nodes(p, m, f, h, nodes)
+    del f, h
+    lat.step(1)
+    fg, hg = split_pops(p, lat.populations())
+    fg = np.asarray(fg[:, nodes], np.float64).T
+    hg = np.asarray(hg[:, nodes], np.float64).T
+    lat.close()
+    scale = np.abs(fo).max()
+    print(storage, len(nodes), np.abs(fg - fo).max() / scale, np.abs(hg - ho).max(), flush=True)
+    assert np.abs(fg - fo).max() <= tol * scale
+    assert np.abs(hg - ho).max() <= tol * max(1.0, np.abs(ho).max())
+
+
+def test_full_size_every_autotune_shape_is_bit_identical(workload):
+    p, mask, m, rho, C = workload
+    ref = None
+    shapes = [(256, 0)]
+    lat = mclbm.Lattice(p)
+    lat.set_geometry(mask)
+    _, _, _, table = mclbm.autotune(lat.h, 1)
+    shapes += [(int(b), int(g)) for b, g, _ in table]
+    for blk, grid in shapes:
+        lat.set_launch(blk, grid)
+        lat.init_fields(rho, None, C)
+        lat.step(2)
+        pops = lat.populations(raw=True)
+        if ref is None:
+            ref = pops
+        else:
+            assert np.array_equal(pops, ref), (blk, grid)
+    lat.close()
