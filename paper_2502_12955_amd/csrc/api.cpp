@@ -354,7 +354,11 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     c.links = h->links;
     c.psi = h->psi;
     c.snap = h->snap;
-    c.work = h->work;
+    // the work list only once some sample has converged: with every sample
+    // running, chunk = item saves a dependent load at the start of each chunk
+    bool any_frozen = false;
+    for (const auto& sm : h->smp) any_frozen |= sm.frozen;
+    c.work = any_frozen ? h->work : nullptr;
     c.nwork = h->nwork;
     c.partials = h->partials;
     c.result = h->result;
@@ -624,6 +628,11 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     return mclbm_init_batch(p, 1, device_arena, arena_bytes, hip_stream, out);
 }
 
+static uint32_t tail_link_word(int lattice) {
+    const int Q = flow_q(lattice);
+    return 0x80000000u | (((1u << Q) - 1u) & ~1u);
+}
+
 int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_reclassified) {
     if (!h) return MCLBM_EINVAL;
     if (!solid_mask) return fail(h, MCLBM_EINVAL, "solid_mask is NULL");
@@ -659,7 +668,9 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
         sm.kbase = kbase;
         const long long padded = pad64(sm.nf);
         pos.resize((size_t)(kbase + padded), 0u);
-        links.resize((size_t)(kbase + padded), 0x80000000u);
+        // tail lanes of the last chunk: box node 0 of the sample, every flow
+        // link blocked and the solid flag (the step kernel has no tail check)
+        links.resize((size_t)(kbase + padded), tail_link_word(h->p.lattice));
         for (long long k = 0; k < sm.nf; ++k) {
             pos[(size_t)(kbase + k)] = sm.pos[k];
             links[(size_t)(kbase + k)] = words[sm.pos[k]];
@@ -936,7 +947,8 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
             return e;
         }
         if (h->step % K != 0) continue;
-        bool all = true, changed = false;
+        bool all = true, changed = false, had_frozen = false;
+        for (const auto& sm : h->smp) had_frozen |= sm.frozen;
         for (auto& sm : h->smp) {
             if (sm.frozen) continue;
             if (sm.mon[0] == (double)h->step && sm.mon[9] <= tol) {
@@ -957,6 +969,7 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
             rc = MCLBM_OK;
             break;
         }
+        if (changed && !had_frozen) drop_graphs(h);   // captured without the work list
         if (changed) {
             int u = upload_work(h);
             if (u != MCLBM_OK) return u;

@@ -63,7 +63,17 @@ struct Geo {
     const int* work;   // nullptr: every chunk
     const int* nwork;
     int nchunks;
+    int reverse;       // 1: visit the work items in reverse order
 };
+
+// Wave-uniform load of a value that no kernel writes while it runs (work
+// list, chunk -> sample table, sample records): read through the constant
+// address space, so it becomes a scalar load that does not queue behind the
+// wavefront's vector loads.
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
 
 // Calls body(chunk) for every work item of this wavefront.
 template <class Body>
@@ -73,13 +83,29 @@ __device__ __forceinline__ void for_each_chunk(const Geo& g, Body body) {
     const int G = gridDim.x;  // multiple of 8
     const int b = blockIdx.x;
     const int lb0 = (b & 7) * (G >> 3) + (b >> 3);
-    const int nitems = g.work ? *g.nwork : g.nchunks;
+    const int nitems = g.work ? ld_uniform(g.nwork) : g.nchunks;
     for (int it = 0;; ++it) {
-        const int item = (it * G + lb0) * wpb + wave;
+        int item = (it * G + lb0) * wpb + wave;
         if (item >= nitems) break;
-        const int ch = g.work ? __builtin_amdgcn_readfirstlane(g.work[item]) : item;
+        if (g.reverse) item = nitems - 1 - item;
+        const int ch = g.work ? ld_uniform(g.work + item) : item;
         body(ch);
     }
+}
+
+__device__ __forceinline__ SampleDev sample_of(const Geo& g, int ch) {
+    const int s = ld_uniform(g.chunk_sample + ch);
+    const int* q = (const int*)(g.smp + s);
+    SampleDev d;
+    d.nx = ld_uniform(q + 0);
+    d.ny = ld_uniform(q + 1);
+    d.nz = ld_uniform(q + 2);
+    d.Nf = ld_uniform(q + 3);
+    d.N = ld_uniform(q + 4);
+    d.dbase = ld_uniform(q + 5);
+    d.kbase = ld_uniform(q + 6);
+    d.pad_ = 0;
+    return d;
 }
 
 __device__ __forceinline__ void coords(const unsigned n, int nx, int ny, int& x, int& y, int& z) {
@@ -126,18 +152,24 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
-        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        // populations and pos first: every lane of a chunk is inside the
+        // (chunk-padded) arrays, so these loads need not wait for the sample
+        // record; tail lanes are discarded below
         const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
-        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
-        const unsigned n = g.pos[k];
-        R* ps = psi + (size_t)NC * sd.dbase;
+        R rho[NC];
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             R r = 0;
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
-            ps[(size_t)s * sd.N + n] = P.rho0 * (R(1) - exp_r<R>(-r * P.inv_rho0));
+            rho[s] = r;
         }
+        const unsigned n = g.pos[k];
+        const SampleDev sd = sample_of(g, ch);
+        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+        R* ps = psi + (size_t)NC * sd.dbase;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) ps[(size_t)s * sd.N + n] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
     });
 }
 
@@ -158,17 +190,13 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
     R sh[NC][Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
-        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        // No tail check: the lanes past a sample's last fluid node (up to the
+        // 64-node chunk boundary) carry pos 0 and a link word with every flow
+        // link blocked, so they read inside the sample and store only into
+        // their own (unused) slots.  Node-local loads are issued first.
         const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
-        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
         const unsigned n = g.pos[k];
         const uint32_t lw = g.links[k];
-        int x, y, z;
-        coords(n, sd.nx, sd.ny, x, y, z);
-        const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
-        const int* mp = g.map + sd.dbase;
-        const R* ps = psi + (size_t)NC * sd.dbase;
-
         R f[NC][Q];
 #pragma unroll
         for (int s = 0; s < NC; ++s)
@@ -179,6 +207,12 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
 #pragma unroll
             for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
         }
+        const SampleDev sd = sample_of(g, ch);
+        int x, y, z;
+        coords(n, sd.nx, sd.ny, x, y, z);
+        const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
+        const int* mp = g.map + sd.dbase;
+        const R* ps = psi + (size_t)NC * sd.dbase;
 
         auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)t * sd.N + nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
         R u[3];
@@ -234,7 +268,7 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
     R sh[NC][L::Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
-        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const SampleDev sd = sample_of(g, ch);
         const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
         if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
         const size_t N = sd.N;
@@ -334,7 +368,7 @@ __global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R>
                                                      double* __restrict__ C_out) {
     using R = typename Store<ST>::R;
     for_each_chunk(g, [&](int ch) {
-        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const SampleDev sd = sample_of(g, ch);
         const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
         if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
         R rho[NC], u[3], C;
@@ -371,7 +405,7 @@ __global__ void __launch_bounds__(256) k_monitor(Phys<typename Store<ST>::R> P, 
                                                  int have_snapshot, double* __restrict__ partials) {
     using R = typename Store<ST>::R;
     for_each_chunk(g, [&](int ch) {
-        const SampleDev sd = g.smp[g.chunk_sample[ch]];
+        const SampleDev sd = sample_of(g, ch);
         const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
         double v[MON_NV];
 #pragma unroll
@@ -509,6 +543,7 @@ static inline Geo make_geo(const Ctx& c, bool use_work) {
     g.work = use_work ? c.work : nullptr;
     g.nwork = c.nwork;
     g.nchunks = (int)c.nchunks;
+    g.reverse = 0;
     return g;
 }
 
@@ -529,7 +564,12 @@ static hipError_t step_t(const Ctx& c) {
     const dim3 grid = grid_for(c, bs, true);
     hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
-    hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+    // the collide pass walks the chunks in the opposite order of the density
+    // pass, so it starts on the chunks the density pass read last (still in
+    // the memory-side cache), and the next density pass on those it wrote last
+    Geo gr = g;
+    gr.reverse = 1;
+    hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,
                        (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
     return hipGetLastError();
 }

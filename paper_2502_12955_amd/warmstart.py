@@ -51,13 +51,12 @@ def make_samples(n, count, first, config=5, radius=8, blob_radius=6, saturation=
 
 def solve(samples, tol, max_steps, storage="f32", init=None):
     """Run a batch to tolerance.  ``init``: optional list of (rho, u) per sample
-    (default: rest with the seeded phases).  Returns per-sample steps, the
-    converged fields, the pinch-filled masks and the wall time."""
+    (default: rest with the seeded phases).  Returns per-sample steps (-1: not
+    converged within max_steps), the final fields and the wall time."""
     plist = [dict(s["params"], storage=storage) for s in samples]
     b = mclbm.Batch(plist)
     b.set_graph(True)
     b.set_geometry([s["mask"] for s in samples])
-    masks = b.geometry() if hasattr(b, "geometry") else None
     if init is None:
         b.init_fields([s["rho"] for s in samples])
     else:
@@ -70,7 +69,7 @@ def solve(samples, tol, max_steps, storage="f32", init=None):
     per = [int(b.sample_monitors(i)[11]) if b.sample_monitors(i)[12] else -1 for i in range(len(samples))]
     rhos, us, _ = b.moments()
     b.close()
-    return dict(converged=ok, steps=per, total_steps=steps, wall=wall, rho=rhos, u=us, masks=masks)
+    return dict(converged=ok, steps=per, total_steps=steps, wall=wall, rho=rhos, u=us)
 
 
 def features(mask, rho):

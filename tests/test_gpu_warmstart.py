@@ -1,0 +1,59 @@
+"""GPU: the warm-start pipeline (data generation, training, restart from a prediction).
+
+The lattice Boltzmann solver judges convergence, so a warm start can only
+change the number of steps.  Pinned here: restarting from the converged fields
+themselves (a perfect prediction) must need far fewer steps than starting from
+rest; training on solver output lowers the loss; a learned prediction restarts
+cleanly and converges.
+"""
+import numpy as np
+import pytest
+
+from paper_2502_12955_amd import warmstart
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N = 32
+TOL = 1e-3
+
+
+def test_restart_from_converged_fields_needs_few_steps():
+    samples = warmstart.make_samples(N, 3, first=500)
+    cold = warmstart.solve(samples, TOL, 60000)
+    assert all(s > 0 for s in cold["steps"]), cold["steps"]
+    init = []
+    for r, u in zip(cold["rho"], cold["u"]):
+        init.append((np.asarray(r).reshape(2, -1), np.asarray(u).reshape(3, -1)))
+    warm = warmstart.solve(samples, TOL, 60000, init=init)
+    print("cold", cold["steps"], "restart", warm["steps"], flush=True)
+    assert all(0 < w <= max(300, 0.25 * c) for w, c in zip(warm["steps"], cold["steps"]))
+
+
+def test_training_lowers_the_loss_and_prediction_restarts():
+    from paper_2502_12955_amd import warmnet
+
+    train = warmstart.make_samples(N, 4, first=600)
+    gen = warmstart.solve(train, TOL, 60000)
+    shape = (N, N, N)
+    scale = warmstart.u_scale(train[0]["params"], 8)
+    X = np.stack([warmstart.features(s["mask"], s["rho"].reshape((2,) + shape)) for s in train])
+    T = np.stack([warmstart.targets(r, u, shape, scale) for r, u in zip(gen["rho"], gen["u"])])
+    x = torch.tensor(X, device="cuda:0")
+    t = torch.tensor(T, device="cuda:0")
+    net = warmnet.UNet(cin=2, cout=4, widths=(8, 16, 32), seed=1)
+    tr = warmstart.Trainer(net, x, t, [4.0, 4.0, 4.0, 1.0], batch=2)
+    rng = np.random.default_rng(0)
+    losses = [tr.epoch(3e-3, rng) for _ in range(25)]
+    print("losses", losses[0], losses[-1], flush=True)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
+    test = warmstart.make_samples(N, 2, first=700)
+    init = []
+    for s in test:
+        xf = torch.tensor(warmstart.features(s["mask"], s["rho"].reshape((2,) + shape))[None], device="cuda:0")
+        y, _ = net.forward(xf)
+        init.append(warmstart.fields_from_prediction(y[0].cpu().numpy(), (s["rho"].sum(0) == 0), scale))
+    warm = warmstart.solve(test, TOL, 60000, init=init)
+    print("warm steps", warm["steps"], flush=True)
+    assert all(s > 0 for s in warm["steps"])
