@@ -62,6 +62,7 @@ enum { MCLBM_FORCING_GUO = 0, MCLBM_FORCING_SC = 1 };
  * fluid-mean density of component s at init_fields) in 16 bits with
  * round-to-nearest-even; collision arithmetic is FP32.  The solute is stored
  * unshifted.  F64 computes in FP64, the others in FP32. */
+enum { MCLBM_KERNEL_TWO_PASS = 0, MCLBM_KERNEL_FUSED = 1 };
 enum { MCLBM_F64 = 0, MCLBM_F32 = 1, MCLBM_F16_SHIFT = 2, MCLBM_BF16_SHIFT = 3 };
 enum { MCLBM_SOLUTE_OFF = 0, MCLBM_SOLUTE_PERIODIC = 1, MCLBM_SOLUTE_INLET_OUTLET_X = 2 };
 
@@ -169,8 +170,12 @@ int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes);
 
 /* Step in chunks of monitor_every until the maximum residual at a monitor is
  * <= tol or max_steps have been taken.  *steps_taken (may be NULL) receives
- * the steps of this call.  Returns MCLBM_OK when converged, 1 when max_steps
- * was reached first, or an error. */
+ * the steps of this call.  In a batch each sample stops (is frozen, its state
+ * kept) at the first monitor where its own residual is <= tol; a sample whose
+ * monitor sees a non-finite value is frozen as diverged while the others go
+ * on.  Returns MCLBM_OK when every sample converged, 1 when max_steps was
+ * reached first, MCLBM_EDIVERGED when every sample has stopped and at least
+ * one diverged (per-sample flags: mclbm_get_sample_monitors), or an error. */
 int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_t* steps_taken);
 
 /* Launch shape of the step kernels: block_threads per workgroup (64, 128 or
@@ -180,19 +185,30 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
  * with the same arithmetic, so results do not depend on the launch shape. */
 int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks);
 
-/* Time the step kernels over a set of launch shapes and keep the fastest.
- * Candidates: block_threads 64, 128, 256 crossed with grid_blocks 0 (one
- * pass) and persistent grids of 8, 16 and 32 wavefronts per compute unit.
- * Each candidate runs 2 untimed steps, then trial_steps (>= 1) steps timed
- * with HIP events on the handle's stream.  Needs set_geometry; it overwrites
- * the populations (uniform rest state, density 1), so init_fields must be
- * called afterwards (ESTATE until then).  The chosen shape is applied as by
- * mclbm_set_launch and returned in *block_threads, *grid_blocks and
- * *ms_per_step (any may be NULL).  The candidates' timings are written to
- * table[3 * i + 0..2] = (block, grid, ms per step) for i < table_rows (table
- * may be NULL); *n_rows (may be NULL) receives the number of candidates. */
-int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
-                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
+/* Step kernel: MCLBM_KERNEL_TWO_PASS (default; a density pass over all fluid
+ * nodes, then a collide-and-push pass) or MCLBM_KERNEL_FUSED (D3Q19 only: one
+ * pass of z-marching workgroups over x-y tiles that keep three planes of
+ * pseudo-potentials and fluid indices in LDS).  Both update every node with
+ * the same arithmetic, so results are bit-identical.  EINVAL for an unknown
+ * kind or the fused kernel on D2Q9. */
+int mclbm_set_kernel(mclbm_handle* h, int32_t kernel);
+
+/* Time the step kernels over a set of candidates and keep the fastest.
+ * Candidates: the two-pass kernels with block_threads 64, 128, 256 crossed
+ * with grid_blocks 0 (one pass) and persistent grids of 8, 16 and 32
+ * wavefronts per compute unit, and (D3Q19) the fused kernel.  Each runs 2
+ * untimed steps, then trial_steps (>= 1) steps timed with HIP events on the
+ * handle's stream.  Needs set_geometry; it overwrites the populations
+ * (uniform rest state, density 1), so init_fields must be called afterwards
+ * (ESTATE until then).  The choice is applied as by mclbm_set_kernel and
+ * mclbm_set_launch and returned in *kernel, *block_threads, *grid_blocks and
+ * *ms_per_step (any may be NULL; for the fused kernel block and grid are its
+ * fixed 512 threads and one workgroup per work item).  The candidates' timings
+ * are written to table[4 * i + 0..3] = (kernel, block, grid, ms per step) for
+ * i < table_rows (table may be NULL); *n_rows (may be NULL) receives the
+ * number of candidates. */
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_t* block_threads,
+                   int32_t* grid_blocks, double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
 
 /* enable != 0: run each aligned interval of monitor_every steps (which must
  * be even) as one replay of a captured HIP graph (the step kernels plus the
@@ -218,8 +234,9 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
                      void* hip_stream, mclbm_handle** out);
 
 /* Monitors of sample s (layout of mclbm_get_monitors), plus out[11] = step
- * at which the sample converged in run_to_residual (-1 if not) and out[12] =
- * 1 if it is frozen. */
+ * at which the sample converged in run_to_residual (-1 if not), out[12] = 1
+ * if it is frozen and out[13] = step of the monitor at which it was found
+ * diverged (-1 if not). */
 int mclbm_get_sample_monitors(mclbm_handle* h, int32_t s, double out[16]);
 
 /* Current step counter. */

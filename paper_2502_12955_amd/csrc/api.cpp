@@ -97,8 +97,10 @@ struct SampleHost {
     long long nf;     // fluid nodes
     std::vector<uint8_t> mask;
     std::vector<unsigned> pos;  // box index of each fluid node, increasing
-    bool frozen = false;        // converged and excluded from the work list
+    bool frozen = false;        // converged or diverged, excluded from the work list
     long long conv_step = -1;
+    long long div_step = -1;    // monitor step at which a non-finite value was seen
+    bool bad = false;           // the last monitor saw a non-finite value
     double mon[16];
 };
 
@@ -128,6 +130,11 @@ struct mclbm_handle {
     int* chunk_sample = nullptr;
     int* work = nullptr;
     int* nwork = nullptr;
+    int4* fitems = nullptr;         // fused-step work items
+    int* fwork = nullptr;
+    int* fnwork = nullptr;
+    long long nfitems = 0;
+    std::vector<long long> fitem_base;  // first fused item of each sample (S + 1 entries)
     double* host_result = nullptr;  // pinned [S][16]
     int* host_nwork = nullptr;      // pinned
     // state
@@ -137,6 +144,7 @@ struct mclbm_handle {
     double mon[16];
     double rhobar[2] = {0, 0};
     int block = 256, grid = 0;
+    int kernel = 0;                  // 0: two passes, 1: fused (D3Q19)
     // graph replay of monitor_every steps (one per A/B parity)
     bool use_graph = false;
     hipStream_t gstream = nullptr;
@@ -149,7 +157,7 @@ namespace {
 
 struct Layout {
     size_t fA, fB, hA, hB, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample, work, nwork,
-        total;
+        fitems, fwork, fnwork, total;
 };
 
 Ctx base_ctx(const mclbm_params& p) {
@@ -172,6 +180,17 @@ Ctx base_ctx(const mclbm_params& p) {
     c.k_wall = p.k_wall;
     c.C_in = p.C_in;
     return c;
+}
+
+// fused-step work items of one sample: x-y tiles times z segments
+long long fused_items_of(const mclbm_params& p) {
+    return (long long)((p.nx + FTX - 1) / FTX) * ((p.ny + FTY - 1) / FTY) * ((p.nz + FZS - 1) / FZS);
+}
+
+long long fused_item_count(const mclbm_params* ps, int n) {
+    long long t = 0;
+    for (int s = 0; s < n; ++s) t += fused_items_of(ps[s]);
+    return t;
 }
 
 Layout layout_for(const mclbm_params* ps, int n) {
@@ -209,6 +228,10 @@ Layout layout_for(const mclbm_params* ps, int n) {
     L.chunk_sample = take(nch * 4);
     L.work = take(nch * 4);
     L.nwork = take(64);
+    const size_t nfi = (size_t)fused_item_count(ps, n);
+    L.fitems = take(nfi * sizeof(int4));
+    L.fwork = take(nfi * 4);
+    L.fnwork = take(64);
     L.total = align256(off);
     return L;
 }
@@ -360,6 +383,11 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     for (const auto& sm : h->smp) any_frozen |= sm.frozen;
     c.work = any_frozen ? h->work : nullptr;
     c.nwork = h->nwork;
+    c.kernel = h->kernel;
+    c.fitems = h->fitems;
+    c.fwork = any_frozen ? h->fwork : nullptr;
+    c.fnwork = h->fnwork;
+    c.nfitems = h->nfitems;
     c.partials = h->partials;
     c.result = h->result;
     c.block = h->block;
@@ -427,7 +455,8 @@ int collect_monitor(mclbm_handle* h, bool had) {
         if (sm.frozen) continue;
         const double* r = h->host_result + (size_t)s * 16;
         sample_monitor(h, sm, r, had);
-        bad |= r[9] != 0.0 || !isfinite(r[0]) || !isfinite(r[2]);
+        sm.bad = r[9] != 0.0 || !isfinite(r[0]) || !isfinite(r[2]);
+        bad |= sm.bad;
     }
     aggregate_monitor(h);
     if (bad) return fail(h, MCLBM_EDIVERGED, "non-finite value at a monitor");
@@ -448,6 +477,17 @@ int upload_work(mclbm_handle* h) {
         HIPCHK(h, hipMemcpyAsync(h->work, w.data(), w.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->nwork, h->host_nwork, 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->fitem_base.size() == (size_t)h->S + 1) {
+        std::vector<int> fw;
+        for (int s = 0; s < h->S; ++s)
+            if (!h->smp[s].frozen)
+                for (long long i = h->fitem_base[s]; i < h->fitem_base[s + 1]; ++i) fw.push_back((int)i);
+        *h->host_nwork = (int)fw.size();
+        if (!fw.empty())
+            HIPCHK(h, hipMemcpyAsync(h->fwork, fw.data(), fw.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->fnwork, h->host_nwork, 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
     return MCLBM_OK;
 }
 
@@ -611,6 +651,10 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
     h->chunk_sample = (int*)(base + L.chunk_sample);
     h->work = (int*)(base + L.work);
     h->nwork = (int*)(base + L.nwork);
+    h->fitems = (int4*)(base + L.fitems);
+    h->fwork = (int*)(base + L.fwork);
+    h->fnwork = (int*)(base + L.fnwork);
+    h->nfitems = fused_item_count(p, n);
     hipError_t e = hipHostMalloc((void**)&h->host_result, (size_t)n * 16 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_nwork, 64, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -679,10 +723,23 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
         sd[s] = SampleDev{sm.nx, sm.ny, sm.nz, (int)sm.nf, (int)sm.N, (int)sm.dbase, (int)sm.kbase, 0};
         sm.frozen = false;
         sm.conv_step = -1;
+        sm.div_step = -1;
+        sm.bad = false;
         kbase += padded;
     }
     h->nchunks = kbase / 64;
     if (n_reclassified) *n_reclassified = nrc;
+    std::vector<int4> items;
+    h->fitem_base.assign(1, 0);
+    for (int s = 0; s < h->S; ++s) {
+        const SampleHost& sm = h->smp[s];
+        for (int z0 = 0; z0 < sm.nz; z0 += FZS)
+            for (int y0 = 0; y0 < sm.ny; y0 += FTY)
+                for (int x0 = 0; x0 < sm.nx; x0 += FTX) items.push_back(make_int4(s, x0, y0, z0));
+        h->fitem_base.push_back((long long)items.size());
+    }
+    if ((long long)items.size() != h->nfitems) return fail(h, MCLBM_EINVAL, "fused item count mismatch");
+    HIPCHK(h, hipMemcpyAsync(h->fitems, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->map, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->links, links.data(), links.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -742,6 +799,8 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     for (auto& sm : h->smp) {
         sm.frozen = false;
         sm.conv_step = -1;
+        sm.div_step = -1;
+        sm.bad = false;
         for (int k = 0; k < 16; ++k) sm.mon[k] = 0.0;
         sm.mon[0] = -1.0;
     }
@@ -832,6 +891,7 @@ int mclbm_get_sample_monitors(mclbm_handle* h, int32_t s, double out[16]) {
     out[10] = (double)h->step;
     out[11] = (double)h->smp[s].conv_step;
     out[12] = h->smp[s].frozen ? 1.0 : 0.0;
+    out[13] = (double)h->smp[s].div_step;
     return MCLBM_OK;
 }
 
@@ -942,16 +1002,25 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
         const int64_t before = h->step;
         int e = mclbm_step(h, chunk);
         taken += h->step - before;
-        if (e != MCLBM_OK) {
+        if (e != MCLBM_OK && e != MCLBM_EDIVERGED) {
             if (steps_taken) *steps_taken = taken;
             return e;
         }
         if (h->step % K != 0) continue;
-        bool all = true, changed = false, had_frozen = false;
+        bool active = false, changed = false, had_frozen = false, any_div = false;
         for (const auto& sm : h->smp) had_frozen |= sm.frozen;
         for (auto& sm : h->smp) {
-            if (sm.frozen) continue;
-            if (sm.mon[0] == (double)h->step && sm.mon[9] <= tol) {
+            if (sm.frozen) {
+                any_div |= sm.div_step >= 0;
+                continue;
+            }
+            const bool fresh = sm.mon[0] == (double)h->step;
+            if (fresh && sm.bad) {
+                sm.frozen = true;
+                sm.div_step = h->step;
+                sm.mon[12] = 1.0;
+                changed = any_div = true;
+            } else if (fresh && sm.mon[9] <= tol) {
                 sm.frozen = true;
                 sm.conv_step = h->step;
                 sm.mon[11] = (double)sm.conv_step;
@@ -962,11 +1031,11 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
                     if (m != MCLBM_OK) return m;
                 }
             } else {
-                all = false;
+                active = true;
             }
         }
-        if (all) {
-            rc = MCLBM_OK;
+        if (!active) {
+            rc = any_div ? fail(h, MCLBM_EDIVERGED, "a sample went non-finite (see the sample monitors)") : MCLBM_OK;
             break;
         }
         if (changed && !had_frozen) drop_graphs(h);   // captured without the work list
@@ -991,8 +1060,19 @@ int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks
     return MCLBM_OK;
 }
 
-int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
-                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
+int mclbm_set_kernel(mclbm_handle* h, int32_t kernel) {
+    if (!h) return MCLBM_EINVAL;
+    if (kernel != MCLBM_KERNEL_TWO_PASS && kernel != MCLBM_KERNEL_FUSED)
+        return fail(h, MCLBM_EINVAL, "unknown step kernel");
+    if (kernel == MCLBM_KERNEL_FUSED && h->p.lattice != MCLBM_D3Q19)
+        return fail(h, MCLBM_EINVAL, "the fused step kernel is D3Q19 only");
+    drop_graphs(h);
+    h->kernel = kernel;
+    return MCLBM_OK;
+}
+
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_t* block_threads,
+                   int32_t* grid_blocks, double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
     if (!h) return MCLBM_EINVAL;
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
     if (trial_steps < 1) return fail(h, MCLBM_EINVAL, "trial_steps must be >= 1");
@@ -1004,26 +1084,32 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads,
     int dev = 0, cus = 0;
     HIPCHK(h, hipGetDevice(&dev));
     HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    std::vector<std::pair<int, int>> cand;
+    struct Cand {
+        int kernel, block, grid;
+    };
+    std::vector<Cand> cand;
     for (int b : {64, 128, 256}) {
-        cand.push_back({b, 0});
+        cand.push_back({MCLBM_KERNEL_TWO_PASS, b, 0});
         for (int w : {8, 16, 32}) {
             const int g = (cus * w / (b / 64) + 7) / 8 * 8;
-            if (g > 0) cand.push_back({b, g});
+            if (g > 0) cand.push_back({MCLBM_KERNEL_TWO_PASS, b, g});
         }
     }
+    if (h->p.lattice == MCLBM_D3Q19) cand.push_back({MCLBM_KERNEL_FUSED, FT_THREADS, 0});
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return fail(h, MCLBM_EHIP, "hipEventCreate failed");
     }
-    const int old_block = h->block, old_grid = h->grid;
+    const int old_kernel = h->kernel, old_block = h->block, old_grid = h->grid;
     double best = INFINITY;
-    int bb = old_block, bg = old_grid, rc = MCLBM_OK;
+    Cand bc{old_kernel, old_block, old_grid};
+    int rc = MCLBM_OK;
     for (size_t i = 0; i < cand.size() && rc == MCLBM_OK; ++i) {
-        h->block = cand[i].first;
-        h->grid = cand[i].second;
+        h->kernel = cand[i].kernel;
+        h->block = cand[i].kernel == MCLBM_KERNEL_FUSED ? old_block : cand[i].block;
+        h->grid = cand[i].kernel == MCLBM_KERNEL_FUSED ? old_grid : cand[i].grid;
         for (int s = 0; s < 2 && rc == MCLBM_OK; ++s) rc = launch_step(h, h->stream);
         if (rc != MCLBM_OK) break;
         hipError_t e = hipEventRecord(e0, h->stream);
@@ -1036,14 +1122,14 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads,
         if (rc != MCLBM_OK) break;
         const double per = (double)ms / trial_steps;
         if (table && (int)i < table_rows) {
-            table[3 * i + 0] = cand[i].first;
-            table[3 * i + 1] = cand[i].second;
-            table[3 * i + 2] = per;
+            table[4 * i + 0] = cand[i].kernel;
+            table[4 * i + 1] = cand[i].block;
+            table[4 * i + 2] = cand[i].grid;
+            table[4 * i + 3] = per;
         }
         if (per < best) {
             best = per;
-            bb = cand[i].first;
-            bg = cand[i].second;
+            bc = cand[i];
         }
     }
     (void)hipEventDestroy(e0);
@@ -1052,14 +1138,18 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads,
     h->step = 0;
     h->snap_valid = false;
     if (rc != MCLBM_OK) {
+        h->kernel = old_kernel;
         h->block = old_block;
         h->grid = old_grid;
         return rc;
     }
-    h->block = bb;
-    h->grid = bg;
-    if (block_threads) *block_threads = bb;
-    if (grid_blocks) *grid_blocks = bg;
+    h->kernel = bc.kernel;
+    // the two-pass launch shape stays valid (the other kernels use it too)
+    h->block = bc.kernel == MCLBM_KERNEL_FUSED ? old_block : bc.block;
+    h->grid = bc.kernel == MCLBM_KERNEL_FUSED ? old_grid : bc.grid;
+    if (kernel) *kernel = bc.kernel;
+    if (block_threads) *block_threads = bc.block;
+    if (grid_blocks) *grid_blocks = bc.grid;
     if (ms_per_step) *ms_per_step = best;
     if (n_rows) *n_rows = (int32_t)cand.size();
     return MCLBM_OK;

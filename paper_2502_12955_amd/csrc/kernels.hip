@@ -10,7 +10,8 @@
 //   ((k >> 6) * P + j) * 64 + (k & 63),   P = planes of the array,
 // so a wavefront reads every plane of its 64 nodes as contiguous 256-byte
 // rows, and no byte of a solid node is moved.  The pseudo-potential field is
-// dense over each sample's box, zero on solid nodes.
+// dense over each sample's box, zero on solid nodes, with the components of a
+// node adjacent (psi[n * NC + s]) so one load fetches both.
 //
 // Work distribution: each wavefront processes one chunk at a time, taken from
 // a device-side list of active chunks (samples that have converged are left
@@ -169,8 +170,66 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
         if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
         R* ps = psi + (size_t)NC * sd.dbase;
 #pragma unroll
-        for (int s = 0; s < NC; ++s) ps[(size_t)s * sd.N + n] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
+        for (int s = 0; s < NC; ++s) ps[(size_t)n * NC + s] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
     });
+}
+
+// ---------------------------------------------------------------------------
+// collision of one fluid node and push of its post-collision populations
+// (flow with halfway bounce-back; solute with the wet-node reaction, inlet and
+// outlet), shared by the two-pass and the fused step kernels.
+//   f: pre-collision flow populations of node k (overwritten)
+//   psi_nb(t, i): pseudo-potential of component t at x + c_i (0 for solids)
+//   dest(i): fluid index of x + c_i (called only where that node is fluid)
+//   x, nx: x coordinate of the node and the box edge (solute seams)
+// ---------------------------------------------------------------------------
+template <int LAT, int ST, int NC, class PsiNb, class Dest>
+__device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& P,
+                                             const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q], unsigned k,
+                                             uint32_t lw, int x, int nx, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q],
+                                             PsiNb psi_nb, Dest dest, typename Store<ST>::T* __restrict__ fB,
+                                             const typename Store<ST>::T* __restrict__ hA,
+                                             typename Store<ST>::T* __restrict__ hB) {
+    using L = Lat<LAT>;
+    using S = Store<ST>;
+    using R = typename S::R;
+    constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
+    R u[3];
+    flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
+        unsigned kd = k;
+        if (i != 0 && !bb) kd = dest(i);
+        const int dir = bb ? L::opp[i] : i;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) S::store(blk(fB, PF, s * Q + dir, kd), f[s][i], sh[s][i]);  // w_i = w_opp(i)
+    }
+    if (P.solute) {
+        // loaded only now: fewer registers live through the flow part
+        R h[QS];
+#pragma unroll
+        for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
+        solute_collide<LAT, R>(P, h, u);
+        S::store_plain(blk(hB, QS, 0, k), h[0]);
+        const bool seam_mode = (P.solute == 2);
+#pragma unroll
+        for (int d = 1; d < QS; ++d) {
+            const int dx = L::cx[d];
+            const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
+            if (!seam && !(lw & (1u << L::opp[d]))) {
+                const unsigned kd = dest(d);
+                S::store_plain(blk(hB, QS, d, kd), h[d]);
+                if (lw & (1u << (L::HOP_SHIFT + d))) {
+                    const R Cb = R(2) * h[d] * P.wet_inv_den;
+                    S::store_plain(blk(hB, QS, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
+                }
+                if (seam_mode && d == L::SXM && x == 1)
+                    S::store_plain(blk(hB, QS, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
+            }
+            if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, QS, d, k), h[d]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -186,7 +245,7 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
+    constexpr int Q = L::Q, PF = NC * Q;
     R sh[NC][Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
@@ -202,11 +261,6 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
         for (int s = 0; s < NC; ++s)
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
-        R h[QS];
-        if (P.solute) {
-#pragma unroll
-            for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
-        }
         const SampleDev sd = sample_of(g, ch);
         int x, y, z;
         coords(n, sd.nx, sd.ny, x, y, z);
@@ -214,42 +268,113 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
         const int* mp = g.map + sd.dbase;
         const R* ps = psi + (size_t)NC * sd.dbase;
 
-        auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)t * sd.N + nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
-        R u[3];
-        flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
-
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
-            unsigned kd = k;
-            if (i != 0 && !bb) kd = (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])];
-            const int dir = bb ? L::opp[i] : i;
-#pragma unroll
-            for (int s = 0; s < NC; ++s) S::store(blk(fB, PF, s * Q + dir, kd), f[s][i], sh[s][i]);  // w_i = w_opp(i)
-        }
-
-        if (P.solute) {
-            solute_collide<LAT, R>(P, h, u);
-            S::store_plain(blk(hB, QS, 0, k), h[0]);
-            const bool seam_mode = (P.solute == 2);
-#pragma unroll
-            for (int d = 1; d < QS; ++d) {
-                const int dx = L::cx[d];
-                const bool seam = seam_mode && ((x == sd.nx - 1 && dx == 1) || (x == 0 && dx == -1));
-                if (!seam && !(lw & (1u << L::opp[d]))) {
-                    const unsigned kd = (unsigned)mp[nb.at(L::cx[d], L::cy[d], L::cz[d])];
-                    S::store_plain(blk(hB, QS, d, kd), h[d]);
-                    if (lw & (1u << (L::HOP_SHIFT + d))) {
-                        const R Cb = R(2) * h[d] * P.wet_inv_den;
-                        S::store_plain(blk(hB, QS, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
-                    }
-                    if (seam_mode && d == L::SXM && x == 1)
-                        S::store_plain(blk(hB, QS, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
-                }
-                if (seam_mode && d == L::SXM && x == sd.nx - 1) S::store_plain(blk(hB, QS, d, k), h[d]);
-            }
-        }
+        auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
+        auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
+        collide_push<LAT, ST, NC>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, fB, hA, hB);
     });
+}
+
+
+// ---------------------------------------------------------------------------
+// fused step for D3Q19: one workgroup per work item = (sample, x-y tile of
+// FTX x FTY nodes, FZS planes), marching in z.  For each plane z + 1 the
+// workgroup computes the pseudo-potentials and fluid indices of the tile plus
+// a one-node ring into LDS (three planes kept), then collides and pushes the
+// nodes of plane z with every neighbour's psi and destination index read from
+// LDS.  The density pass of the two-pass step disappears: ring nodes and the
+// first plane of each item are the only populations read twice.
+// ---------------------------------------------------------------------------
+template <int ST, int NC>
+__global__ void __launch_bounds__(FT_THREADS) k_fused(Phys<typename Store<ST>::R> P, Geo g, FusedItems fi,
+                                                      const typename Store<ST>::T* __restrict__ fA,
+                                                      typename Store<ST>::T* __restrict__ fB,
+                                                      const typename Store<ST>::T* __restrict__ hA,
+                                                      typename Store<ST>::T* __restrict__ hB) {
+    using L = Lat<1>;
+    using S = Store<ST>;
+    using R = typename S::R;
+    constexpr int Q = L::Q, PF = NC * Q;
+    constexpr int HX = FTX + 2, HP = (FTX + 2) * (FTY + 2);
+    __shared__ R s_psi[3][HP][NC];
+    __shared__ int s_map[3][HP];
+
+    int idx = blockIdx.x;
+    if (fi.work) {
+        if (idx >= ld_uniform(fi.nwork)) return;
+        idx = ld_uniform(fi.work + idx);
+    }
+    const int* ip = (const int*)(fi.items + idx);   // sample, x0, y0, z0
+    int4 it;
+    it.x = ld_uniform(ip + 0);
+    it.y = ld_uniform(ip + 1);
+    it.z = ld_uniform(ip + 2);
+    it.w = ld_uniform(ip + 3);
+    const int* q = (const int*)(g.smp + it.x);
+    const int nx = ld_uniform(q + 0), ny = ld_uniform(q + 1), nz = ld_uniform(q + 2), dbase = ld_uniform(q + 5);
+    const int* mp = g.map + dbase;
+    R sh[NC][Q];
+    load_shifts<1, ST, NC>(P, sh);
+
+    // pseudo-potential and fluid index of the tile + ring at plane zz (-1 <= zz <= nz) into slot
+    auto fill = [&](int zz, int slot) {
+        const int zw = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        for (int p = threadIdx.x; p < HP; p += FT_THREADS) {
+            const int hy = p / HX, hx = p - hy * HX;
+            int x = (it.y + hx - 1) % nx, y = (it.z + hy - 1) % ny;
+            x += x < 0 ? nx : 0;
+            y += y < 0 ? ny : 0;
+            const int kf = mp[x + nx * (y + ny * zw)];
+            s_map[slot][p] = kf;
+            R r[NC];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) r[s] = R(0);
+            if (kf >= 0) {
+#pragma unroll
+                for (int s = 0; s < NC; ++s) {
+                    R a = 0;
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) a += S::load(blk(fA, PF, s * Q + i, (unsigned)kf), sh[s][i]);
+                    r[s] = P.rho0 * (R(1) - exp_r<R>(-a * P.inv_rho0));
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NC; ++s) s_psi[slot][p][s] = r[s];
+        }
+    };
+
+    const int xl = threadIdx.x % FTX, yl = threadIdx.x / FTX;
+    const int x = it.y + xl, y = it.z + yl;
+    const bool inside = x < nx && y < ny;
+    const int ph = (yl + 1) * HX + xl + 1;
+    const int z1 = min(it.w + FZS, nz);
+    int sm = 0, s0 = 1, sp = 2;   // slots of planes z - 1, z, z + 1
+    fill(it.w - 1, sm);
+    fill(it.w, s0);
+    for (int z = it.w; z < z1; ++z) {
+        fill(z + 1, sp);
+        __syncthreads();
+        const int kf = inside ? s_map[s0][ph] : -1;
+        if (kf >= 0) {
+            const unsigned k = (unsigned)kf;
+            const uint32_t lw = g.links[k];
+            R f[NC][Q];
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
+            auto slot = [&](int cz) { return cz < 0 ? sm : (cz > 0 ? sp : s0); };
+            auto psi_nb = [&](int t, int i) -> R {
+                return s_psi[slot(L::cz[i])][ph + L::cy[i] * HX + L::cx[i]][t];
+            };
+            auto dest = [&](int i) -> unsigned { return (unsigned)s_map[slot(L::cz[i])][ph + L::cy[i] * HX + L::cx[i]]; };
+            collide_push<1, ST, NC>(P, sh, k, lw, x, nx, f, psi_nb, dest, fB, hA, hB);
+        }
+        __syncthreads();
+        const int t = sm;
+        sm = s0;
+        s0 = sp;
+        sp = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -339,7 +464,7 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
         }
         rho[s] = r;
     }
-    auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)t * sd.N + nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
+    auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
     flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
     C = 0;
     if (P.solute) {
@@ -559,8 +684,16 @@ static inline dim3 grid_for(const Ctx& c, int bs, bool persistent) {
 template <int LAT, int ST, int NC>
 static hipError_t step_t(const Ctx& c) {
     auto P = make_phys<SR<ST>>(c);
-    const int bs = c.block > 0 ? c.block : 256;
     const Geo g = make_geo(c, true);
+    if constexpr (LAT == 1) {
+        if (c.kernel == 1) {
+            const FusedItems fi{c.fitems, c.fwork, c.fnwork};
+            hipLaunchKernelGGL((k_fused<ST, NC>), dim3((unsigned)c.nfitems), dim3(FT_THREADS), 0, c.stream, P, g, fi,
+                               (const STT<ST>*)c.fA, (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB);
+            return hipGetLastError();
+        }
+    }
+    const int bs = c.block > 0 ? c.block : 256;
     const dim3 grid = grid_for(c, bs, true);
     hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);

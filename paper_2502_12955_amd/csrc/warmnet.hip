@@ -4,12 +4,14 @@
 //   forward  Y[v][o]  = sum_{k,i} X[v + off_k][i] W[o][k][i]      M = voxels, N = c_out, K = 27 c_in
 //   dgrad    dX[v][i] = sum_{k,o} dY[v - off_k][o] W[o][k][i]     M = voxels, N = c_in,  K = 27 c_out
 //   wgrad    dW[o][k][i] = sum_v dY[v][o] X[v + off_k][i]         M = c_out,  N = c_in,  K = voxels
-// with v_mfma_f32_16x16x16_bf16: per wavefront a 16x16 FP32 tile, operands of
-// 16x16 BF16 values.  Lane l (q = l / 16, r = l % 16) supplies A[r][4q..4q+3]
-// and B[4q..4q+3][r] and receives D[4q + j][r], j = 0..3.  Operands are FP32
-// tensors rounded to BF16 (nearest even) on load; accumulation stays FP32.
-// The weight gradient splits the voxel sum into fixed chunks whose partial
-// tiles are summed in chunk order by a second kernel (deterministic).
+// on v_mfma_f32_16x16x16_bf16 (a 16x16 FP32 tile from 16x16 BF16 operands;
+// lane l, q = l / 16, r = l % 16, supplies A[r][4q..4q+3] and B[4q..4q+3][r]
+// and receives D[4q + j][r], j = 0..3).  A workgroup computes a 64 x 64 output
+// tile; each K stage of the operands is rounded to BF16 (nearest even) once
+// and staged in LDS, and each of the four wavefronts runs 2 x 2 MFMA tiles on
+// it.  Accumulation stays FP32.  The weight gradient splits the voxel sum into
+// fixed chunks whose partial tiles are summed in chunk order by a second
+// kernel (deterministic).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -58,134 +60,8 @@ __device__ __forceinline__ void koff(int kk, int k, int& dz, int& dy, int& dx) {
     dz = kk / (k * k) - r;
 }
 
-// ---------------------------------------------------------------------------
-// forward: one wavefront per (16 voxels, 16 output channels) tile
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) conv_fwd(const float* __restrict__ X, Grid3 g, int V, int ci,
-                                                const float* __restrict__ W, const float* __restrict__ bias, int co,
-                                                int k, int relu, float* __restrict__ Y) {
-    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
-    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int nco = (co + 15) >> 4;
-    const int vt = tile / nco, ot = tile % nco;
-    if (vt * 16 >= V) return;
-    const int v0 = vt * 16, o0 = ot * 16;
-    const int K3 = k * k * k;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int va = v0 + r;   // voxel of this lane's A row
-    const int ob = o0 + r;   // output channel of this lane's B column
-    for (int kk = 0; kk < K3; ++kk) {
-        int dz, dy, dx;
-        koff(kk, k, dz, dy, dx);
-        const int vs = g.shift(va, dz, dy, dx);
-        for (int c0 = 0; c0 < ci; c0 += 16) {
-            bf16x4 a, b;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = c0 + 4 * q + j;
-                a[j] = to_bf16(c < ci ? X[(size_t)vs * ci + c] : 0.f);
-                b[j] = to_bf16((c < ci && ob < co) ? W[((size_t)ob * K3 + kk) * ci + c] : 0.f);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-        }
-    }
-    if (ob < co) {
-        const float bb = bias ? bias[ob] : 0.f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = v0 + 4 * q + j;
-            float y = acc[j] + bb;
-            if (relu) y = y > 0.f ? y : 0.f;
-            Y[(size_t)v * co + ob] = y;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// data gradient: one wavefront per (16 voxels, 16 input channels) tile
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) conv_dgrad(const float* __restrict__ dY, Grid3 g, int V, int co,
-                                                  const float* __restrict__ W, int ci, int k,
-                                                  float* __restrict__ dX) {
-    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
-    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int nci = (ci + 15) >> 4;
-    const int vt = tile / nci, it = tile % nci;
-    if (vt * 16 >= V) return;
-    const int v0 = vt * 16, i0 = it * 16;
-    const int K3 = k * k * k;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int va = v0 + r;
-    const int ib = i0 + r;
-    for (int kk = 0; kk < K3; ++kk) {
-        int dz, dy, dx;
-        koff(kk, k, dz, dy, dx);
-        const int vs = g.shift(va, -dz, -dy, -dx);
-        for (int c0 = 0; c0 < co; c0 += 16) {
-            bf16x4 a, b;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = c0 + 4 * q + j;
-                a[j] = to_bf16(o < co ? dY[(size_t)vs * co + o] : 0.f);
-                b[j] = to_bf16((o < co && ib < ci) ? W[((size_t)o * K3 + kk) * ci + ib] : 0.f);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-        }
-    }
-    if (ib < ci) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dX[(size_t)(v0 + 4 * q + j) * ci + ib] = acc[j];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// weight gradient: one wavefront per (16 out ch, 16 in ch, offset, voxel chunk)
-// tile; partial[chunk][o][kk][i]
-// ---------------------------------------------------------------------------
+// weight gradients split the voxel sum into chunks of this many voxels
 constexpr int WG_CHUNK = 4096;
-
-__global__ void __launch_bounds__(256) conv_wgrad_part(const float* __restrict__ X, const float* __restrict__ dY,
-                                                       Grid3 g, int V, int ci, int co, int k,
-                                                       float* __restrict__ part) {
-    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
-    const int K3 = k * k * k;
-    const int nco = (co + 15) >> 4, nci = (ci + 15) >> 4;
-    const int nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
-    const long long tile = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const long long ntile = (long long)nco * nci * K3 * nchunk;
-    if (tile >= ntile) return;
-    long long t = tile;
-    const int ot = (int)(t % nco);
-    t /= nco;
-    const int it = (int)(t % nci);
-    t /= nci;
-    const int kk = (int)(t % K3);
-    const int ch = (int)(t / K3);
-    int dz, dy, dx;
-    koff(kk, k, dz, dy, dx);
-    const int o0 = ot * 16, i0 = it * 16;
-    const int vend = min(V, (ch + 1) * WG_CHUNK);
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int oa = o0 + r, ib = i0 + r;
-    for (int v0 = ch * WG_CHUNK; v0 < vend; v0 += 16) {
-        bf16x4 a, b;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = v0 + 4 * q + j;
-            a[j] = to_bf16(oa < co ? dY[(size_t)v * co + oa] : 0.f);
-            const int vs = g.shift(v, dz, dy, dx);
-            b[j] = to_bf16(ib < ci ? X[(size_t)vs * ci + ib] : 0.f);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    if (ib < ci) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int o = o0 + 4 * q + j;
-            if (o < co) part[(((size_t)ch * co + o) * K3 + kk) * ci + ib] = acc[j];
-        }
-    }
-}
 
 __global__ void __launch_bounds__(256) sum_chunks(const float* __restrict__ part, int nchunk, long long n,
                                                   float* __restrict__ out) {
@@ -194,6 +70,212 @@ __global__ void __launch_bounds__(256) sum_chunks(const float* __restrict__ part
     float s = 0.f;
     for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
     out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled implicit GEMMs (the paths the entry points use).  A workgroup of
+// four wavefronts computes a 64 x 64 output tile; per K stage the operands
+// (TK wide) are rounded to BF16 once, staged in LDS, and each wavefront runs
+// 2 x 2 MFMA 16x16x16 tiles on them (32 x 32 outputs per wavefront).
+// LDS rows are padded by 8 BF16 values against bank conflicts.
+// ---------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64;
+
+template <int TK>
+struct Tiles {
+    static constexpr int LD = TK + 8;
+    short a[TM][LD];
+    short b[TN][LD];
+};
+
+// the 2 x 2 MFMA tiles of wavefront `wave` on one staged K chunk
+template <int TK>
+__device__ __forceinline__ void mma_stage(const Tiles<TK>& t, int wave, int q, int r, floatx4 (&acc)[2][2]) {
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 16) {
+        bf16x4 af[2], bfr[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = *(const bf16x4*)&t.a[wm + i * 16 + r][ks + 4 * q];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bfr[j] = *(const bf16x4*)&t.b[wn + j * 16 + r][ks + 4 * q];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// forward: M = voxels, N = c_out, K = (offset, c_in)
+template <int TK>
+__global__ void __launch_bounds__(256) conv_fwd_t(const float* __restrict__ X, Grid3 g, int V, int ci,
+                                                  const float* __restrict__ W, const float* __restrict__ bias, int co,
+                                                  int k, int relu, float* __restrict__ Y) {
+    __shared__ Tiles<TK> t;
+    constexpr int PER = TK / 4;   // values staged per thread and row (64 rows x TK = 256 threads x PER)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
+    const int ntn = (co + TN - 1) / TN;
+    const int m0 = (blockIdx.x / ntn) * TM, n0 = (blockIdx.x % ntn) * TN;
+    const int K3 = k * k * k;
+    const int srow = tid >> 2, scol = (tid & 3) * PER;
+    const int sv = m0 + srow, so = n0 + srow;
+    floatx4 acc[2][2] = {};
+    for (int kk = 0; kk < K3; ++kk) {
+        int dz, dy, dx;
+        koff(kk, k, dz, dy, dx);
+        const int vs = sv < V ? g.shift(sv, dz, dy, dx) : 0;
+        for (int c0 = 0; c0 < ci; c0 += TK) {
+            short av[PER], bv[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int c = c0 + scol + j;
+                av[j] = to_bf16((sv < V && c < ci) ? X[(size_t)vs * ci + c] : 0.f);
+                bv[j] = to_bf16((so < co && c < ci) ? W[((size_t)so * K3 + kk) * ci + c] : 0.f);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                t.a[srow][scol + j] = av[j];
+                t.b[srow][scol + j] = bv[j];
+            }
+            __syncthreads();
+            mma_stage<TK>(t, wave, q, r, acc);
+        }
+    }
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int o = n0 + wn + j * 16 + r;
+        if (o >= co) continue;
+        const float bb = bias ? bias[o] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = m0 + wm + i * 16 + 4 * q + e;
+                if (v >= V) continue;
+                float y = acc[i][j][e] + bb;
+                if (relu) y = y > 0.f ? y : 0.f;
+                Y[(size_t)v * co + o] = y;
+            }
+    }
+}
+
+// data gradient: M = voxels, N = c_in, K = (offset, c_out)
+template <int TK>
+__global__ void __launch_bounds__(256) conv_dgrad_t(const float* __restrict__ dY, Grid3 g, int V, int co,
+                                                    const float* __restrict__ W, int ci, int k,
+                                                    float* __restrict__ dX) {
+    __shared__ Tiles<TK> t;
+    constexpr int PER = TK / 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
+    const int ntn = (ci + TN - 1) / TN;
+    const int m0 = (blockIdx.x / ntn) * TM, n0 = (blockIdx.x % ntn) * TN;
+    const int K3 = k * k * k;
+    const int srow = tid >> 2, scol = (tid & 3) * PER;   // A staging: voxel row, c_out columns
+    const int sv = m0 + srow;
+    // B staging: TK c_out rows of W (contiguous in c_in) -> t.b[c_in][c_out]
+    constexpr int BPER = TN * TK / 256;                   // c_in values per thread
+    const int bo = tid / (TN / BPER), bi = (tid % (TN / BPER)) * BPER;
+    floatx4 acc[2][2] = {};
+    for (int kk = 0; kk < K3; ++kk) {
+        int dz, dy, dx;
+        koff(kk, k, dz, dy, dx);
+        const int vs = sv < V ? g.shift(sv, -dz, -dy, -dx) : 0;
+        for (int c0 = 0; c0 < co; c0 += TK) {
+            short av[PER], bv[BPER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int o = c0 + scol + j;
+                av[j] = to_bf16((sv < V && o < co) ? dY[(size_t)vs * co + o] : 0.f);
+            }
+            const int o = c0 + bo;
+#pragma unroll
+            for (int j = 0; j < BPER; ++j) {
+                const int i = n0 + bi + j;
+                bv[j] = to_bf16((o < co && i < ci) ? W[((size_t)o * K3 + kk) * ci + i] : 0.f);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER; ++j) t.a[srow][scol + j] = av[j];
+#pragma unroll
+            for (int j = 0; j < BPER; ++j) t.b[bi + j][bo] = bv[j];
+            __syncthreads();
+            mma_stage<TK>(t, wave, q, r, acc);
+        }
+    }
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = n0 + wn + j * 16 + r;
+        if (i >= ci) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = m0 + wm + a * 16 + 4 * q + e;
+                if (v < V) dX[(size_t)v * ci + i] = acc[a][j][e];
+            }
+    }
+}
+
+// weight gradient: M = c_out, N = c_in, K = voxels of one chunk; one offset per
+// workgroup; partial[chunk][o][kk][i]
+__global__ void __launch_bounds__(256) conv_wgrad_t(const float* __restrict__ X, const float* __restrict__ dY,
+                                                    Grid3 g, int V, int ci, int co, int k,
+                                                    float* __restrict__ part) {
+    constexpr int TK = 32;
+    __shared__ Tiles<TK> t;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
+    const int K3 = k * k * k;
+    const int nmt = (co + TM - 1) / TM, nnt = (ci + TN - 1) / TN;
+    int b = blockIdx.x;
+    const int mt = b % nmt;
+    b /= nmt;
+    const int nt = b % nnt;
+    b /= nnt;
+    const int kk = b % K3;
+    const int ch = b / K3;
+    const int m0 = mt * TM, n0 = nt * TN;
+    int dz, dy, dx;
+    koff(kk, k, dz, dy, dx);
+    // staging: voxel row tid / 8 (32 voxels per stage), 8 channels at (tid % 8) * 8, written transposed
+    const int sv = tid >> 3, sc = (tid & 7) * 8;
+    const int vbeg = ch * WG_CHUNK, vend = min(V, vbeg + WG_CHUNK);
+    floatx4 acc[2][2] = {};
+    for (int v0 = vbeg; v0 < vend; v0 += TK) {
+        const int v = v0 + sv;
+        const bool ok = v < vend;
+        const int vs = ok ? g.shift(v, dz, dy, dx) : 0;
+        short av[8], bv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int o = m0 + sc + j, i = n0 + sc + j;
+            av[j] = to_bf16((ok && o < co) ? dY[(size_t)v * co + o] : 0.f);
+            bv[j] = to_bf16((ok && i < ci) ? X[(size_t)vs * ci + i] : 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            t.a[sc + j][sv] = av[j];
+            t.b[sc + j][sv] = bv[j];
+        }
+        __syncthreads();
+        mma_stage<TK>(t, wave, q, r, acc);
+    }
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = n0 + wn + j * 16 + r;
+        if (i >= ci) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = m0 + wm + a * 16 + 4 * q + e;
+                if (o < co) part[(((size_t)ch * co + o) * K3 + kk) * ci + i] = acc[a][j][e];
+            }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -408,9 +490,13 @@ int wn_conv3d_fwd(const float* x, int n, int d, int h, int w, int ci, const floa
     if (!x || !W || !y || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || co < 1)
         return err(-1, "wn_conv3d_fwd: bad arguments");
     const int V = n * d * h * w;
-    const long long tiles = (long long)(V / 16) * ((co + 15) / 16);
-    hipLaunchKernelGGL(conv_fwd, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, (hipStream_t)stream, x,
-                       Grid3{n, d, h, w}, V, ci, W, b, co, k, relu, y);
+    const unsigned blocks = (unsigned)(((V + TM - 1) / TM) * ((co + TN - 1) / TN));
+    if (ci <= 16)
+        hipLaunchKernelGGL(conv_fwd_t<16>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, x, Grid3{n, d, h, w}, V,
+                           ci, W, b, co, k, relu, y);
+    else
+        hipLaunchKernelGGL(conv_fwd_t<32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, x, Grid3{n, d, h, w}, V,
+                           ci, W, b, co, k, relu, y);
     return hip_result("conv_fwd");
 }
 
@@ -419,9 +505,13 @@ int wn_conv3d_dgrad(const float* dy, int n, int d, int h, int w, int co, const f
     if (!dy || !W || !dx || (k != 1 && k != 3) || !shape_ok(n, d, h, w, co) || ci < 1)
         return err(-1, "wn_conv3d_dgrad: bad arguments");
     const int V = n * d * h * w;
-    const long long tiles = (long long)(V / 16) * ((ci + 15) / 16);
-    hipLaunchKernelGGL(conv_dgrad, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, (hipStream_t)stream, dy,
-                       Grid3{n, d, h, w}, V, co, W, ci, k, dx);
+    const unsigned blocks = (unsigned)(((V + TM - 1) / TM) * ((ci + TN - 1) / TN));
+    if (co <= 16)
+        hipLaunchKernelGGL(conv_dgrad_t<16>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, dy, Grid3{n, d, h, w},
+                           V, co, W, ci, k, dx);
+    else
+        hipLaunchKernelGGL(conv_dgrad_t<32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, dy, Grid3{n, d, h, w},
+                           V, co, W, ci, k, dx);
     return hip_result("conv_dgrad");
 }
 
@@ -440,8 +530,8 @@ int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w,
     const int V = n * d * h * w;
     const int K3 = k * k * k;
     const int nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
-    const long long tiles = (long long)((co + 15) / 16) * ((ci + 15) / 16) * K3 * nchunk;
-    hipLaunchKernelGGL(conv_wgrad_part, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, (hipStream_t)stream, x, dy,
+    const long long blocks = (long long)((co + TM - 1) / TM) * ((ci + TN - 1) / TN) * K3 * nchunk;
+    hipLaunchKernelGGL(conv_wgrad_t, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, x, dy,
                        Grid3{n, d, h, w}, V, ci, co, k, (float*)workspace);
     const long long nw = (long long)co * K3 * ci;
     hipLaunchKernelGGL(sum_chunks, blocks_for(nw), dim3(256), 0, (hipStream_t)stream, (const float*)workspace,

@@ -82,7 +82,7 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
-           "mclbm_synchronize", "mclbm_autotune", "mclbm_destroy", "mclbm_last_error")
+           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_kernel", "mclbm_destroy", "mclbm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -115,8 +115,9 @@ def load(path: str = LIB_PATH):
     lib.mclbm_get_sample_monitors.argtypes = [vp, i32, vp]
     lib.mclbm_get_step.argtypes = [vp, ct.POINTER(i64)]
     lib.mclbm_synchronize.argtypes = [vp]
-    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp, i32,
-                                   ct.POINTER(i32)]
+    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp,
+                                   i32, ct.POINTER(i32)]
+    lib.mclbm_set_kernel.argtypes = [vp, i32]
     lib.mclbm_destroy.argtypes = [vp]
     lib.mclbm_destroy.restype = None
     lib.mclbm_last_error.argtypes = [vp]
@@ -229,9 +230,13 @@ def set_populations(h, src, raw=False):
     _check(load().mclbm_set_populations(h, _ptr(a), int(bool(raw))), h)
 
 
-def run_to_residual(h, tol: float, max_steps: int):
+def run_to_residual(h, tol: float, max_steps: int, allow_diverged=False):
+    """Returns (every sample converged, steps taken).  With allow_diverged, a
+    batch in which some sample went non-finite returns (False, steps) instead
+    of raising; the sample monitors say which (out[13] >= 0)."""
     n = ct.c_int64()
-    rc = _check(load().mclbm_run_to_residual(h, float(tol), int(max_steps), ct.byref(n)), h, (OK, 1))
+    allow = (OK, 1, EDIVERGED) if allow_diverged else (OK, 1)
+    rc = _check(load().mclbm_run_to_residual(h, float(tol), int(max_steps), ct.byref(n)), h, allow)
     return rc == OK, n.value
 
 
@@ -239,14 +244,22 @@ def set_launch(h, block_threads=256, grid_blocks=0):
     _check(load().mclbm_set_launch(h, int(block_threads), int(grid_blocks)), h)
 
 
+KERNEL = {"two_pass": 0, "fused": 1}
+
+
+def set_kernel(h, kernel="two_pass"):
+    _check(load().mclbm_set_kernel(h, KERNEL[kernel] if isinstance(kernel, str) else int(kernel)), h)
+
+
 def autotune(h, trial_steps=20):
-    """Native launch-shape tuner; returns (block, grid, ms_per_step, table rows)."""
-    b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    """Native step-kernel tuner; returns (kernel, block, grid, ms_per_step, table rows
+    (kernel, block, grid, ms))."""
+    k, b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
     ms = ct.c_double()
-    table = np.zeros((64, 3))
-    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(b), ct.byref(g), ct.byref(ms), _ptr(table), 64,
-                                 ct.byref(n)), h)
-    return b.value, g.value, ms.value, table[: n.value].tolist()
+    table = np.zeros((64, 4))
+    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(k), ct.byref(b), ct.byref(g), ct.byref(ms),
+                                 _ptr(table), 64, ct.byref(n)), h)
+    return k.value, b.value, g.value, ms.value, table[: n.value].tolist()
 
 
 def tune_key(plist):
@@ -358,8 +371,8 @@ class Lattice:
     def set_populations(self, src, raw=False):
         set_populations(self.h, src, raw)
 
-    def run_to_residual(self, tol, max_steps):
-        return run_to_residual(self.h, tol, max_steps)
+    def run_to_residual(self, tol, max_steps, allow_diverged=False):
+        return run_to_residual(self.h, tol, max_steps, allow_diverged)
 
     def set_launch(self, block_threads=256, grid_blocks=0):
         set_launch(self.h, block_threads, grid_blocks)
@@ -367,12 +380,15 @@ class Lattice:
     def set_graph(self, enable=True):
         set_graph(self.h, enable)
 
+    def set_kernel(self, kernel="two_pass"):
+        set_kernel(self.h, kernel)
+
     def autotune(self, trial_steps=20, cache_path=None):
-        """Choose the launch shape (after set_geometry; init_fields must follow).
+        """Choose the step kernel and launch shape (after set_geometry; init_fields must follow).
 
         With ``cache_path`` (a JSON file), a shape already chosen for the same
         physics and size class is reused without timing, and new choices are
-        added to the file.  Returns (block, grid, ms_per_step or None if cached)."""
+        added to the file.  Returns (kernel, block, grid, ms_per_step or None if cached)."""
         import json
 
         key = tune_key(getattr(self, "plist", [self.params]))
@@ -381,15 +397,17 @@ class Lattice:
             with open(cache_path) as f:
                 cache = json.load(f)
         if key in cache:
-            b, g = cache[key]["block"], cache[key]["grid"]
-            self.set_launch(b, g)
-            return b, g, None
-        b, g, ms, table = autotune(self.h, trial_steps)
+            k, b, g = cache[key]["kernel"], cache[key]["block"], cache[key]["grid"]
+            self.set_kernel(k)
+            if k == KERNEL["two_pass"]:
+                self.set_launch(b, g)
+            return k, b, g, None
+        k, b, g, ms, table = autotune(self.h, trial_steps)
         if cache_path:
-            cache[key] = dict(block=b, grid=g, ms_per_step=ms, table=table)
+            cache[key] = dict(kernel=k, block=b, grid=g, ms_per_step=ms, table=table)
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)
-        return b, g, ms
+        return k, b, g, ms
 
     @property
     def step_count(self):

@@ -323,3 +323,53 @@ class UNet:
         for l in self.layers():
             for p, g, m, v in l.params():
                 adam(p, g, m, v, lr, self.step_count)
+
+
+def conv_flops(net, shape, batch=1):
+    """Multiply-add flops (x2) of one forward pass over ``batch`` samples of ``shape`` (d, h, w)."""
+    V = int(np.prod(shape)) * batch
+    total = 0.0
+    for lvl, (a, b) in enumerate(net.enc):
+        total += 2.0 * (V // 8 ** lvl) * 27 * (a.ci * a.co + b.ci * b.co)
+    L = len(net.widths)
+    for j, (a, b) in enumerate(net.dec):
+        lvl = L - 2 - j
+        total += 2.0 * (V // 8 ** lvl) * 27 * (a.ci * a.co + b.ci * b.co)
+    total += 2.0 * V * net.head.ci * net.head.co
+    return total
+
+
+def bench(n=64, batch=2, iters=20, widths=(16, 32, 64, 128)):
+    """Training-step throughput on random inputs: forward, MSE, backward, Adam."""
+    import time
+
+    import torch
+
+    net = UNet(cin=2, cout=4, widths=widths, seed=0)
+    rng = np.random.default_rng(0)
+    x = torch.tensor(rng.standard_normal((batch, n, n, n, 2)), dtype=torch.float32, device="cuda:0")
+    t = torch.tensor(rng.standard_normal((batch, n, n, n, 4)), dtype=torch.float32, device="cuda:0")
+    for _ in range(2):
+        y, acts = net.forward(x)
+        _, g = mse(y, t)
+        net.backward(g, acts)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        y, acts = net.forward(x)
+        _, g = mse(y, t)
+        net.backward(g, acts)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    fl = 3.0 * conv_flops(net, (n, n, n), batch)
+    return dict(n=n, batch=batch, ms_per_iter=dt * 1e3, conv_tflop_per_iter=fl / 1e12, tflops=fl / dt / 1e12,
+                params=net.n_params())
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+
+    print(json.dumps(bench(n=int(sys.argv[1]) if len(sys.argv) > 1 else 64)))

@@ -52,7 +52,8 @@ def make_samples(n, count, first, config=5, radius=8, blob_radius=6, saturation=
 def solve(samples, tol, max_steps, storage="f32", init=None):
     """Run a batch to tolerance.  ``init``: optional list of (rho, u) per sample
     (default: rest with the seeded phases).  Returns per-sample steps (-1: not
-    converged within max_steps), the final fields and the wall time."""
+    converged within max_steps), per-sample divergence flags, the final fields
+    and the wall time."""
     plist = [dict(s["params"], storage=storage) for s in samples]
     b = mclbm.Batch(plist)
     b.set_graph(True)
@@ -63,13 +64,14 @@ def solve(samples, tol, max_steps, storage="f32", init=None):
         b.init_fields([r for r, _ in init], [u for _, u in init])
     b.synchronize()
     t0 = time.perf_counter()
-    ok, steps = b.run_to_residual(tol, max_steps)
+    ok, steps = b.run_to_residual(tol, max_steps, allow_diverged=True)
     b.synchronize()
     wall = time.perf_counter() - t0
-    per = [int(b.sample_monitors(i)[11]) if b.sample_monitors(i)[12] else -1 for i in range(len(samples))]
+    mons = [b.sample_monitors(i) for i in range(len(samples))]
     rhos, us, _ = b.moments()
     b.close()
-    return dict(converged=ok, steps=per, total_steps=steps, wall=wall, rho=rhos, u=us)
+    return dict(converged=ok, steps=[int(m[11]) for m in mons], diverged=[bool(m[13] >= 0) for m in mons],
+                total_steps=steps, wall=wall, rho=rhos, u=us)
 
 
 def features(mask, rho):
@@ -127,22 +129,6 @@ class Trainer:
         return float(torch.stack(losses).mean().item())
 
 
-def conv_flops(net, shape):
-    """Multiply-add flops (x2) of one forward pass on one sample of ``shape`` (d, h, w)."""
-    V = int(np.prod(shape))
-    total = 0.0
-    L = len(net.widths)
-    for lvl, (a, b) in enumerate(net.enc):
-        v = V // 8 ** lvl
-        total += 2.0 * v * 27 * (a.ci * a.co + b.ci * b.co)
-    for j, (a, b) in enumerate(net.dec):
-        lvl = L - 2 - j
-        v = V // 8 ** lvl
-        total += 2.0 * v * 27 * (a.ci * a.co + b.ci * b.co)
-    total += 2.0 * V * net.head.ci * net.head.co
-    return total
-
-
 def run(args):
     import torch
 
@@ -155,12 +141,13 @@ def run(args):
     shape = (args.n,) * 3
 
     def solve_all(samples, init=None):
-        out = dict(steps=[], wall=0.0, rho=[], u=[])
+        out = dict(steps=[], diverged=[], wall=0.0, rho=[], u=[])
         for i in range(0, len(samples), args.batch_solve):
             part = samples[i: i + args.batch_solve]
             r = solve(part, args.tol, args.max_steps, args.storage,
                       None if init is None else init[i: i + args.batch_solve])
             out["steps"] += r["steps"]
+            out["diverged"] += r["diverged"]
             out["wall"] += r["wall"]
             out["rho"] += r["rho"]
             out["u"] += r["u"]
@@ -169,10 +156,12 @@ def run(args):
         return out
 
     gen = solve_all(train_s)
-    rep["train_steps_mean"] = float(np.mean(gen["steps"]))
-    rep["train_solve_wall_s"] = gen["wall"]
-    X = np.stack([features(s["mask"], s["rho"].reshape((2,) + shape)) for s in train_s])
-    T = np.stack([targets(r, u, shape, scale) for r, u in zip(gen["rho"], gen["u"])])
+    keep = [i for i, d in enumerate(gen["diverged"]) if not d]
+    conv = [gen["steps"][i] for i in keep if gen["steps"][i] > 0]
+    rep.update(train_converged=len(conv), train_diverged=len(train_s) - len(keep),
+               train_steps_mean=float(np.mean(conv)) if conv else None, train_solve_wall_s=gen["wall"])
+    X = np.stack([features(train_s[i]["mask"], train_s[i]["rho"].reshape((2,) + shape)) for i in keep])
+    T = np.stack([targets(gen["rho"][i], gen["u"][i], shape, scale) for i in keep])
     var_u = float(np.mean(T[..., :3] ** 2))
     var_p = float(np.mean(T[..., 3] ** 2))
     wt = [var_p / max(var_u, 1e-30)] * 3 + [1.0]
@@ -190,8 +179,8 @@ def run(args):
         print(f"[warmstart] epoch {ep} loss {hist[-1]:.4e}", flush=True)
     torch.cuda.synchronize()
     train_wall = time.perf_counter() - t0
-    it = args.epochs * (args.train // args.batch) * args.batch
-    fl = 3.0 * conv_flops(net, shape) * it
+    it = args.epochs * (len(keep) // args.batch) * args.batch
+    fl = 3.0 * warmnet.conv_flops(net, shape) * it
     rep.update(params=net.n_params(), loss_history=hist, train_wall_s=train_wall,
                train_tflops=fl / train_wall / 1e12)
 
@@ -209,6 +198,8 @@ def run(args):
     infer = time.perf_counter() - t0
     warm = solve_all(test_s, init)
     ratio = [w / c for w, c in zip(warm["steps"], cold["steps"]) if w > 0 and c > 0]
+    rep.update(cold_converged=sum(c > 0 for c in cold["steps"]), warm_converged=sum(w > 0 for w in warm["steps"]),
+               cold_diverged=sum(cold["diverged"]), warm_diverged=sum(warm["diverged"]))
     dphi, du = [], []
     for rc, rw, uc, uw in zip(cold["rho"], warm["rho"], cold["u"], warm["u"]):
         pc = targets(rc, uc, shape, scale)

@@ -29,8 +29,10 @@ def _samples(n=4, seed=0, storage="f32", k_wall=0.02):
     return cases
 
 
-def _batch(cases, **launch):
+def _batch(cases, kernel=None, **launch):
     b = mclbm.Batch([c[0] for c in cases])
+    if kernel:
+        b.set_kernel(kernel)
     if launch:
         b.set_launch(**launch)
     b.set_geometry([c[1] for c in cases])
@@ -73,13 +75,18 @@ def test_persistent_grid_and_block_sizes_bit_identical():
         b.step(20)
         assert np.array_equal(b.populations(raw=True), want), launch
         b.close()
+    b = _batch(cases, kernel="fused")
+    b.step(20)
+    assert np.array_equal(b.populations(raw=True), want), "fused"
+    b.close()
 
 
-def test_graph_replay_matches_eager_steps():
+@pytest.mark.parametrize("kernel", ["two_pass", "fused"])
+def test_graph_replay_matches_eager_steps(kernel):
     """Replays interleaved with eager steps and host reads; each compared bitwise."""
     cases = _samples(3, seed=11)
     eager = _batch(cases)
-    graph = _batch(cases)
+    graph = _batch(cases, kernel=kernel)
     graph.set_graph(True)
     for rep in range(4):
         eager.step(10)
@@ -98,7 +105,8 @@ def test_graph_replay_matches_eager_steps():
     graph.close()
 
 
-def test_run_to_residual_freezes_each_sample():
+@pytest.mark.parametrize("kernel", ["two_pass", "fused"])
+def test_run_to_residual_freezes_each_sample(kernel):
     """Samples stop at their own convergence step; the batch result equals each
     sample run alone to the same tolerance.  FP64 storage: at this flow speed
     (|u| ~ 1e-4) FP32 round-off alone keeps the relative velocity change near
@@ -109,7 +117,8 @@ def test_run_to_residual_freezes_each_sample():
                  accel=(1e-5, 0.0, 0.0))
     cases = [(p, m, r[:1] * 0 + 1.0, C) for p, m, r, C in cases]
     tol = 1e-5
-    b = _batch(cases)
+    b = _batch(cases, kernel=kernel)
+    b.set_graph(True)
     ok, steps = b.run_to_residual(tol, 20000)
     assert ok
     conv = [int(b.sample_monitors(s)[11]) for s in range(3)]
@@ -128,9 +137,10 @@ def test_run_to_residual_freezes_each_sample():
     b.close()
 
 
-def test_batch_fp64_matches_oracle_per_sample():
+@pytest.mark.parametrize("kernel", ["two_pass", "fused"])
+def test_batch_fp64_matches_oracle_per_sample(kernel):
     cases = _samples(2, seed=31, storage="f64")
-    b = _batch(cases)
+    b = _batch(cases, kernel=kernel)
     b.step(15)
     rhos, us, Cs = b.moments()
     for s, (p, mask, rho, C) in enumerate(cases):
@@ -149,8 +159,8 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     b = mclbm.Batch([c[0] for c in cases])
     b.set_geometry([c[1] for c in cases])
     cache = str(tmp_path / "tune.json")
-    blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
-    assert blk in (64, 128, 256) and grid % 8 == 0 and ms > 0
+    kern, blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
+    assert kern in (0, 1) and blk in (64, 128, 256, 512) and grid % 8 == 0 and ms > 0
     with pytest.raises(mclbm.MclbmError) as e:      # populations were overwritten
         b.step(1)
     assert e.value.code == mclbm.ESTATE
@@ -162,6 +172,51 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     # a second handle of the same class takes the cached shape without timing
     b2 = mclbm.Batch([c[0] for c in cases])
     b2.set_geometry([c[1] for c in cases])
-    assert b2.autotune(trial_steps=4, cache_path=cache) == (blk, grid, None)
+    assert b2.autotune(trial_steps=4, cache_path=cache) == (kern, blk, grid, None)
     for x in (b, b2, ref):
         x.close()
+
+
+def test_a_diverged_sample_is_frozen_and_the_others_finish():
+    """A NaN planted in one sample's populations (from the host) freezes that
+    sample as diverged at the next monitor; the other samples run on to their
+    own convergence, bit-identical to running them alone."""
+    cases = _samples(3, seed=21, k_wall=0.0, storage="f64")
+    for p, *_ in cases:
+        p.update(ncomp=1, G=((0, 0), (0, 0)), G_ads=(0, 0), solute="off", monitor_every=20,
+                 accel=(1e-5, 0.0, 0.0))
+    cases = [(p, m, r[:1] * 0 + 1.0, C) for p, m, r, C in cases]
+    b = _batch(cases)
+    gmask, _, _ = b.get_geometry()
+    n0 = b.sizes[0]
+    n1 = int(np.flatnonzero(gmask[n0: n0 + b.sizes[1]] == 0)[0])   # a fluid node of sample 1
+    pops = b.populations(raw=True)                   # [sample][plane][box node]
+    pops[19 * n0 + n1] = np.nan                      # plane 0 of that node
+    b.set_populations(pops, raw=True)
+    ok, steps = b.run_to_residual(1e-5, 20000, allow_diverged=True)
+    assert not ok
+    mons = [b.sample_monitors(s) for s in range(3)]
+    assert mons[1][13] == 20 and mons[1][11] == -1
+    for s in (0, 2):
+        assert mons[s][13] == -1 and mons[s][11] > 0
+    with pytest.raises(mclbm.MclbmError) as e:
+        b2 = _batch(cases)
+        b2.set_populations(pops, raw=True)
+        try:
+            b2.run_to_residual(1e-5, 20000)
+        finally:
+            b2.close()
+    assert e.value.code == mclbm.EDIVERGED
+    out = b.populations(raw=True)
+    sizes = []
+    for s in (0, 2):
+        p, mask, rho, C = cases[s]
+        lat = gpu_lattice(p, mask, rho)
+        ok1, st1 = lat.run_to_residual(1e-5, 20000)
+        assert ok1 and st1 == mons[s][11]
+        ref = lat.populations(raw=True)
+        sizes.append(ref.size)
+        off = 0 if s == 0 else out.size - ref.size
+        assert np.array_equal(out[off: off + ref.size], ref)
+        lat.close()
+    b.close()
