@@ -79,6 +79,7 @@ def main():
                     help="step kernel (auto: the native tuner picks kernel and launch shape)")
     ap.add_argument("--block", type=int, default=256, help="threads per workgroup of the two-pass kernels")
     ap.add_argument("--grid", type=int, default=0, help="persistent grid blocks of the two-pass kernels (0: one pass)")
+    ap.add_argument("--slab", type=int, default=0, help="z-slab sweep planes of the two-pass kernels (0: off)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -104,15 +105,16 @@ def main():
     lat = mclbm.Lattice(p)
     nrc = lat.set_geometry(mask)
     if args.kernel == "auto":
-        kern, blk, grd, ms = lat.autotune(trial_steps=10)
+        kern, blk, grd, slab, ms = lat.autotune(trial_steps=10)
         kname = {0: "two_pass", 1: "fused"}[kern]
-        log(f"[bench] autotuned: kernel {kname}, block {blk}, grid {grd} ({ms:.3f} ms/step)")
+        log(f"[bench] autotuned: kernel {kname}, block {blk}, grid {grd}, slab {slab} ({ms:.3f} ms/step)")
     else:
-        kname, blk, grd = args.kernel, args.block, args.grid
+        kname, blk, grd, slab = args.kernel, args.block, args.grid, args.slab
         lat.set_kernel(kname)
         lat.set_launch(args.block, args.grid)
+        lat.set_sweep(args.slab)
         if kname == "fused":
-            blk, grd = 512, 0
+            blk, grd, slab = 512, 0, 0
     gmask, _, _ = lat.get_geometry()
     nfluid = int((gmask == 0).sum())
     lat.init_fields(rho, None, C)
@@ -168,7 +170,7 @@ def main():
                                f"Boolean sphere pack porosity 0.4 R=8, Guo forcing, body force x 1e-5, "
                                f"wall reaction k=1e-3, inlet/outlet solute",
                    "nodes": N, "fluid_nodes": nfluid, "storage": args.storage,
-                   "launch": {"kernel": kname, "block": blk, "grid": grd},
+                   "launch": {"kernel": kname, "block": blk, "grid": grd, "slab_planes": slab},
                    "mflups": round(nfluid / (ms_per_step * 1e-3) / 1e6, 1),
                    "monitor_every": p["monitor_every"], "final_residual": float(mon[9])},
         "roofline": roofline,

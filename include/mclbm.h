@@ -193,22 +193,33 @@ int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks
  * kind or the fused kernel on D2Q9. */
 int mclbm_set_kernel(mclbm_handle* h, int32_t kernel);
 
+/* Sweep order of the two-pass kernels: slab_planes = 0 (default) runs each
+ * pass over the whole lattice; slab_planes >= 2 splits a single D3Q19 lattice
+ * into z-slabs of that many planes (the last takes the remainder) and runs the
+ * density pass one slab ahead of the collide pass, so the collide pass reads
+ * populations the density pass has just read.  Results are bit-identical.
+ * EINVAL for a batch of several samples or for D2Q9. */
+int mclbm_set_sweep(mclbm_handle* h, int32_t slab_planes);
+
 /* Time the step kernels over a set of candidates and keep the fastest.
  * Candidates: the two-pass kernels with block_threads 64, 128, 256 crossed
  * with grid_blocks 0 (one pass) and persistent grids of 8, 16 and 32
- * wavefronts per compute unit, and (D3Q19) the fused kernel.  Each runs 2
- * untimed steps, then trial_steps (>= 1) steps timed with HIP events on the
- * handle's stream.  Needs set_geometry; it overwrites the populations
- * (uniform rest state, density 1), so init_fields must be called afterwards
- * (ESTATE until then).  The choice is applied as by mclbm_set_kernel and
- * mclbm_set_launch and returned in *kernel, *block_threads, *grid_blocks and
- * *ms_per_step (any may be NULL; for the fused kernel block and grid are its
- * fixed 512 threads and one workgroup per work item).  The candidates' timings
- * are written to table[4 * i + 0..3] = (kernel, block, grid, ms per step) for
+ * wavefronts per compute unit; for a single D3Q19 lattice the z-slab sweep
+ * with 8, 16 and 32 planes (block 256, one pass); for D3Q19 the fused kernel.
+ * Each runs 2 untimed steps, then trial_steps (>= 1) steps timed with HIP
+ * events on the handle's stream.  Needs set_geometry; it overwrites the
+ * populations (uniform rest state, density 1), so init_fields must be called
+ * afterwards (ESTATE until then).  The choice is applied as by
+ * mclbm_set_kernel, mclbm_set_launch and mclbm_set_sweep and returned in
+ * *kernel, *block_threads, *grid_blocks, *slab_planes and *ms_per_step (any
+ * may be NULL; for the fused kernel block and grid are its fixed 512 threads
+ * and one workgroup per work item).  The candidates' timings are written to
+ * table[5 * i + 0..4] = (kernel, block, grid, slab planes, ms per step) for
  * i < table_rows (table may be NULL); *n_rows (may be NULL) receives the
  * number of candidates. */
 int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_t* block_threads,
-                   int32_t* grid_blocks, double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
+                   int32_t* grid_blocks, int32_t* slab_planes, double* ms_per_step, double* table, int32_t table_rows,
+                   int32_t* n_rows);
 
 /* enable != 0: run each aligned interval of monitor_every steps (which must
  * be even) as one replay of a captured HIP graph (the step kernels plus the

@@ -56,6 +56,10 @@ int wn_relu_bwd(const float* y, float* g, long long count, void* stream);
 /* y[i] += x[i] (gradient accumulation where a tensor feeds two layers). */
 int wn_add(const float* x, float* y, long long count, void* stream);
 
+/* y[v][jy] += x[v][jx] for v < V (y has cy channels, x has cx): a residual
+ * connection from an input channel to an output channel. */
+int wn_add_channel(float* y, int cy, int jy, const float* x, int cx, int jx, long long V, void* stream);
+
 /* 2x2x2 average pooling [n][d][h][w][c] -> [n][d/2][h/2][w/2][c] and its adjoint. */
 int wn_pool2_fwd(const float* x, int n, int d, int h, int w, int c, float* y, void* stream);
 int wn_pool2_bwd(const float* dy, int n, int d, int h, int w, int c, float* dx, void* stream);

@@ -145,6 +145,9 @@ struct mclbm_handle {
     double rhobar[2] = {0, 0};
     int block = 256, grid = 0;
     int kernel = 0;                  // 0: two passes, 1: fused (D3Q19)
+    int slab_planes = 0;             // z-slab sweep of the two-pass kernels (0: off)
+    std::vector<int> slab_chunk;     // first chunk of each slab's collide pass, then the chunk count
+    std::vector<int> slab_dend;      // end chunk of each slab's density pass
     // graph replay of monitor_every steps (one per A/B parity)
     bool use_graph = false;
     hipStream_t gstream = nullptr;
@@ -388,6 +391,9 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     c.fwork = any_frozen ? h->fwork : nullptr;
     c.fnwork = h->fnwork;
     c.nfitems = h->nfitems;
+    c.nslab = h->slab_chunk.empty() ? 0 : (int)h->slab_chunk.size() - 1;
+    c.slab_chunk = h->slab_chunk.empty() ? nullptr : h->slab_chunk.data();
+    c.slab_dend = h->slab_dend.empty() ? nullptr : h->slab_dend.data();
     c.partials = h->partials;
     c.result = h->result;
     c.block = h->block;
@@ -672,6 +678,30 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     return mclbm_init_batch(p, 1, device_arena, arena_bytes, hip_stream, out);
 }
 
+// Chunk ranges of z-slabs of `planes` planes (at least 2 each) of a single
+// D3Q19 sample; empty when the sweep is off or does not apply.
+static void setup_slabs(mclbm_handle* h) {
+    h->slab_chunk.clear();
+    h->slab_dend.clear();
+    if (h->slab_planes < 2 || h->S != 1 || h->p.lattice != MCLBM_D3Q19 || !h->geom_set) return;
+    const SampleHost& sm = h->smp[0];
+    const int P = h->slab_planes;
+    int S = sm.nz / P;
+    if (S < 2) return;
+    const unsigned plane = (unsigned)sm.nx * (unsigned)sm.ny;
+    std::vector<long long> kfirst;   // first fluid node at or after plane s * P (slab S-1 takes the rest)
+    for (int s = 0; s < S; ++s) {
+        const unsigned n0 = (unsigned)(s * P) * plane;
+        kfirst.push_back(sm.kbase + (long long)(std::lower_bound(sm.pos.begin(), sm.pos.end(), n0) - sm.pos.begin()));
+    }
+    kfirst.push_back(sm.kbase + sm.nf);
+    for (int s = 0; s < S; ++s) {
+        h->slab_chunk.push_back((int)(kfirst[s] / 64));
+        h->slab_dend.push_back((int)std::min<long long>(h->nchunks, (kfirst[s + 1] + 63) / 64));
+    }
+    h->slab_chunk.push_back((int)h->nchunks);
+}
+
 static uint32_t tail_link_word(int lattice) {
     const int Q = flow_q(lattice);
     return 0x80000000u | (((1u << Q) - 1u) & ~1u);
@@ -750,6 +780,7 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
     int rc = upload_work(h);
     if (rc != MCLBM_OK) return rc;
     h->geom_set = true;
+    setup_slabs(h);
     return MCLBM_OK;
 }
 
@@ -1071,8 +1102,20 @@ int mclbm_set_kernel(mclbm_handle* h, int32_t kernel) {
     return MCLBM_OK;
 }
 
+int mclbm_set_sweep(mclbm_handle* h, int32_t slab_planes) {
+    if (!h) return MCLBM_EINVAL;
+    if (slab_planes != 0 && slab_planes < 2) return fail(h, MCLBM_EINVAL, "slab_planes must be 0 or >= 2");
+    if (slab_planes != 0 && (h->S != 1 || h->p.lattice != MCLBM_D3Q19))
+        return fail(h, MCLBM_EINVAL, "the slab sweep is for a single D3Q19 lattice");
+    drop_graphs(h);
+    h->slab_planes = slab_planes;
+    setup_slabs(h);
+    return MCLBM_OK;
+}
+
 int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_t* block_threads,
-                   int32_t* grid_blocks, double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
+                   int32_t* grid_blocks, int32_t* slab_planes, double* ms_per_step, double* table, int32_t table_rows,
+                   int32_t* n_rows) {
     if (!h) return MCLBM_EINVAL;
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
     if (trial_steps < 1) return fail(h, MCLBM_EINVAL, "trial_steps must be >= 1");
@@ -1085,31 +1128,43 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
     HIPCHK(h, hipGetDevice(&dev));
     HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     struct Cand {
-        int kernel, block, grid;
+        int kernel, block, grid, slab;
     };
     std::vector<Cand> cand;
     for (int b : {64, 128, 256}) {
-        cand.push_back({MCLBM_KERNEL_TWO_PASS, b, 0});
+        cand.push_back({MCLBM_KERNEL_TWO_PASS, b, 0, 0});
         for (int w : {8, 16, 32}) {
             const int g = (cus * w / (b / 64) + 7) / 8 * 8;
-            if (g > 0) cand.push_back({MCLBM_KERNEL_TWO_PASS, b, g});
+            if (g > 0) cand.push_back({MCLBM_KERNEL_TWO_PASS, b, g, 0});
         }
     }
-    if (h->p.lattice == MCLBM_D3Q19) cand.push_back({MCLBM_KERNEL_FUSED, FT_THREADS, 0});
+    if (h->p.lattice == MCLBM_D3Q19) {
+        if (h->S == 1)
+            for (int sp : {8, 16, 32})
+                if (h->smp[0].nz / sp >= 2) cand.push_back({MCLBM_KERNEL_TWO_PASS, 256, 0, sp});
+        cand.push_back({MCLBM_KERNEL_FUSED, FT_THREADS, 0, 0});
+    }
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return fail(h, MCLBM_EHIP, "hipEventCreate failed");
     }
-    const int old_kernel = h->kernel, old_block = h->block, old_grid = h->grid;
+    const Cand old{h->kernel, h->block, h->grid, h->slab_planes};
+    auto apply = [&](const Cand& c) {
+        h->kernel = c.kernel;
+        if (c.kernel == MCLBM_KERNEL_TWO_PASS) {   // the fused kernel keeps the two-pass shape for other kernels
+            h->block = c.block;
+            h->grid = c.grid;
+        }
+        h->slab_planes = c.slab;
+        setup_slabs(h);
+    };
     double best = INFINITY;
-    Cand bc{old_kernel, old_block, old_grid};
+    Cand bc = old;
     int rc = MCLBM_OK;
     for (size_t i = 0; i < cand.size() && rc == MCLBM_OK; ++i) {
-        h->kernel = cand[i].kernel;
-        h->block = cand[i].kernel == MCLBM_KERNEL_FUSED ? old_block : cand[i].block;
-        h->grid = cand[i].kernel == MCLBM_KERNEL_FUSED ? old_grid : cand[i].grid;
+        apply(cand[i]);
         for (int s = 0; s < 2 && rc == MCLBM_OK; ++s) rc = launch_step(h, h->stream);
         if (rc != MCLBM_OK) break;
         hipError_t e = hipEventRecord(e0, h->stream);
@@ -1122,10 +1177,11 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
         if (rc != MCLBM_OK) break;
         const double per = (double)ms / trial_steps;
         if (table && (int)i < table_rows) {
-            table[4 * i + 0] = cand[i].kernel;
-            table[4 * i + 1] = cand[i].block;
-            table[4 * i + 2] = cand[i].grid;
-            table[4 * i + 3] = per;
+            table[5 * i + 0] = cand[i].kernel;
+            table[5 * i + 1] = cand[i].block;
+            table[5 * i + 2] = cand[i].grid;
+            table[5 * i + 3] = cand[i].slab;
+            table[5 * i + 4] = per;
         }
         if (per < best) {
             best = per;
@@ -1137,19 +1193,16 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
     h->fields_set = false;
     h->step = 0;
     h->snap_valid = false;
+    drop_graphs(h);
     if (rc != MCLBM_OK) {
-        h->kernel = old_kernel;
-        h->block = old_block;
-        h->grid = old_grid;
+        apply(old);
         return rc;
     }
-    h->kernel = bc.kernel;
-    // the two-pass launch shape stays valid (the other kernels use it too)
-    h->block = bc.kernel == MCLBM_KERNEL_FUSED ? old_block : bc.block;
-    h->grid = bc.kernel == MCLBM_KERNEL_FUSED ? old_grid : bc.grid;
+    apply(bc);
     if (kernel) *kernel = bc.kernel;
     if (block_threads) *block_threads = bc.block;
     if (grid_blocks) *grid_blocks = bc.grid;
+    if (slab_planes) *slab_planes = bc.slab;
     if (ms_per_step) *ms_per_step = best;
     if (n_rows) *n_rows = (int32_t)cand.size();
     return MCLBM_OK;

@@ -65,6 +65,7 @@ struct Geo {
     const int* nwork;
     int nchunks;
     int reverse;       // 1: visit the work items in reverse order
+    int first;         // without a work list: chunks first .. first + nchunks - 1
 };
 
 // Wave-uniform load of a value that no kernel writes while it runs (work
@@ -89,7 +90,7 @@ __device__ __forceinline__ void for_each_chunk(const Geo& g, Body body) {
         int item = (it * G + lb0) * wpb + wave;
         if (item >= nitems) break;
         if (g.reverse) item = nitems - 1 - item;
-        const int ch = g.work ? ld_uniform(g.work + item) : item;
+        const int ch = g.work ? ld_uniform(g.work + item) : g.first + item;
         body(ch);
     }
 }
@@ -669,6 +670,7 @@ static inline Geo make_geo(const Ctx& c, bool use_work) {
     g.nwork = c.nwork;
     g.nchunks = (int)c.nchunks;
     g.reverse = 0;
+    g.first = 0;
     return g;
 }
 
@@ -694,6 +696,44 @@ static hipError_t step_t(const Ctx& c) {
         }
     }
     const int bs = c.block > 0 ? c.block : 256;
+    if (c.nslab > 1 && !c.work) {
+        // z-slab sweep: density passes run one slab ahead of the collide
+        // passes, so each collide pass re-reads populations the density pass
+        // has just read (memory-side cache) instead of the whole lattice.
+        // Density pass s covers every node of its planes (its last chunk may
+        // also hold nodes of the next slab: those are computed twice, to the
+        // same value); collide pass s takes each chunk exactly once.  Slabs
+        // have >= 2 planes, so collide pass s needs density passes s - 1, s,
+        // s + 1 only (and the last / first slab across the periodic boundary).
+        auto D = [&](int s) {
+            Geo gs = g;
+            gs.first = c.slab_chunk[s];
+            gs.nchunks = c.slab_dend[s] - c.slab_chunk[s];
+            Ctx cs = c;
+            cs.nchunks = gs.nchunks;
+            hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid_for(cs, bs, true), dim3(bs), 0, c.stream, P, gs,
+                               (const STT<ST>*)c.fA, (SR<ST>*)c.psi);
+        };
+        auto Cl = [&](int s) {
+            Geo gs = g;
+            gs.first = c.slab_chunk[s];
+            gs.nchunks = c.slab_chunk[s + 1] - c.slab_chunk[s];
+            gs.reverse = 1;
+            Ctx cs = c;
+            cs.nchunks = gs.nchunks;
+            hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid_for(cs, bs, true), dim3(bs), 0, c.stream, P, gs,
+                               (const STT<ST>*)c.fA, (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB,
+                               (const SR<ST>*)c.psi);
+        };
+        const int S = c.nslab;
+        D(S - 1);   // the collide of slab 0 reads the last planes across the periodic boundary
+        D(0);
+        for (int s = 0; s < S; ++s) {
+            if (s + 1 <= S - 2) D(s + 1);
+            Cl(s);
+        }
+        return hipGetLastError();
+    }
     const dim3 grid = grid_for(c, bs, true);
     hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);

@@ -60,6 +60,9 @@ struct Ctx {
     const int* fwork;           // active fused items or nullptr = every item
     const int* fnwork;          // device count of `fwork`
     long long nfitems;
+    int nslab;                  // > 1: z-slab sweep of a single sample
+    const int* slab_chunk;      // host [nslab + 1]: collide pass s covers chunks slab_chunk[s] .. slab_chunk[s+1]-1
+    const int* slab_dend;       // host [nslab]: density pass s covers chunks slab_chunk[s] .. slab_dend[s]-1
 };
 
 constexpr int MON_NV = 11;      // values reduced per monitor

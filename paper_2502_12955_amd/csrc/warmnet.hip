@@ -306,6 +306,12 @@ __global__ void __launch_bounds__(256) add_k(const float* __restrict__ x, float*
     if (i < n) y[i] += x[i];
 }
 
+__global__ void __launch_bounds__(256) add_channel_k(float* __restrict__ y, int cy, int jy,
+                                                     const float* __restrict__ x, int cx, int jx, long long V) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V) y[v * cy + jy] += x[v * cx + jx];
+}
+
 __global__ void __launch_bounds__(256) pool2_fwd_k(const float* __restrict__ x, int n, int d, int h, int w, int c,
                                                    float* __restrict__ y) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -557,6 +563,14 @@ int wn_add(const float* x, float* y, long long count, void* stream) {
     if (count == 0) return 0;
     hipLaunchKernelGGL(add_k, blocks_for(count), dim3(256), 0, (hipStream_t)stream, x, y, count);
     return hip_result("add");
+}
+
+int wn_add_channel(float* y, int cy, int jy, const float* x, int cx, int jx, long long V, void* stream) {
+    if (!y || !x || cy < 1 || cx < 1 || jy < 0 || jy >= cy || jx < 0 || jx >= cx || V < 0)
+        return err(-1, "wn_add_channel: bad arguments");
+    if (V == 0) return 0;
+    hipLaunchKernelGGL(add_channel_k, blocks_for(V), dim3(256), 0, (hipStream_t)stream, y, cy, jy, x, cx, jx, V);
+    return hip_result("add_channel");
 }
 
 int wn_pool2_fwd(const float* x, int n, int d, int h, int w, int c, float* y, void* stream) {

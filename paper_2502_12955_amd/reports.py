@@ -137,7 +137,8 @@ def batch(args):
     fluid = int(b.monitors()[8])
     ms = _timed_steps(b, args.steps)
     out["fluid_nodes"] = fluid
-    out["batched"] = dict(launch=dict(kernel=tuned[0], block=tuned[1], grid=tuned[2]), ms_per_step=ms / args.steps,
+    out["batched"] = dict(launch=dict(kernel=tuned[0], block=tuned[1], grid=tuned[2], slab=tuned[3]),
+                          ms_per_step=ms / args.steps,
                           mlups=nodes / (ms / args.steps * 1e-3) / 1e6,
                           mflups=fluid / (ms / args.steps * 1e-3) / 1e6)
     b.close()

@@ -36,6 +36,7 @@ def load(path: str = LIB_PATH):
     lib.wn_bias_grad.argtypes = [vp, i64, i32, vp, vp]
     lib.wn_relu_bwd.argtypes = [vp, vp, i64, vp]
     lib.wn_add.argtypes = [vp, vp, i64, vp]
+    lib.wn_add_channel.argtypes = [vp, i32, i32, vp, i32, i32, i64, vp]
     for name in ("wn_pool2_fwd", "wn_pool2_bwd", "wn_up2_fwd", "wn_up2_bwd"):
         getattr(lib, name).argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
     lib.wn_concat.argtypes = [vp, i32, vp, i32, i64, vp, vp]
@@ -175,6 +176,12 @@ def add_(y, x):
     _ok(load().wn_add(_p(x), _p(y), y.numel(), _stream()))
 
 
+def add_channel_(y, jy, x, jx):
+    """y[..., jy] += x[..., jx] in place (same voxel count)."""
+    V = y.numel() // y.shape[-1]
+    _ok(load().wn_add_channel(_p(y), y.shape[-1], jy, _p(x), x.shape[-1], jx, V, _stream()))
+
+
 def adam(p, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
     _ok(load().wn_adam(_p(p), _p(g), _p(m), _p(v), p.numel(), lr, b1, b2, eps, step, _stream()))
 
@@ -213,9 +220,16 @@ class Conv:
 class UNet:
     """Four-level U-Net: widths (16, 32, 64, 128), two 3x3x3 convolutions per
     level, 2x average pooling down, nearest upsampling and skip concatenation
-    up, a 1x1x1 head to ``cout`` channels."""
+    up, a 1x1x1 head to ``cout`` channels.
 
-    def __init__(self, cin=2, cout=4, widths=(16, 32, 64, 128), seed=0, device="cuda:0"):
+    ``residual`` lists (output channel, input channel) pairs added after the
+    head, so the network learns a correction to that input (for the warm
+    start: the steady phase field as the initial one plus a change).  With
+    ``zero_head`` the head starts at zero, so the untrained network returns
+    exactly the residual inputs (the start from rest)."""
+
+    def __init__(self, cin=2, cout=4, widths=(16, 32, 64, 128), seed=0, device="cuda:0", residual=(),
+                 zero_head=False):
         rng = np.random.default_rng(seed)
         self.widths = widths
         self.enc = []
@@ -229,6 +243,9 @@ class UNet:
             self.dec.append((Conv(cin_d, widths[lvl], 3, True, rng, device),
                              Conv(widths[lvl], widths[lvl], 3, True, rng, device)))
         self.head = Conv(widths[0], cout, 1, False, rng, device)
+        if zero_head:
+            self.head.W.zero_()
+        self.residual = tuple(residual)
         self.step_count = 0
         self._ws = None
 
@@ -272,6 +289,8 @@ class UNet:
             h = h2
         acts["head_in"] = h
         y = self.head.forward(h)
+        for jo, ji in self.residual:
+            add_channel_(y, jo, x, ji)
         return y, acts
 
     def _workspace(self, acts):

@@ -95,7 +95,9 @@ def targets(rho, u, shape, scale):
 
 def fields_from_prediction(pred, solid, scale):
     """(rho [2, N], u [3, N]) for init_fields from a prediction [d, h, w, 4]."""
-    phi = np.clip(pred[..., 3].astype(np.float64), -1.0, 1.0)
+    # the two phases' densities bound phi; clipping there keeps both densities >= RHO_MINOR > 0
+    pmax = (RHO_MAJOR - RHO_MINOR) / (RHO_MAJOR + RHO_MINOR)
+    phi = np.clip(pred[..., 3].astype(np.float64), -pmax, pmax)
     fluid = solid == 0
     tot = RHO_MAJOR + RHO_MINOR
     rho = np.stack([0.5 * tot * (1 + phi), 0.5 * tot * (1 - phi)]) * fluid
@@ -167,7 +169,8 @@ def run(args):
     wt = [var_p / max(var_u, 1e-30)] * 3 + [1.0]
     x = torch.tensor(X, device=dev)
     t = torch.tensor(T, device=dev)
-    net = warmnet.UNet(cin=2, cout=4, widths=tuple(args.widths), seed=args.seed)
+    net = warmnet.UNet(cin=2, cout=4, widths=tuple(args.widths), seed=args.seed, residual=[(3, 1)],
+                       zero_head=True)
     tr = Trainer(net, x, t, wt, batch=args.batch)
     rng = np.random.default_rng(args.seed)
     torch.cuda.synchronize()
@@ -201,7 +204,9 @@ def run(args):
     rep.update(cold_converged=sum(c > 0 for c in cold["steps"]), warm_converged=sum(w > 0 for w in warm["steps"]),
                cold_diverged=sum(cold["diverged"]), warm_diverged=sum(warm["diverged"]))
     dphi, du = [], []
-    for rc, rw, uc, uw in zip(cold["rho"], warm["rho"], cold["u"], warm["u"]):
+    for i, (rc, rw, uc, uw) in enumerate(zip(cold["rho"], warm["rho"], cold["u"], warm["u"])):
+        if cold["diverged"][i] or warm["diverged"][i]:
+            continue      # non-finite fields: no comparison
         pc = targets(rc, uc, shape, scale)
         pw = targets(rw, uw, shape, scale)
         dphi.append(float(np.mean(np.abs(pc[..., 3] - pw[..., 3]))))

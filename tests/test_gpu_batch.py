@@ -159,7 +159,8 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     b = mclbm.Batch([c[0] for c in cases])
     b.set_geometry([c[1] for c in cases])
     cache = str(tmp_path / "tune.json")
-    kern, blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
+    kern, blk, grid, slab, ms = b.autotune(trial_steps=4, cache_path=cache)
+    assert slab == 0                                # no slab sweep for batches
     assert kern in (0, 1) and blk in (64, 128, 256, 512) and grid % 8 == 0 and ms > 0
     with pytest.raises(mclbm.MclbmError) as e:      # populations were overwritten
         b.step(1)
@@ -172,7 +173,7 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     # a second handle of the same class takes the cached shape without timing
     b2 = mclbm.Batch([c[0] for c in cases])
     b2.set_geometry([c[1] for c in cases])
-    assert b2.autotune(trial_steps=4, cache_path=cache) == (kern, blk, grid, None)
+    assert b2.autotune(trial_steps=4, cache_path=cache) == (kern, blk, grid, slab, None)
     for x in (b, b2, ref):
         x.close()
 
