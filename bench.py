@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Throughput of the fused multi-component LBM step on one MI355X.
+"""Throughput of the multi-component LBM step on one MI355X.
 
 Workload (default): two-component D3Q19 Shan-Chen flow + D3Q7 reactive solute
 in a 256^3 seeded Boolean sphere pack (porosity 0.4, R = 8), body force along
@@ -75,11 +75,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic sphere-pack box")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused"],
-                    help="step kernel (auto: the native tuner picks kernel and launch shape)")
-    ap.add_argument("--block", type=int, default=256, help="threads per workgroup of the two-pass kernels")
-    ap.add_argument("--grid", type=int, default=0, help="persistent grid blocks of the two-pass kernels (0: one pass)")
-    ap.add_argument("--slab", type=int, default=0, help="z-slab sweep planes of the two-pass kernels (0: off)")
+    ap.add_argument("--block", type=int, default=0,
+                    help="threads per workgroup of the step kernels (0: the native tuner picks the launch shape)")
+    ap.add_argument("--grid", type=int, default=0, help="persistent grid blocks with --block (0: one pass)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -104,17 +102,12 @@ def main():
 
     lat = mclbm.Lattice(p)
     nrc = lat.set_geometry(mask)
-    if args.kernel == "auto":
-        kern, blk, grd, slab, ms = lat.autotune(trial_steps=10)
-        kname = {0: "two_pass", 1: "fused"}[kern]
-        log(f"[bench] autotuned: kernel {kname}, block {blk}, grid {grd}, slab {slab} ({ms:.3f} ms/step)")
+    if args.block == 0:
+        blk, grd, ms = lat.autotune(trial_steps=10)
+        log(f"[bench] autotuned launch shape: block {blk}, grid {grd} ({ms:.3f} ms/step)")
     else:
-        kname, blk, grd, slab = args.kernel, args.block, args.grid, args.slab
-        lat.set_kernel(kname)
-        lat.set_launch(args.block, args.grid)
-        lat.set_sweep(args.slab)
-        if kname == "fused":
-            blk, grd, slab = 512, 0, 0
+        blk, grd = args.block, args.grid
+        lat.set_launch(blk, grd)
     gmask, _, _ = lat.get_geometry()
     nfluid = int((gmask == 0).sum())
     lat.init_fields(rho, None, C)
@@ -150,8 +143,7 @@ def main():
     traffic = traffic_from_profiles(args.storage, args.n, nfluid)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "mcmp step (" + ("k_fused" if kname == "fused" else "k_density + k_collide") + ")",
-                "alg_bytes_per_launch": alg_bytes,
+                "kernel": "mcmp step (k_density + k_collide)", "alg_bytes_per_launch": alg_bytes,
                 "launch_ms": round(launch_ms, 4)}
 
     cpu = None
@@ -170,7 +162,7 @@ def main():
                                f"Boolean sphere pack porosity 0.4 R=8, Guo forcing, body force x 1e-5, "
                                f"wall reaction k=1e-3, inlet/outlet solute",
                    "nodes": N, "fluid_nodes": nfluid, "storage": args.storage,
-                   "launch": {"kernel": kname, "block": blk, "grid": grd, "slab_planes": slab},
+                   "launch": {"block": blk, "grid": grd},
                    "mflups": round(nfluid / (ms_per_step * 1e-3) / 1e6, 1),
                    "monitor_every": p["monitor_every"], "final_residual": float(mon[9])},
         "roofline": roofline,

@@ -62,7 +62,6 @@ enum { MCLBM_FORCING_GUO = 0, MCLBM_FORCING_SC = 1 };
  * fluid-mean density of component s at init_fields) in 16 bits with
  * round-to-nearest-even; collision arithmetic is FP32.  The solute is stored
  * unshifted.  F64 computes in FP64, the others in FP32. */
-enum { MCLBM_KERNEL_TWO_PASS = 0, MCLBM_KERNEL_FUSED = 1 };
 enum { MCLBM_F64 = 0, MCLBM_F32 = 1, MCLBM_F16_SHIFT = 2, MCLBM_BF16_SHIFT = 3 };
 enum { MCLBM_SOLUTE_OFF = 0, MCLBM_SOLUTE_PERIODIC = 1, MCLBM_SOLUTE_INLET_OUTLET_X = 2 };
 
@@ -154,15 +153,18 @@ int mclbm_get_monitors(mclbm_handle* h, double out[16]);
 /* Run monitors now on the current state (as if at a monitor step). */
 int mclbm_monitor_now(mclbm_handle* h);
 
-/* Populations of the current pre-collision state.  raw == 0: FP64 decoded
- * values [ncomp*Q + QS][N] (flow [s][i], then solute [k]; QS = 0 without
- * solute); raw != 0: the stored bytes in the same order (8, 4 or 2 bytes per
- * value; shifted values for *_SHIFT).  Solid nodes read 0. */
+/* Populations of the current pre-collision state (after streaming, before
+ * the next collision).  raw == 0: FP64 decoded values [ncomp*Q + QS][N]
+ * (flow [s][i], then solute [k]; QS = 0 without solute); raw != 0: the stored
+ * bytes in the same order (8, 4 or 2 bytes per value; shifted values for
+ * *_SHIFT).  Solid nodes read 0. */
 int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw);
 
-/* Replace the pre-collision state (same layout as mclbm_get_populations; the
- * storage shift rhobar_s is kept).  Writing back what get_populations(raw=1)
- * returned restores the state bit for bit.  ESTATE before init_fields. */
+/* Replace the pre-collision state of every sample (same layout as
+ * mclbm_get_populations; the storage shift rhobar_s is kept).  Writing back
+ * what get_populations(raw=1) returned continues the run bit for bit.
+ * Convergence flags of a batch and the residual snapshot start over.  ESTATE
+ * before init_fields. */
 int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw);
 
 /* Bytes of mclbm_get_populations output for the given raw flag. */
@@ -185,41 +187,20 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
  * with the same arithmetic, so results do not depend on the launch shape. */
 int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks);
 
-/* Step kernel: MCLBM_KERNEL_TWO_PASS (default; a density pass over all fluid
- * nodes, then a collide-and-push pass) or MCLBM_KERNEL_FUSED (D3Q19 only: one
- * pass of z-marching workgroups over x-y tiles that keep three planes of
- * pseudo-potentials and fluid indices in LDS).  Both update every node with
- * the same arithmetic, so results are bit-identical.  EINVAL for an unknown
- * kind or the fused kernel on D2Q9. */
-int mclbm_set_kernel(mclbm_handle* h, int32_t kernel);
-
-/* Sweep order of the two-pass kernels: slab_planes = 0 (default) runs each
- * pass over the whole lattice; slab_planes >= 2 splits a single D3Q19 lattice
- * into z-slabs of that many planes (the last takes the remainder) and runs the
- * density pass one slab ahead of the collide pass, so the collide pass reads
- * populations the density pass has just read.  Results are bit-identical.
- * EINVAL for a batch of several samples or for D2Q9. */
-int mclbm_set_sweep(mclbm_handle* h, int32_t slab_planes);
-
-/* Time the step kernels over a set of candidates and keep the fastest.
- * Candidates: the two-pass kernels with block_threads 64, 128, 256 crossed
- * with grid_blocks 0 (one pass) and persistent grids of 8, 16 and 32
- * wavefronts per compute unit; for a single D3Q19 lattice the z-slab sweep
- * with 8, 16 and 32 planes (block 256, one pass); for D3Q19 the fused kernel.
- * Each runs 2 untimed steps, then trial_steps (>= 1) steps timed with HIP
- * events on the handle's stream.  Needs set_geometry; it overwrites the
- * populations (uniform rest state, density 1), so init_fields must be called
- * afterwards (ESTATE until then).  The choice is applied as by
- * mclbm_set_kernel, mclbm_set_launch and mclbm_set_sweep and returned in
- * *kernel, *block_threads, *grid_blocks, *slab_planes and *ms_per_step (any
- * may be NULL; for the fused kernel block and grid are its fixed 512 threads
- * and one workgroup per work item).  The candidates' timings are written to
- * table[5 * i + 0..4] = (kernel, block, grid, slab planes, ms per step) for
- * i < table_rows (table may be NULL); *n_rows (may be NULL) receives the
- * number of candidates. */
-int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_t* block_threads,
-                   int32_t* grid_blocks, int32_t* slab_planes, double* ms_per_step, double* table, int32_t table_rows,
-                   int32_t* n_rows);
+/* Time the step kernels over a set of launch shapes and keep the fastest.
+ * Candidates: block_threads 64, 128, 256 crossed with grid_blocks 0 (one
+ * pass) and persistent grids of 8, 16 and 32 wavefronts per compute unit.
+ * Each candidate runs 2 untimed steps, then
+ * trial_steps (>= 1) steps timed with HIP events on the handle's stream.
+ * Needs set_geometry; it overwrites the populations (uniform rest state,
+ * density 1), so init_fields must be called afterwards (ESTATE until then).
+ * The chosen shape is applied as by mclbm_set_launch and returned in
+ * *block_threads, *grid_blocks and *ms_per_step (any may be NULL).  The
+ * candidates' timings are written to table[3 * i + 0..2] = (block, grid, ms
+ * per step) for i < table_rows (table may be NULL); *n_rows (may be NULL)
+ * receives the number of candidates. */
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
+                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
 
 /* enable != 0: run each aligned interval of monitor_every steps (which must
  * be even) as one replay of a captured HIP graph (the step kernels plus the

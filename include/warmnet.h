@@ -47,8 +47,13 @@ size_t wn_wgrad_workspace_bytes(int n, int d, int h, int w, int ci, int co, int 
 int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w, int ci, int co, int k, float* dW,
                     void* workspace, size_t workspace_bytes, void* stream);
 
-/* db[o] = sum_v dy[v][o] (overwrites). */
-int wn_bias_grad(const float* dy, long long V, int co, float* db, void* stream);
+/* Workspace bytes needed by wn_bias_grad for V voxels and co channels. */
+size_t wn_bias_grad_workspace_bytes(long long V, int co);
+
+/* db[o] = sum_v dy[v][o] (overwrites), co <= 256; partial sums over blocks of
+ * voxels go to `workspace` and are added in a fixed order (deterministic). */
+int wn_bias_grad(const float* dy, long long V, int co, float* db, void* workspace, size_t workspace_bytes,
+                 void* stream);
 
 /* g[i] = y[i] > 0 ? g[i] : 0, in place. */
 int wn_relu_bwd(const float* y, float* g, long long count, void* stream);

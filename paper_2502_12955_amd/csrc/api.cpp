@@ -130,11 +130,7 @@ struct mclbm_handle {
     int* chunk_sample = nullptr;
     int* work = nullptr;
     int* nwork = nullptr;
-    int4* fitems = nullptr;         // fused-step work items
-    int* fwork = nullptr;
-    int* fnwork = nullptr;
-    long long nfitems = 0;
-    std::vector<long long> fitem_base;  // first fused item of each sample (S + 1 entries)
+    long long nactive = 0;          // chunks in the work list
     double* host_result = nullptr;  // pinned [S][16]
     int* host_nwork = nullptr;      // pinned
     // state
@@ -144,10 +140,6 @@ struct mclbm_handle {
     double mon[16];
     double rhobar[2] = {0, 0};
     int block = 256, grid = 0;
-    int kernel = 0;                  // 0: two passes, 1: fused (D3Q19)
-    int slab_planes = 0;             // z-slab sweep of the two-pass kernels (0: off)
-    std::vector<int> slab_chunk;     // first chunk of each slab's collide pass, then the chunk count
-    std::vector<int> slab_dend;      // end chunk of each slab's density pass
     // graph replay of monitor_every steps (one per A/B parity)
     bool use_graph = false;
     hipStream_t gstream = nullptr;
@@ -160,7 +152,7 @@ namespace {
 
 struct Layout {
     size_t fA, fB, hA, hB, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample, work, nwork,
-        fitems, fwork, fnwork, total;
+        total;
 };
 
 Ctx base_ctx(const mclbm_params& p) {
@@ -183,17 +175,6 @@ Ctx base_ctx(const mclbm_params& p) {
     c.k_wall = p.k_wall;
     c.C_in = p.C_in;
     return c;
-}
-
-// fused-step work items of one sample: x-y tiles times z segments
-long long fused_items_of(const mclbm_params& p) {
-    return (long long)((p.nx + FTX - 1) / FTX) * ((p.ny + FTY - 1) / FTY) * ((p.nz + FZS - 1) / FZS);
-}
-
-long long fused_item_count(const mclbm_params* ps, int n) {
-    long long t = 0;
-    for (int s = 0; s < n; ++s) t += fused_items_of(ps[s]);
-    return t;
 }
 
 Layout layout_for(const mclbm_params* ps, int n) {
@@ -231,10 +212,6 @@ Layout layout_for(const mclbm_params* ps, int n) {
     L.chunk_sample = take(nch * 4);
     L.work = take(nch * 4);
     L.nwork = take(64);
-    const size_t nfi = (size_t)fused_item_count(ps, n);
-    L.fitems = take(nfi * sizeof(int4));
-    L.fwork = take(nfi * 4);
-    L.fnwork = take(64);
     L.total = align256(off);
     return L;
 }
@@ -386,14 +363,7 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     for (const auto& sm : h->smp) any_frozen |= sm.frozen;
     c.work = any_frozen ? h->work : nullptr;
     c.nwork = h->nwork;
-    c.kernel = h->kernel;
-    c.fitems = h->fitems;
-    c.fwork = any_frozen ? h->fwork : nullptr;
-    c.fnwork = h->fnwork;
-    c.nfitems = h->nfitems;
-    c.nslab = h->slab_chunk.empty() ? 0 : (int)h->slab_chunk.size() - 1;
-    c.slab_chunk = h->slab_chunk.empty() ? nullptr : h->slab_chunk.data();
-    c.slab_dend = h->slab_dend.empty() ? nullptr : h->slab_dend.data();
+    c.nactive = h->nactive;
     c.partials = h->partials;
     c.result = h->result;
     c.block = h->block;
@@ -479,21 +449,11 @@ int upload_work(mclbm_handle* h) {
         for (long long c = 0; c < nc; ++c) w.push_back((int)(c0 + c));
     }
     *h->host_nwork = (int)w.size();
+    h->nactive = (long long)w.size();
     if (!w.empty())
         HIPCHK(h, hipMemcpyAsync(h->work, w.data(), w.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->nwork, h->host_nwork, 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (h->fitem_base.size() == (size_t)h->S + 1) {
-        std::vector<int> fw;
-        for (int s = 0; s < h->S; ++s)
-            if (!h->smp[s].frozen)
-                for (long long i = h->fitem_base[s]; i < h->fitem_base[s + 1]; ++i) fw.push_back((int)i);
-        *h->host_nwork = (int)fw.size();
-        if (!fw.empty())
-            HIPCHK(h, hipMemcpyAsync(h->fwork, fw.data(), fw.size() * 4, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(h->fnwork, h->host_nwork, 4, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-    }
     return MCLBM_OK;
 }
 
@@ -657,10 +617,6 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
     h->chunk_sample = (int*)(base + L.chunk_sample);
     h->work = (int*)(base + L.work);
     h->nwork = (int*)(base + L.nwork);
-    h->fitems = (int4*)(base + L.fitems);
-    h->fwork = (int*)(base + L.fwork);
-    h->fnwork = (int*)(base + L.fnwork);
-    h->nfitems = fused_item_count(p, n);
     hipError_t e = hipHostMalloc((void**)&h->host_result, (size_t)n * 16 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_nwork, 64, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -678,29 +634,9 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     return mclbm_init_batch(p, 1, device_arena, arena_bytes, hip_stream, out);
 }
 
-// Chunk ranges of z-slabs of `planes` planes (at least 2 each) of a single
-// D3Q19 sample; empty when the sweep is off or does not apply.
-static void setup_slabs(mclbm_handle* h) {
-    h->slab_chunk.clear();
-    h->slab_dend.clear();
-    if (h->slab_planes < 2 || h->S != 1 || h->p.lattice != MCLBM_D3Q19 || !h->geom_set) return;
-    const SampleHost& sm = h->smp[0];
-    const int P = h->slab_planes;
-    int S = sm.nz / P;
-    if (S < 2) return;
-    const unsigned plane = (unsigned)sm.nx * (unsigned)sm.ny;
-    std::vector<long long> kfirst;   // first fluid node at or after plane s * P (slab S-1 takes the rest)
-    for (int s = 0; s < S; ++s) {
-        const unsigned n0 = (unsigned)(s * P) * plane;
-        kfirst.push_back(sm.kbase + (long long)(std::lower_bound(sm.pos.begin(), sm.pos.end(), n0) - sm.pos.begin()));
-    }
-    kfirst.push_back(sm.kbase + sm.nf);
-    for (int s = 0; s < S; ++s) {
-        h->slab_chunk.push_back((int)(kfirst[s] / 64));
-        h->slab_dend.push_back((int)std::min<long long>(h->nchunks, (kfirst[s + 1] + 63) / 64));
-    }
-    h->slab_chunk.push_back((int)h->nchunks);
-}
+// rows per y-band of the fluid numbering: eight bands (one per XCD of a
+// single large lattice), at least 4 rows
+static int band_rows(int ny) { return std::max(4, (ny + 7) / 8); }
 
 static uint32_t tail_link_word(int lattice) {
     const int Q = flow_q(lattice);
@@ -727,12 +663,23 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
         nrc += pinch_fill(gs, sm.mask);
         std::vector<uint32_t> words;
         link_words(gs, sm.mask, words, nullptr, nullptr);
+        // fluid numbering: y-bands of band_rows(ny) rows, each swept plane by
+        // plane (z), row by row, x fastest.  Within a band the nodes of the
+        // planes above and below are a few dozen chunks away, so the
+        // neighbour gathers of the collide pass (pseudo-potentials, fluid
+        // indices) and its pushes across planes stay in the L2 cache of the
+        // XCD that sweeps the band.
         sm.pos.clear();
-        for (long long n = 0; n < sm.N; ++n)
-            if (!sm.mask[n]) {
-                map[(size_t)(sm.dbase + n)] = (int)(kbase + (long long)sm.pos.size());
-                sm.pos.push_back((unsigned)n);
-            }
+        const int rows = band_rows(sm.ny);
+        for (int y0 = 0; y0 < sm.ny; y0 += rows)
+            for (int z = 0; z < sm.nz; ++z)
+                for (int y = y0; y < std::min(sm.ny, y0 + rows); ++y)
+                    for (int x = 0; x < sm.nx; ++x) {
+                        const long long n = x + (long long)sm.nx * (y + (long long)sm.ny * z);
+                        if (sm.mask[n]) continue;
+                        map[(size_t)(sm.dbase + n)] = (int)(kbase + (long long)sm.pos.size());
+                        sm.pos.push_back((unsigned)n);
+                    }
         sm.nf = (long long)sm.pos.size();
         if (sm.nf == 0) {
             char buf[96];
@@ -759,17 +706,6 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
     }
     h->nchunks = kbase / 64;
     if (n_reclassified) *n_reclassified = nrc;
-    std::vector<int4> items;
-    h->fitem_base.assign(1, 0);
-    for (int s = 0; s < h->S; ++s) {
-        const SampleHost& sm = h->smp[s];
-        for (int z0 = 0; z0 < sm.nz; z0 += FZS)
-            for (int y0 = 0; y0 < sm.ny; y0 += FTY)
-                for (int x0 = 0; x0 < sm.nx; x0 += FTX) items.push_back(make_int4(s, x0, y0, z0));
-        h->fitem_base.push_back((long long)items.size());
-    }
-    if ((long long)items.size() != h->nfitems) return fail(h, MCLBM_EINVAL, "fused item count mismatch");
-    HIPCHK(h, hipMemcpyAsync(h->fitems, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->map, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->links, links.data(), links.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -780,7 +716,6 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
     int rc = upload_work(h);
     if (rc != MCLBM_OK) return rc;
     h->geom_set = true;
-    setup_slabs(h);
     return MCLBM_OK;
 }
 
@@ -1017,7 +952,17 @@ int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw) {
     HIPCHK(h, hipMemcpyAsync(h->fA, dev.data(), PF * M * sb, hipMemcpyHostToDevice, h->stream));
     if (PS) HIPCHK(h, hipMemcpyAsync(h->hA, dev.data() + PF * M * sb, PS * M * sb, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    return MCLBM_OK;
+    // a new state for every sample: convergence flags (frozen samples would
+    // otherwise keep a stale mirror in B) and the residual snapshot start over
+    drop_graphs(h);
+    h->snap_valid = false;
+    for (auto& sm : h->smp) {
+        sm.frozen = false;
+        sm.conv_step = -1;
+        sm.div_step = -1;
+        sm.bad = false;
+    }
+    return upload_work(h);
 }
 
 int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_t* steps_taken) {
@@ -1038,8 +983,7 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
             return e;
         }
         if (h->step % K != 0) continue;
-        bool active = false, changed = false, had_frozen = false, any_div = false;
-        for (const auto& sm : h->smp) had_frozen |= sm.frozen;
+        bool active = false, changed = false, any_div = false;
         for (auto& sm : h->smp) {
             if (sm.frozen) {
                 any_div |= sm.div_step >= 0;
@@ -1069,7 +1013,8 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
             rc = any_div ? fail(h, MCLBM_EDIVERGED, "a sample went non-finite (see the sample monitors)") : MCLBM_OK;
             break;
         }
-        if (changed && !had_frozen) drop_graphs(h);   // captured without the work list
+        // graphs hold grid sizes and the work-list choice: capture again
+        if (changed) drop_graphs(h);
         if (changed) {
             int u = upload_work(h);
             if (u != MCLBM_OK) return u;
@@ -1091,31 +1036,8 @@ int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks
     return MCLBM_OK;
 }
 
-int mclbm_set_kernel(mclbm_handle* h, int32_t kernel) {
-    if (!h) return MCLBM_EINVAL;
-    if (kernel != MCLBM_KERNEL_TWO_PASS && kernel != MCLBM_KERNEL_FUSED)
-        return fail(h, MCLBM_EINVAL, "unknown step kernel");
-    if (kernel == MCLBM_KERNEL_FUSED && h->p.lattice != MCLBM_D3Q19)
-        return fail(h, MCLBM_EINVAL, "the fused step kernel is D3Q19 only");
-    drop_graphs(h);
-    h->kernel = kernel;
-    return MCLBM_OK;
-}
-
-int mclbm_set_sweep(mclbm_handle* h, int32_t slab_planes) {
-    if (!h) return MCLBM_EINVAL;
-    if (slab_planes != 0 && slab_planes < 2) return fail(h, MCLBM_EINVAL, "slab_planes must be 0 or >= 2");
-    if (slab_planes != 0 && (h->S != 1 || h->p.lattice != MCLBM_D3Q19))
-        return fail(h, MCLBM_EINVAL, "the slab sweep is for a single D3Q19 lattice");
-    drop_graphs(h);
-    h->slab_planes = slab_planes;
-    setup_slabs(h);
-    return MCLBM_OK;
-}
-
-int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_t* block_threads,
-                   int32_t* grid_blocks, int32_t* slab_planes, double* ms_per_step, double* table, int32_t table_rows,
-                   int32_t* n_rows) {
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
+                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
     if (!h) return MCLBM_EINVAL;
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
     if (trial_steps < 1) return fail(h, MCLBM_EINVAL, "trial_steps must be >= 1");
@@ -1127,22 +1049,13 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
     int dev = 0, cus = 0;
     HIPCHK(h, hipGetDevice(&dev));
     HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    struct Cand {
-        int kernel, block, grid, slab;
-    };
-    std::vector<Cand> cand;
+    std::vector<std::pair<int, int>> cand;
     for (int b : {64, 128, 256}) {
-        cand.push_back({MCLBM_KERNEL_TWO_PASS, b, 0, 0});
+        cand.push_back({b, 0});
         for (int w : {8, 16, 32}) {
             const int g = (cus * w / (b / 64) + 7) / 8 * 8;
-            if (g > 0) cand.push_back({MCLBM_KERNEL_TWO_PASS, b, g, 0});
+            if (g > 0) cand.push_back({b, g});
         }
-    }
-    if (h->p.lattice == MCLBM_D3Q19) {
-        if (h->S == 1)
-            for (int sp : {8, 16, 32})
-                if (h->smp[0].nz / sp >= 2) cand.push_back({MCLBM_KERNEL_TWO_PASS, 256, 0, sp});
-        cand.push_back({MCLBM_KERNEL_FUSED, FT_THREADS, 0, 0});
     }
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
@@ -1150,21 +1063,12 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
         (void)hipEventDestroy(e0);
         return fail(h, MCLBM_EHIP, "hipEventCreate failed");
     }
-    const Cand old{h->kernel, h->block, h->grid, h->slab_planes};
-    auto apply = [&](const Cand& c) {
-        h->kernel = c.kernel;
-        if (c.kernel == MCLBM_KERNEL_TWO_PASS) {   // the fused kernel keeps the two-pass shape for other kernels
-            h->block = c.block;
-            h->grid = c.grid;
-        }
-        h->slab_planes = c.slab;
-        setup_slabs(h);
-    };
+    const int old_block = h->block, old_grid = h->grid;
     double best = INFINITY;
-    Cand bc = old;
-    int rc = MCLBM_OK;
+    int bb = old_block, bg = old_grid, rc = MCLBM_OK;
     for (size_t i = 0; i < cand.size() && rc == MCLBM_OK; ++i) {
-        apply(cand[i]);
+        h->block = cand[i].first;
+        h->grid = cand[i].second;
         for (int s = 0; s < 2 && rc == MCLBM_OK; ++s) rc = launch_step(h, h->stream);
         if (rc != MCLBM_OK) break;
         hipError_t e = hipEventRecord(e0, h->stream);
@@ -1177,15 +1081,14 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
         if (rc != MCLBM_OK) break;
         const double per = (double)ms / trial_steps;
         if (table && (int)i < table_rows) {
-            table[5 * i + 0] = cand[i].kernel;
-            table[5 * i + 1] = cand[i].block;
-            table[5 * i + 2] = cand[i].grid;
-            table[5 * i + 3] = cand[i].slab;
-            table[5 * i + 4] = per;
+            table[3 * i + 0] = cand[i].first;
+            table[3 * i + 1] = cand[i].second;
+            table[3 * i + 2] = per;
         }
         if (per < best) {
             best = per;
-            bc = cand[i];
+            bb = cand[i].first;
+            bg = cand[i].second;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1195,14 +1098,14 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* kernel, int32_
     h->snap_valid = false;
     drop_graphs(h);
     if (rc != MCLBM_OK) {
-        apply(old);
+        h->block = old_block;
+        h->grid = old_grid;
         return rc;
     }
-    apply(bc);
-    if (kernel) *kernel = bc.kernel;
-    if (block_threads) *block_threads = bc.block;
-    if (grid_blocks) *grid_blocks = bc.grid;
-    if (slab_planes) *slab_planes = bc.slab;
+    h->block = bb;
+    h->grid = bg;
+    if (block_threads) *block_threads = bb;
+    if (grid_blocks) *grid_blocks = bg;
     if (ms_per_step) *ms_per_step = best;
     if (n_rows) *n_rows = (int32_t)cand.size();
     return MCLBM_OK;

@@ -2,8 +2,9 @@
 //
 // A handle holds a batch of independent samples (a single lattice is a batch
 // of one).  Storage is fluid-only: the fluid nodes of sample s are numbered
-// k = kbase_s .. kbase_s + Nf_s - 1 in increasing box index (kbase_s is a
-// multiple of 64, so no 64-node chunk straddles two samples); pos[k] is the
+// k = kbase_s .. kbase_s + Nf_s - 1 band by band (bands of y rows, each swept
+// plane by plane, row by row, x fastest; kbase_s is a multiple of 64, so no
+// 64-node chunk straddles two samples); pos[k] is the
 // box index within the sample and map[dbase_s + n] the fluid index (or -1 for
 // a solid node).  Populations are kept in chunks of 64 fluid nodes (one
 // wavefront): element (plane j, node k) lives at
@@ -65,7 +66,6 @@ struct Geo {
     const int* nwork;
     int nchunks;
     int reverse;       // 1: visit the work items in reverse order
-    int first;         // without a work list: chunks first .. first + nchunks - 1
 };
 
 // Wave-uniform load of a value that no kernel writes while it runs (work
@@ -90,7 +90,7 @@ __device__ __forceinline__ void for_each_chunk(const Geo& g, Body body) {
         int item = (it * G + lb0) * wpb + wave;
         if (item >= nitems) break;
         if (g.reverse) item = nitems - 1 - item;
-        const int ch = g.work ? ld_uniform(g.work + item) : g.first + item;
+        const int ch = g.work ? ld_uniform(g.work + item) : item;
         body(ch);
     }
 }
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
 // ---------------------------------------------------------------------------
 // collision of one fluid node and push of its post-collision populations
 // (flow with halfway bounce-back; solute with the wet-node reaction, inlet and
-// outlet), shared by the two-pass and the fused step kernels.
+// outlet).
 //   f: pre-collision flow populations of node k (overwritten)
 //   psi_nb(t, i): pseudo-potential of component t at x + c_i (0 for solids)
 //   dest(i): fluid index of x + c_i (called only where that node is fluid)
@@ -275,108 +275,6 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
     });
 }
 
-
-// ---------------------------------------------------------------------------
-// fused step for D3Q19: one workgroup per work item = (sample, x-y tile of
-// FTX x FTY nodes, FZS planes), marching in z.  For each plane z + 1 the
-// workgroup computes the pseudo-potentials and fluid indices of the tile plus
-// a one-node ring into LDS (three planes kept), then collides and pushes the
-// nodes of plane z with every neighbour's psi and destination index read from
-// LDS.  The density pass of the two-pass step disappears: ring nodes and the
-// first plane of each item are the only populations read twice.
-// ---------------------------------------------------------------------------
-template <int ST, int NC>
-__global__ void __launch_bounds__(FT_THREADS) k_fused(Phys<typename Store<ST>::R> P, Geo g, FusedItems fi,
-                                                      const typename Store<ST>::T* __restrict__ fA,
-                                                      typename Store<ST>::T* __restrict__ fB,
-                                                      const typename Store<ST>::T* __restrict__ hA,
-                                                      typename Store<ST>::T* __restrict__ hB) {
-    using L = Lat<1>;
-    using S = Store<ST>;
-    using R = typename S::R;
-    constexpr int Q = L::Q, PF = NC * Q;
-    constexpr int HX = FTX + 2, HP = (FTX + 2) * (FTY + 2);
-    __shared__ R s_psi[3][HP][NC];
-    __shared__ int s_map[3][HP];
-
-    int idx = blockIdx.x;
-    if (fi.work) {
-        if (idx >= ld_uniform(fi.nwork)) return;
-        idx = ld_uniform(fi.work + idx);
-    }
-    const int* ip = (const int*)(fi.items + idx);   // sample, x0, y0, z0
-    int4 it;
-    it.x = ld_uniform(ip + 0);
-    it.y = ld_uniform(ip + 1);
-    it.z = ld_uniform(ip + 2);
-    it.w = ld_uniform(ip + 3);
-    const int* q = (const int*)(g.smp + it.x);
-    const int nx = ld_uniform(q + 0), ny = ld_uniform(q + 1), nz = ld_uniform(q + 2), dbase = ld_uniform(q + 5);
-    const int* mp = g.map + dbase;
-    R sh[NC][Q];
-    load_shifts<1, ST, NC>(P, sh);
-
-    // pseudo-potential and fluid index of the tile + ring at plane zz (-1 <= zz <= nz) into slot
-    auto fill = [&](int zz, int slot) {
-        const int zw = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-        for (int p = threadIdx.x; p < HP; p += FT_THREADS) {
-            const int hy = p / HX, hx = p - hy * HX;
-            int x = (it.y + hx - 1) % nx, y = (it.z + hy - 1) % ny;
-            x += x < 0 ? nx : 0;
-            y += y < 0 ? ny : 0;
-            const int kf = mp[x + nx * (y + ny * zw)];
-            s_map[slot][p] = kf;
-            R r[NC];
-#pragma unroll
-            for (int s = 0; s < NC; ++s) r[s] = R(0);
-            if (kf >= 0) {
-#pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    R a = 0;
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) a += S::load(blk(fA, PF, s * Q + i, (unsigned)kf), sh[s][i]);
-                    r[s] = P.rho0 * (R(1) - exp_r<R>(-a * P.inv_rho0));
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < NC; ++s) s_psi[slot][p][s] = r[s];
-        }
-    };
-
-    const int xl = threadIdx.x % FTX, yl = threadIdx.x / FTX;
-    const int x = it.y + xl, y = it.z + yl;
-    const bool inside = x < nx && y < ny;
-    const int ph = (yl + 1) * HX + xl + 1;
-    const int z1 = min(it.w + FZS, nz);
-    int sm = 0, s0 = 1, sp = 2;   // slots of planes z - 1, z, z + 1
-    fill(it.w - 1, sm);
-    fill(it.w, s0);
-    for (int z = it.w; z < z1; ++z) {
-        fill(z + 1, sp);
-        __syncthreads();
-        const int kf = inside ? s_map[s0][ph] : -1;
-        if (kf >= 0) {
-            const unsigned k = (unsigned)kf;
-            const uint32_t lw = g.links[k];
-            R f[NC][Q];
-#pragma unroll
-            for (int s = 0; s < NC; ++s)
-#pragma unroll
-                for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
-            auto slot = [&](int cz) { return cz < 0 ? sm : (cz > 0 ? sp : s0); };
-            auto psi_nb = [&](int t, int i) -> R {
-                return s_psi[slot(L::cz[i])][ph + L::cy[i] * HX + L::cx[i]][t];
-            };
-            auto dest = [&](int i) -> unsigned { return (unsigned)s_map[slot(L::cz[i])][ph + L::cy[i] * HX + L::cx[i]]; };
-            collide_push<1, ST, NC>(P, sh, k, lw, x, nx, f, psi_nb, dest, fB, hA, hB);
-        }
-        __syncthreads();
-        const int t = sm;
-        sm = s0;
-        s0 = sp;
-        sp = t;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // initialisation at equilibrium (no force term) from dense staging fields
@@ -670,14 +568,16 @@ static inline Geo make_geo(const Ctx& c, bool use_work) {
     g.nwork = c.nwork;
     g.nchunks = (int)c.nchunks;
     g.reverse = 0;
-    g.first = 0;
     return g;
 }
 
 // grid: blocks of bs threads (bs/64 chunks per pass), multiple of 8 for the XCD remap
+// (sized for the active chunks when a work list is in use; a smaller grid than
+// the items only makes the wavefronts loop)
 static inline dim3 grid_for(const Ctx& c, int bs, bool persistent) {
     const long long wpb = bs / 64;
-    long long nb = (c.nchunks + wpb - 1) / wpb;
+    const long long items = c.work ? c.nactive : c.nchunks;
+    long long nb = (items + wpb - 1) / wpb;
     if (persistent && c.grid > 0 && c.grid < nb) nb = c.grid;
     nb = (nb + 7) & ~7LL;
     return dim3((unsigned)(nb > 0 ? nb : 8));
@@ -687,59 +587,12 @@ template <int LAT, int ST, int NC>
 static hipError_t step_t(const Ctx& c) {
     auto P = make_phys<SR<ST>>(c);
     const Geo g = make_geo(c, true);
-    if constexpr (LAT == 1) {
-        if (c.kernel == 1) {
-            const FusedItems fi{c.fitems, c.fwork, c.fnwork};
-            hipLaunchKernelGGL((k_fused<ST, NC>), dim3((unsigned)c.nfitems), dim3(FT_THREADS), 0, c.stream, P, g, fi,
-                               (const STT<ST>*)c.fA, (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB);
-            return hipGetLastError();
-        }
-    }
     const int bs = c.block > 0 ? c.block : 256;
-    if (c.nslab > 1 && !c.work) {
-        // z-slab sweep: density passes run one slab ahead of the collide
-        // passes, so each collide pass re-reads populations the density pass
-        // has just read (memory-side cache) instead of the whole lattice.
-        // Density pass s covers every node of its planes (its last chunk may
-        // also hold nodes of the next slab: those are computed twice, to the
-        // same value); collide pass s takes each chunk exactly once.  Slabs
-        // have >= 2 planes, so collide pass s needs density passes s - 1, s,
-        // s + 1 only (and the last / first slab across the periodic boundary).
-        auto D = [&](int s) {
-            Geo gs = g;
-            gs.first = c.slab_chunk[s];
-            gs.nchunks = c.slab_dend[s] - c.slab_chunk[s];
-            Ctx cs = c;
-            cs.nchunks = gs.nchunks;
-            hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid_for(cs, bs, true), dim3(bs), 0, c.stream, P, gs,
-                               (const STT<ST>*)c.fA, (SR<ST>*)c.psi);
-        };
-        auto Cl = [&](int s) {
-            Geo gs = g;
-            gs.first = c.slab_chunk[s];
-            gs.nchunks = c.slab_chunk[s + 1] - c.slab_chunk[s];
-            gs.reverse = 1;
-            Ctx cs = c;
-            cs.nchunks = gs.nchunks;
-            hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid_for(cs, bs, true), dim3(bs), 0, c.stream, P, gs,
-                               (const STT<ST>*)c.fA, (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB,
-                               (const SR<ST>*)c.psi);
-        };
-        const int S = c.nslab;
-        D(S - 1);   // the collide of slab 0 reads the last planes across the periodic boundary
-        D(0);
-        for (int s = 0; s < S; ++s) {
-            if (s + 1 <= S - 2) D(s + 1);
-            Cl(s);
-        }
-        return hipGetLastError();
-    }
     const dim3 grid = grid_for(c, bs, true);
     hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
     // the collide pass walks the chunks in the opposite order of the density
-    // pass, so it starts on the chunks the density pass read last (still in
-    // the memory-side cache), and the next density pass on those it wrote last
+    // pass, so it starts on the chunks the density pass read last
     Geo gr = g;
     gr.reverse = 1;
     hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,

@@ -19,18 +19,6 @@ struct SampleDev {
     int pad_;
 };
 
-// Fused step: work items are x-y tiles of FTX x FTY nodes over FZS planes,
-// one workgroup of FT_THREADS threads each.
-constexpr int FTX = 32, FTY = 16, FZS = 16, FT_THREADS = FTX * FTY;
-
-// Work items of the fused step: items[i] = (sample, x0, y0, z0); work lists the
-// items of the samples still running (nullptr: all items).
-struct FusedItems {
-    const int4* items;
-    const int* work;
-    const int* nwork;
-};
-
 struct Ctx {
     int lat, st, nc;            // lattice (0 D2Q9, 1 D3Q19), storage, components
     int nsamples;
@@ -51,18 +39,11 @@ struct Ctx {
     void* snap;                 // residual snapshot [5][nchunks*64] (arith type)
     const int* work;            // active chunk list (device) or nullptr = every chunk
     const int* nwork;           // device count of `work`
+    long long nactive;          // host copy of that count (grid sizes)
     double* partials;           // [nchunks][MON_NV] per-chunk monitor partials
     double* result;             // [nsamples][16] per-sample monitor sums
     int block;                  // threads per block of the step kernels (64, 128, 256)
     int grid;                   // persistent grid (blocks, multiple of 8); 0 = one pass over the chunks
-    int kernel;                 // 0: density + collide passes, 1: fused z-marching step (D3Q19)
-    const int4* fitems;         // [nfitems] fused work items
-    const int* fwork;           // active fused items or nullptr = every item
-    const int* fnwork;          // device count of `fwork`
-    long long nfitems;
-    int nslab;                  // > 1: z-slab sweep of a single sample
-    const int* slab_chunk;      // host [nslab + 1]: collide pass s covers chunks slab_chunk[s] .. slab_chunk[s+1]-1
-    const int* slab_dend;       // host [nslab]: density pass s covers chunks slab_chunk[s] .. slab_dend[s]-1
 };
 
 constexpr int MON_NV = 11;      // values reduced per monitor

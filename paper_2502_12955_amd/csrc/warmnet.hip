@@ -281,19 +281,37 @@ __global__ void __launch_bounds__(256) conv_wgrad_t(const float* __restrict__ X,
 // ---------------------------------------------------------------------------
 // small layers
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) bias_grad_k(const float* __restrict__ dy, long long V, int co,
-                                                   float* __restrict__ db) {
+// bias gradient, stage 1: block b sums rows [b * BG_ROWS, ...) of dy [V][co];
+// thread t owns column t % co of rows t / co + j * (256 / co), so each pass
+// reads a contiguous run of whole rows; partial[b][o] in fixed order
+constexpr int BG_ROWS = 512;
+
+__global__ void __launch_bounds__(256) bias_grad_part(const float* __restrict__ dy, long long V, int co,
+                                                      float* __restrict__ part) {
     __shared__ float red[256];
-    const int o = blockIdx.x;
+    const int t = threadIdx.x;
+    const int rpp = 256 / co;                // rows per pass (co <= 256)
+    const int o = t % co, r = t / co;
+    const long long v0 = (long long)blockIdx.x * BG_ROWS, v1 = min(V, v0 + BG_ROWS);
     float s = 0.f;
-    for (long long v = threadIdx.x; v < V; v += 256) s += dy[(size_t)v * co + o];
-    red[threadIdx.x] = s;
+    if (r < rpp)
+        for (long long v = v0 + r; v < v1; v += rpp) s += dy[v * co + o];
+    red[t] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    if (t < co) {
+        float acc = 0.f;
+        for (int j = 0; j < rpp; ++j) acc += red[j * co + t];
+        part[(size_t)blockIdx.x * co + t] = acc;
     }
-    if (threadIdx.x == 0) db[o] = red[0];
+}
+
+__global__ void __launch_bounds__(256) bias_grad_final(const float* __restrict__ part, int nblk, int co,
+                                                       float* __restrict__ db) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= co) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * co + o];
+    db[o] = s;
 }
 
 __global__ void __launch_bounds__(256) relu_bwd_k(const float* __restrict__ y, float* __restrict__ g, long long n) {
@@ -545,9 +563,19 @@ int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w,
     return hip_result("conv_wgrad");
 }
 
-int wn_bias_grad(const float* dy, long long V, int co, float* db, void* stream) {
-    if (!dy || !db || V < 1 || co < 1) return err(-1, "wn_bias_grad: bad arguments");
-    hipLaunchKernelGGL(bias_grad_k, dim3(co), dim3(256), 0, (hipStream_t)stream, dy, V, co, db);
+size_t wn_bias_grad_workspace_bytes(long long V, int co) {
+    return (size_t)((V + BG_ROWS - 1) / BG_ROWS) * (size_t)(co > 0 ? co : 0) * sizeof(float);
+}
+
+int wn_bias_grad(const float* dy, long long V, int co, float* db, void* workspace, size_t workspace_bytes,
+                 void* stream) {
+    if (!dy || !db || V < 1 || co < 1 || co > 256) return err(-1, "wn_bias_grad: bad arguments");
+    if (!workspace || workspace_bytes < wn_bias_grad_workspace_bytes(V, co))
+        return err(-1, "wn_bias_grad: workspace too small");
+    const int nblk = (int)((V + BG_ROWS - 1) / BG_ROWS);
+    hipLaunchKernelGGL(bias_grad_part, dim3(nblk), dim3(256), 0, (hipStream_t)stream, dy, V, co, (float*)workspace);
+    hipLaunchKernelGGL(bias_grad_final, dim3((co + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)workspace, nblk, co, db);
     return hip_result("bias_grad");
 }
 

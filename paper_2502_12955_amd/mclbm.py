@@ -82,7 +82,7 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
-           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_kernel", "mclbm_set_sweep", "mclbm_destroy", "mclbm_last_error")
+           "mclbm_synchronize", "mclbm_autotune", "mclbm_destroy", "mclbm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -115,10 +115,8 @@ def load(path: str = LIB_PATH):
     lib.mclbm_get_sample_monitors.argtypes = [vp, i32, vp]
     lib.mclbm_get_step.argtypes = [vp, ct.POINTER(i64)]
     lib.mclbm_synchronize.argtypes = [vp]
-    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32),
-                                   ct.POINTER(dbl), vp, i32, ct.POINTER(i32)]
-    lib.mclbm_set_kernel.argtypes = [vp, i32]
-    lib.mclbm_set_sweep.argtypes = [vp, i32]
+    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp, i32,
+                                   ct.POINTER(i32)]
     lib.mclbm_destroy.argtypes = [vp]
     lib.mclbm_destroy.restype = None
     lib.mclbm_last_error.argtypes = [vp]
@@ -245,26 +243,14 @@ def set_launch(h, block_threads=256, grid_blocks=0):
     _check(load().mclbm_set_launch(h, int(block_threads), int(grid_blocks)), h)
 
 
-KERNEL = {"two_pass": 0, "fused": 1}
-
-
-def set_kernel(h, kernel="two_pass"):
-    _check(load().mclbm_set_kernel(h, KERNEL[kernel] if isinstance(kernel, str) else int(kernel)), h)
-
-
-def set_sweep(h, slab_planes=0):
-    _check(load().mclbm_set_sweep(h, int(slab_planes)), h)
-
-
 def autotune(h, trial_steps=20):
-    """Native step-kernel tuner; returns (kernel, block, grid, slab planes, ms_per_step,
-    table rows (kernel, block, grid, slab planes, ms))."""
-    k, b, g, sl, n = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
+    """Native launch-shape tuner; returns (block, grid, ms_per_step, table rows (block, grid, ms))."""
+    b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32()
     ms = ct.c_double()
-    table = np.zeros((64, 5))
-    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(k), ct.byref(b), ct.byref(g), ct.byref(sl),
-                                 ct.byref(ms), _ptr(table), 64, ct.byref(n)), h)
-    return k.value, b.value, g.value, sl.value, ms.value, table[: n.value].tolist()
+    table = np.zeros((64, 3))
+    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(b), ct.byref(g), ct.byref(ms), _ptr(table), 64,
+                                 ct.byref(n)), h)
+    return b.value, g.value, ms.value, table[: n.value].tolist()
 
 
 def tune_key(plist):
@@ -385,18 +371,14 @@ class Lattice:
     def set_graph(self, enable=True):
         set_graph(self.h, enable)
 
-    def set_kernel(self, kernel="two_pass"):
-        set_kernel(self.h, kernel)
 
-    def set_sweep(self, slab_planes=0):
-        set_sweep(self.h, slab_planes)
 
     def autotune(self, trial_steps=20, cache_path=None):
-        """Choose the step kernel and launch shape (after set_geometry; init_fields must follow).
+        """Choose the launch shape (after set_geometry; init_fields must follow).
 
         With ``cache_path`` (a JSON file), a shape already chosen for the same
         physics and size class is reused without timing, and new choices are
-        added to the file.  Returns (kernel, block, grid, slab planes, ms_per_step or None if cached)."""
+        added to the file.  Returns (block, grid, ms_per_step or None if cached)."""
         import json
 
         key = tune_key(getattr(self, "plist", [self.params]))
@@ -405,19 +387,15 @@ class Lattice:
             with open(cache_path) as f:
                 cache = json.load(f)
         if key in cache:
-            e = cache[key]
-            k, b, g, sl = e["kernel"], e["block"], e["grid"], e["slab"]
-            self.set_kernel(k)
-            if k == KERNEL["two_pass"]:
-                self.set_launch(b, g)
-                self.set_sweep(sl)
-            return k, b, g, sl, None
-        k, b, g, sl, ms, table = autotune(self.h, trial_steps)
+            b, g = cache[key]["block"], cache[key]["grid"]
+            self.set_launch(b, g)
+            return b, g, None
+        b, g, ms, table = autotune(self.h, trial_steps)
         if cache_path:
-            cache[key] = dict(kernel=k, block=b, grid=g, slab=sl, ms_per_step=ms, table=table)
+            cache[key] = dict(block=b, grid=g, ms_per_step=ms, table=table)
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)
-        return k, b, g, sl, ms
+        return b, g, ms
 
     @property
     def step_count(self):

@@ -64,8 +64,10 @@ def kernels(args):
             step_avg += avg
         lines.append(f"| `{n}` | {r['Calls']} | {avg:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} % |")
-    lines += ["", f"Sum of the average durations of the step kernels ({', '.join(STEP_KERNELS)}): "
-                  f"{step_avg:.1f} us per step.", ""]
+    if step_avg > 0:
+        lines += ["", f"Sum of the average durations of the step kernels ({', '.join(STEP_KERNELS)}): "
+                      f"{step_avg:.1f} us per step."]
+    lines.append("")
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
     print("\n".join(lines))

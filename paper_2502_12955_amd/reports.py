@@ -1,6 +1,6 @@
 """Measurement studies beyond the single-lattice benchmark.
 
-    python -m paper_2502_12955_amd.reports precision [--n 384 --steps 20000]
+    python -m paper_2502_12955_amd.reports precision [--n 384 --steps 10000]
         Reduced-precision storage (FP16 / BF16 shifted, FP32) against an FP64
         run on the GPU from the same state: per-field max-abs and RMS error
         over fluid nodes after ``steps``, throughput of each storage, and the
@@ -137,8 +137,7 @@ def batch(args):
     fluid = int(b.monitors()[8])
     ms = _timed_steps(b, args.steps)
     out["fluid_nodes"] = fluid
-    out["batched"] = dict(launch=dict(kernel=tuned[0], block=tuned[1], grid=tuned[2], slab=tuned[3]),
-                          ms_per_step=ms / args.steps,
+    out["batched"] = dict(launch=dict(block=tuned[0], grid=tuned[1]), ms_per_step=ms / args.steps,
                           mlups=nodes / (ms / args.steps * 1e-3) / 1e6,
                           mflups=fluid / (ms / args.steps * 1e-3) / 1e6)
     b.close()
@@ -159,9 +158,7 @@ def batch(args):
 
     b = mclbm.Batch([c[0] for c in cases])
     b.set_geometry([c[1] for c in cases])
-    b.set_kernel(tuned[0])
-    if tuned[0] == 0:
-        b.set_launch(tuned[1], tuned[2])
+    b.set_launch(tuned[0], tuned[1])
     b.set_graph(True)
     b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
     b.synchronize()
@@ -203,7 +200,10 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="what", required=True)
     a = sub.add_parser("precision")
     a.add_argument("--n", type=int, default=384)
-    a.add_argument("--steps", type=int, default=20000)
+    # the 384^3 two-phase case goes non-finite near step 13,000 in FP64 as well
+    # as FP32 (a physical instability of this parameter set), so the
+    # comparison is taken at 10,000 steps
+    a.add_argument("--steps", type=int, default=10000)
     a.add_argument("--storages", nargs="+", default=["f32", "f16s", "bf16s"])
     a.add_argument("--res-n", type=int, default=128)
     a.add_argument("--tol", type=float, default=1e-6)

@@ -33,7 +33,9 @@ def load(path: str = LIB_PATH):
     lib.wn_wgrad_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, i32]
     lib.wn_wgrad_workspace_bytes.restype = sz
     lib.wn_conv3d_wgrad.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
-    lib.wn_bias_grad.argtypes = [vp, i64, i32, vp, vp]
+    lib.wn_bias_grad.argtypes = [vp, i64, i32, vp, vp, sz, vp]
+    lib.wn_bias_grad_workspace_bytes.argtypes = [i64, i32]
+    lib.wn_bias_grad_workspace_bytes.restype = sz
     lib.wn_relu_bwd.argtypes = [vp, vp, i64, vp]
     lib.wn_add.argtypes = [vp, vp, i64, vp]
     lib.wn_add_channel.argtypes = [vp, i32, i32, vp, i32, i32, i64, vp]
@@ -95,9 +97,20 @@ def conv3d_wgrad(x, dy, k, dW, ws):
     _ok(load().wn_conv3d_wgrad(_p(x), _p(dy), n, d, h, w, ci, co, k, _p(dW), _p(ws), ws.numel() * 4, _stream()))
 
 
-def bias_grad(dy, db):
+def bias_grad_workspace_bytes(V, co):
+    return load().wn_bias_grad_workspace_bytes(V, co)
+
+
+def bias_grad(dy, db, ws=None):
+    """db = sum of dy over voxels; ``ws`` a device workspace (allocated if None)."""
+    import torch
+
     co = dy.shape[-1]
-    _ok(load().wn_bias_grad(_p(dy), dy.numel() // co, co, _p(db), _stream()))
+    V = dy.numel() // co
+    need = bias_grad_workspace_bytes(V, co)
+    if ws is None or ws.numel() * 4 < need:
+        ws = torch.empty((need + 3) // 4, dtype=torch.float32, device=dy.device)
+    _ok(load().wn_bias_grad(_p(dy), V, co, _p(db), _p(ws), ws.numel() * 4, _stream()))
 
 
 def relu_bwd(y, g):
@@ -210,7 +223,7 @@ class Conv:
         if self.relu:
             relu_bwd(y, dy)
         conv3d_wgrad(x, dy, self.k, self.dW, ws)
-        bias_grad(dy, self.db)
+        bias_grad(dy, self.db, ws)
         return conv3d_dgrad(dy, self.W) if need_dx else None
 
     def params(self):
@@ -298,7 +311,8 @@ class UNet:
 
         need = 0
         for l, xin in self._layer_inputs(acts):
-            need = max(need, wgrad_workspace_bytes(tuple(xin.shape), l.co, l.k))
+            need = max(need, wgrad_workspace_bytes(tuple(xin.shape), l.co, l.k),
+                       bias_grad_workspace_bytes(xin.numel() // xin.shape[-1], l.co))
         if self._ws is None or self._ws.numel() * 4 < need:
             self._ws = torch.empty((need + 3) // 4, dtype=torch.float32, device=acts["x"].device)
         return self._ws

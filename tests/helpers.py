@@ -18,13 +18,7 @@ def gpu_lattice(p, mask, rho, u=None, C=None, block=None):
     from paper_2502_12955_amd import mclbm
 
     lat = mclbm.Lattice(p)
-    if block == "fused":           # the fused step kernel (D3Q19); 2-D keeps the two-pass kernels
-        if p.get("lattice", "D3Q19") == "D3Q19":
-            lat.set_kernel("fused")
-    elif block == "slab":          # z-slab sweep of 2 planes (D3Q19 single lattice)
-        if p.get("lattice", "D3Q19") == "D3Q19" and p.get("nz", 1) >= 4:
-            lat.set_sweep(2)
-    elif block is not None:
+    if block is not None:
         lat.set_launch(block)
     lat.set_geometry(mask)
     lat.init_fields(rho, u, C)

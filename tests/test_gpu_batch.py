@@ -29,10 +29,8 @@ def _samples(n=4, seed=0, storage="f32", k_wall=0.02):
     return cases
 
 
-def _batch(cases, kernel=None, **launch):
+def _batch(cases, **launch):
     b = mclbm.Batch([c[0] for c in cases])
-    if kernel:
-        b.set_kernel(kernel)
     if launch:
         b.set_launch(**launch)
     b.set_geometry([c[1] for c in cases])
@@ -75,18 +73,13 @@ def test_persistent_grid_and_block_sizes_bit_identical():
         b.step(20)
         assert np.array_equal(b.populations(raw=True), want), launch
         b.close()
-    b = _batch(cases, kernel="fused")
-    b.step(20)
-    assert np.array_equal(b.populations(raw=True), want), "fused"
-    b.close()
 
 
-@pytest.mark.parametrize("kernel", ["two_pass", "fused"])
-def test_graph_replay_matches_eager_steps(kernel):
+def test_graph_replay_matches_eager_steps():
     """Replays interleaved with eager steps and host reads; each compared bitwise."""
     cases = _samples(3, seed=11)
     eager = _batch(cases)
-    graph = _batch(cases, kernel=kernel)
+    graph = _batch(cases)
     graph.set_graph(True)
     for rep in range(4):
         eager.step(10)
@@ -105,8 +98,7 @@ def test_graph_replay_matches_eager_steps(kernel):
     graph.close()
 
 
-@pytest.mark.parametrize("kernel", ["two_pass", "fused"])
-def test_run_to_residual_freezes_each_sample(kernel):
+def test_run_to_residual_freezes_each_sample():
     """Samples stop at their own convergence step; the batch result equals each
     sample run alone to the same tolerance.  FP64 storage: at this flow speed
     (|u| ~ 1e-4) FP32 round-off alone keeps the relative velocity change near
@@ -117,7 +109,7 @@ def test_run_to_residual_freezes_each_sample(kernel):
                  accel=(1e-5, 0.0, 0.0))
     cases = [(p, m, r[:1] * 0 + 1.0, C) for p, m, r, C in cases]
     tol = 1e-5
-    b = _batch(cases, kernel=kernel)
+    b = _batch(cases)
     b.set_graph(True)
     ok, steps = b.run_to_residual(tol, 20000)
     assert ok
@@ -137,10 +129,9 @@ def test_run_to_residual_freezes_each_sample(kernel):
     b.close()
 
 
-@pytest.mark.parametrize("kernel", ["two_pass", "fused"])
-def test_batch_fp64_matches_oracle_per_sample(kernel):
+def test_batch_fp64_matches_oracle_per_sample():
     cases = _samples(2, seed=31, storage="f64")
-    b = _batch(cases, kernel=kernel)
+    b = _batch(cases)
     b.step(15)
     rhos, us, Cs = b.moments()
     for s, (p, mask, rho, C) in enumerate(cases):
@@ -159,9 +150,8 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     b = mclbm.Batch([c[0] for c in cases])
     b.set_geometry([c[1] for c in cases])
     cache = str(tmp_path / "tune.json")
-    kern, blk, grid, slab, ms = b.autotune(trial_steps=4, cache_path=cache)
-    assert slab == 0                                # no slab sweep for batches
-    assert kern in (0, 1) and blk in (64, 128, 256, 512) and grid % 8 == 0 and ms > 0
+    blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
+    assert blk in (64, 128, 256) and grid % 8 == 0 and ms > 0
     with pytest.raises(mclbm.MclbmError) as e:      # populations were overwritten
         b.step(1)
     assert e.value.code == mclbm.ESTATE
@@ -173,7 +163,7 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     # a second handle of the same class takes the cached shape without timing
     b2 = mclbm.Batch([c[0] for c in cases])
     b2.set_geometry([c[1] for c in cases])
-    assert b2.autotune(trial_steps=4, cache_path=cache) == (kern, blk, grid, slab, None)
+    assert b2.autotune(trial_steps=4, cache_path=cache) == (blk, grid, None)
     for x in (b, b2, ref):
         x.close()
 

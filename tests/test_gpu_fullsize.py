@@ -73,22 +73,18 @@ def test_full_size_sampled_step_matches_oracle(workload, storage, tol):
 def test_full_size_every_autotune_shape_is_bit_identical(workload):
     p, mask, m, rho, C = workload
     ref = None
-    shapes = [(0, 256, 0, 0)]
+    shapes = [(256, 0)]
     lat = mclbm.Lattice(p)
     lat.set_geometry(mask)
     *_, table = mclbm.autotune(lat.h, 1)
-    shapes += [(int(k), int(b), int(g), int(s)) for k, b, g, s, _ in table]
-    assert any(k == 1 for k, *_ in shapes) and any(s > 0 for *_, s in shapes)
-    for kern, blk, grid, slab in shapes:
-        lat.set_kernel(kern)
-        if kern == 0:
-            lat.set_launch(blk, grid)
-            lat.set_sweep(slab)
+    shapes += [(int(b), int(g)) for b, g, _ in table]
+    for blk, grid in shapes:
+        lat.set_launch(blk, grid)
         lat.init_fields(rho, None, C)
         lat.step(2)
         pops = lat.populations(raw=True)
         if ref is None:
             ref = pops
         else:
-            assert np.array_equal(pops, ref), (kern, blk, grid, slab)
+            assert np.array_equal(pops, ref), (blk, grid)
     lat.close()

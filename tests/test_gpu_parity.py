@@ -15,7 +15,7 @@ from helpers import gpu_lattice, nrel, oracle_state, small_porous, split_pops
 
 pytestmark = pytest.mark.gpu
 
-BLOCKS = [256, 64, "fused", "slab"]
+BLOCKS = [256, 64]
 
 
 @pytest.fixture(scope="module")
@@ -149,7 +149,7 @@ def test_launch_shapes_agree_bitwise():
     workgroup size cannot change a single bit."""
     p, mask, rho, u, C = small_porous(storage="f32", k_wall=0.05, C_in=1.0)
     out = []
-    for bs in (64, 128, 256, "fused", "slab"):
+    for bs in (64, 128, 256):
         lat = gpu_lattice(p, mask, rho, u, C, block=bs)
         lat.step(20)
         out.append(lat.populations(raw=True))
