@@ -5,9 +5,10 @@
  * solid mask and the initial phase field; the lattice Boltzmann solver then
  * starts from that prediction and remains the judge of convergence.  These
  * entry points are the layers of that network (a 3-D U-Net), written as HIP
- * kernels: 3-D convolutions as implicit GEMMs on BF16 matrix cores (MFMA,
- * FP32 accumulation), their data and weight gradients, pooling, upsampling,
- * channel concatenation, ReLU, the loss and the Adam update.
+ * kernels: 3-D convolutions on BF16 matrix cores (MFMA, FP32 accumulation)
+ * over 256-voxel bricks staged with their halo in LDS, their data and weight
+ * gradients, pooling, upsampling, channel concatenation, ReLU, the loss and
+ * the Adam update.
  *
  * Conventions:
  *   - every tensor pointer is device memory, FP32, channels-last
@@ -39,7 +40,9 @@ int wn_conv3d_fwd(const float* x, int n, int d, int h, int w, int ci, const floa
 int wn_conv3d_dgrad(const float* dy, int n, int d, int h, int w, int co, const float* W, int ci, int k, float* dx,
                     void* stream);
 
-/* Workspace bytes needed by wn_conv3d_wgrad for this shape. */
+/* Workspace bytes needed by wn_conv3d_wgrad for this shape (one FP32 dW per
+ * chunk of bricks; the chunk count depends only on the shape); 0 for an
+ * invalid shape. */
 size_t wn_wgrad_workspace_bytes(int n, int d, int h, int w, int ci, int co, int k);
 
 /* dW = d/dW sum(dy * conv3d(x, W)) (overwrites dW [co][k][k][k][ci]); split

@@ -1,21 +1,21 @@
 // Warm-start network layers on gfx950 (declarations and contract in include/warmnet.h).
 //
-// 3-D convolutions are implicit GEMMs on the BF16 matrix cores:
+// 3-D convolutions with periodic padding on the BF16 matrix cores:
 //   forward  Y[v][o]  = sum_{k,i} X[v + off_k][i] W[o][k][i]      M = voxels, N = c_out, K = 27 c_in
 //   dgrad    dX[v][i] = sum_{k,o} dY[v - off_k][o] W[o][k][i]     M = voxels, N = c_in,  K = 27 c_out
 //   wgrad    dW[o][k][i] = sum_v dY[v][o] X[v + off_k][i]         M = c_out,  N = c_in,  K = voxels
 // on v_mfma_f32_16x16x16_bf16 (a 16x16 FP32 tile from 16x16 BF16 operands;
 // lane l, q = l / 16, r = l % 16, supplies A[r][4q..4q+3] and B[4q..4q+3][r]
-// and receives D[4q + j][r], j = 0..3).  A workgroup computes a 64 x 64 output
-// tile; each K stage of the operands is rounded to BF16 (nearest even) once
-// and staged in LDS, and each of the four wavefronts runs 2 x 2 MFMA tiles on
-// it.  Accumulation stays FP32.  The weight gradient splits the voxel sum into
-// fixed chunks whose partial tiles are summed in chunk order by a second
-// kernel (deterministic).
+// and receives D[4q + j][r], j = 0..3).  Every operand is rounded to BF16
+// (nearest even) once, accumulation stays FP32.  The work is cut into bricks
+// of 256 voxels whose input, with its halo, is staged once in LDS (see the
+// brick kernels below).  The weight gradient sums over chunks of bricks and
+// adds the chunk sums in chunk order in a second kernel (deterministic).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 
 #include "warmnet.h"
@@ -60,242 +60,463 @@ __device__ __forceinline__ void koff(int kk, int k, int& dz, int& dy, int& dx) {
     dz = kk / (k * k) - r;
 }
 
-// weight gradients split the voxel sum into chunks of this many voxels
-constexpr int WG_CHUNK = 4096;
-
+// the weight gradient's partial sums (one per chunk of bricks) added in a
+// fixed order: block b owns 16 outputs; thread (e, c) = (t % 16, t / 16) adds
+// chunks c, c + 16, ... of output 16 b + e, then the 16 partials are added
+// in order
 __global__ void __launch_bounds__(256) sum_chunks(const float* __restrict__ part, int nchunk, long long n,
                                                   float* __restrict__ out) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float red[16][17];
+    const int t = threadIdx.x, e = t & 15, c0 = t >> 4;
+    const long long i = (long long)blockIdx.x * 16 + e;
     float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
-    out[i] = s;
+    if (i < n)
+        for (int c = c0; c < nchunk; c += 16) s += part[(size_t)c * n + i];
+    red[c0][e] = s;
+    __syncthreads();
+    if (c0 == 0 && i < n) {
+        float a = 0.f;
+        for (int j = 0; j < 16; ++j) a += red[j][e];
+        out[i] = a;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled implicit GEMMs (the paths the entry points use).  A workgroup of
-// four wavefronts computes a 64 x 64 output tile; per K stage the operands
-// (TK wide) are rounded to BF16 once, staged in LDS, and each wavefront runs
-// 2 x 2 MFMA 16x16x16 tiles on them (32 x 32 outputs per wavefront).
-// LDS rows are padded by 8 BF16 values against bank conflicts.
+// Brick convolutions.  The output is cut into bricks of 256 voxels
+// (bx x by x bz, chosen per shape; bricks at the far faces may stick out of
+// the volume and their outside voxels are neither stored nor summed).  A
+// workgroup stages the input around its brick, with the periodic one-voxel
+// halo, in LDS as BF16 (rounded once), one chunk of input channels at a time;
+// every tap then reads its MFMA operand from LDS at a constant offset, so each
+// input value leaves memory once per brick instead of once per tap.
 // ---------------------------------------------------------------------------
-constexpr int TM = 64, TN = 64;
+constexpr int BRICK = 256;
+constexpr int MAX_HALO = 600;   // halo voxels of a brick: 48 KB of BF16 staging at 32 channels
+constexpr int MAX_XS = 480;     // voxels of a weight-gradient brick's x-shifted input
+constexpr int W_LDS = 16384;    // bytes of staged BF16 weights per tap group
 
-template <int TK>
-struct Tiles {
-    static constexpr int LD = TK + 8;
-    short a[TM][LD];
-    short b[TN][LD];
+struct Brick {
+    int bx, by, bz;      // extents, bx * by * bz = BRICK, bx a multiple of 4
+    int nbx, nby, nbz;   // bricks per sample along x, y, z
 };
 
-// the 2 x 2 MFMA tiles of wavefront `wave` on one staged K chunk
-template <int TK>
-__device__ __forceinline__ void mma_stage(const Tiles<TK>& t, int wave, int q, int r, floatx4 (&acc)[2][2]) {
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+// smallest padded volume, then the smallest halo, then the longest x rows
+Brick choose_brick(int d, int h, int w) {
+    Brick best{};
+    long long best_vol = -1;
+    int best_halo = 0;
+    for (int bx = 32; bx >= 4; bx /= 2)
+        for (int by = 1; by <= 16; by *= 2) {
+            if (BRICK % (bx * by)) continue;
+            const int bz = BRICK / (bx * by);
+            if (bz > 16) continue;
+            const long long vol = (long long)((d + bz - 1) / bz) * bz * (long long)((h + by - 1) / by) * by *
+                                  (long long)((w + bx - 1) / bx) * bx;
+            const int halo = (bx + 2) * (by + 2) * (bz + 2);
+            if (halo > MAX_HALO || (bz + 2) * (by + 2) * bx > MAX_XS) continue;
+            if (best_vol < 0 || vol < best_vol || (vol == best_vol && halo < best_halo)) {
+                best = Brick{bx, by, bz, (w + bx - 1) / bx, (h + by - 1) / by, (d + bz - 1) / bz};
+                best_vol = vol;
+                best_halo = halo;
+            }
+        }
+    return best;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// blocks are dealt to the eight XCDs round robin; give each XCD a contiguous
+// run of logical blocks so that neighbouring bricks share that XCD's L2
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int per = G / 8;
+    return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
+__device__ __forceinline__ void brick_origin(const Brick& bk, int bi, int& b, int& z0, int& y0, int& x0) {
+    x0 = (bi % bk.nbx) * bk.bx;
+    bi /= bk.nbx;
+    y0 = (bi % bk.nby) * bk.by;
+    bi /= bk.nby;
+    z0 = (bi % bk.nbz) * bk.bz;
+    b = bi / bk.nbz;
+}
+
+// Convolution of X [V][C] into Y [V][N] (forward: C = c_in, N = c_out;
+// data gradient: X = dY, C = c_out, N = c_in, taps mirrored, W transposed).
+// W is the layer's [c_out][K^3][c_in] tensor.  A workgroup computes one brick
+// and 16 NR output channels; wavefront `wave` owns brick voxels
+// [64 wave, 64 wave + 64) as four MFMA row blocks.  Per chunk of CK input
+// channels the halo is staged once and the weights TPG taps at a time, as
+// BF16 fragments in MFMA lane order.  Each thread issues all of its staging
+// loads before it converts and stores any of them, so a stage costs one
+// memory latency; other workgroups on the CU overlap it.  (Prefetching the
+// next stage into registers during the matrix work was measured slower: the
+// extra registers halve the workgroups per CU.)
+template <int K, int CK, int NR>
+struct ConvCfg {
+    static constexpr int R = K / 2, K3 = K * K * K, LDA = CK + 8, C4 = CK / 4, KS = CK / 16;
+    static constexpr int TPG = K == 1                          ? 1
+                               : 27 * KS * NR * 64 * 8 <= W_LDS ? 27
+                               : 9 * KS * NR * 64 * 8 <= W_LDS  ? 9
+                                                                : 3;
+    static constexpr int NG = K3 / TPG;
+    static constexpr int WITEMS = TPG * KS * NR * 64;                 // bf16x4 fragments per group
+    static constexpr int WPT = (WITEMS + 255) / 256;                  // per thread
+    static constexpr int HMAX = K == 1 ? BRICK : MAX_HALO;
+    static constexpr int HPT = (HMAX * C4 + 255) / 256;               // halo float4 per thread
+    static constexpr size_t lds_bytes = (size_t)HMAX * LDA * 2 + (size_t)WITEMS * 8;
+};
+
+template <int K, int CK, int NR>
+__global__ void __launch_bounds__(256) conv_brick(const float* __restrict__ X, int C, Grid3 g, Brick bk,
+                                                  const float* __restrict__ W, int dgrad,
+                                                  const float* __restrict__ bias, int N, int relu,
+                                                  float* __restrict__ Y) {
+    using F = ConvCfg<K, CK, NR>;
+    static_assert(F::lds_bytes <= 65536 && F::WITEMS * 8 <= W_LDS, "conv_brick staging exceeds 64 KiB of LDS");
+    constexpr int R = F::R, K3 = F::K3, LDA = F::LDA, C4 = F::C4, KS = F::KS, TPG = F::TPG, NG = F::NG;
+    extern __shared__ short lds[];
+    short* halo = lds;                                   // [HV][LDA]
+    bf16x4* wl = (bf16x4*)(lds + F::HMAX * LDA);         // [TPG][KS][NR][64]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
+    const int ntn = (N + 16 * NR - 1) / (16 * NR);
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int n0 = (lb % ntn) * 16 * NR;
+    int b, z0, y0, x0;
+    brick_origin(bk, lb / ntn, b, z0, y0, x0);
+    const int HX = bk.bx + 2 * R, HY = bk.by + 2 * R, HV = HX * HY * (bk.bz + 2 * R);
+    const bool vec = (C & 3) == 0;
+
+    float4 hreg[F::HPT];
+    auto load_halo = [&](int c0) {
 #pragma unroll
-    for (int ks = 0; ks < TK; ks += 16) {
-        bf16x4 af[2], bfr[2];
+        for (int j = 0; j < F::HPT; ++j) {
+            const int it = tid + 256 * j;
+            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (it < HV * C4) {
+                const int hv = it / C4, c = c0 + (it % C4) * 4;
+                const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+                const long long vox =
+                    ((long long)(b * g.d + wrap(z0 + hz - R, g.d)) * g.h + wrap(y0 + hy - R, g.h)) * g.w +
+                    wrap(x0 + hx - R, g.w);
+                const float* src = X + vox * C + c;
+                if (vec && c + 3 < C) {
+                    t = *(const float4*)src;
+                } else {
+                    t.x = c < C ? src[0] : 0.f;
+                    t.y = c + 1 < C ? src[1] : 0.f;
+                    t.z = c + 2 < C ? src[2] : 0.f;
+                    t.w = c + 3 < C ? src[3] : 0.f;
+                }
+            }
+            hreg[j] = t;
+        }
+    };
+    auto store_halo = [&]() {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = *(const bf16x4*)&t.a[wm + i * 16 + r][ks + 4 * q];
+        for (int j = 0; j < F::HPT; ++j) {
+            const int it = tid + 256 * j;
+            if (it < HV * C4) {
+                bf16x4 o;
+                o[0] = to_bf16(hreg[j].x), o[1] = to_bf16(hreg[j].y), o[2] = to_bf16(hreg[j].z),
+                o[3] = to_bf16(hreg[j].w);
+                *(bf16x4*)&halo[(it / C4) * LDA + (it % C4) * 4] = o;
+            }
+        }
+    };
+    float4 wreg[F::WPT];
+    auto load_w = [&](int c0, int grp) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bfr[j] = *(const bf16x4*)&t.b[wn + j * 16 + r][ks + 4 * q];
+        for (int j = 0; j < F::WPT; ++j) {
+            const int it = tid + 256 * j;
+            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (it < F::WITEMS) {
+                const int l = it & 63, nb = (it >> 6) % NR, ks = (it >> 6) / NR % KS, tt = (it >> 6) / NR / KS;
+                const int kk = grp * TPG + tt;
+                const int n = n0 + nb * 16 + (l & 15), cb = c0 + ks * 16 + 4 * (l >> 4);
+                float v[4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int c = cb + jj;
+                    v[jj] = !(n < N && c < C) ? 0.f
+                            : dgrad           ? W[((size_t)c * K3 + (K3 - 1 - kk)) * N + n]
+                                              : W[((size_t)n * K3 + kk) * C + c];
+                }
+                t = make_float4(v[0], v[1], v[2], v[3]);
+            }
+            wreg[j] = t;
+        }
+    };
+    auto store_w = [&]() {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < F::WPT; ++j) {
+            const int it = tid + 256 * j;
+            if (it < F::WITEMS) {
+                bf16x4 o;
+                o[0] = to_bf16(wreg[j].x), o[1] = to_bf16(wreg[j].y), o[2] = to_bf16(wreg[j].z),
+                o[3] = to_bf16(wreg[j].w);
+                wl[it] = o;
+            }
+        }
+    };
+
+    int hv0[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        const int m = wave * 64 + mb * 16 + r;
+        const int mx = m % bk.bx, my = (m / bk.bx) % bk.by, mz = m / (bk.bx * bk.by);
+        hv0[mb] = ((mz + R) * HY + my + R) * HX + mx + R;
+    }
+    floatx4 acc[4][NR] = {};
+    for (int c0 = 0; c0 < C; c0 += CK) {
+        for (int grp = 0; grp < NG; ++grp) {
+            if (grp == 0) load_halo(c0);
+            load_w(c0, grp);
+            __syncthreads();
+            if (grp == 0) store_halo();
+            store_w();
+            __syncthreads();
+#pragma unroll 1
+            for (int tt = 0; tt < TPG; ++tt) {
+                int dz, dy, dx;
+                koff(grp * TPG + tt, K, dz, dy, dx);
+                const int toff = (dz * HY + dy) * HX + dx;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    bf16x4 bf[NR];
+#pragma unroll
+                    for (int nb = 0; nb < NR; ++nb) bf[nb] = wl[((tt * KS + ks) * NR + nb) * 64 + lane];
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb) {
+                        const bf16x4 af = *(const bf16x4*)&halo[(hv0[mb] + toff) * LDA + ks * 16 + 4 * q];
+#pragma unroll
+                        for (int nb = 0; nb < NR; ++nb)
+                            acc[mb][nb] =
+                                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[nb], acc[mb][nb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NR; ++nb) {
+        const int n = n0 + nb * 16 + r;
+        if (n >= N) continue;
+        const float bb = bias ? bias[n] : 0.f;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = wave * 64 + mb * 16 + 4 * q + j;
+                const int x = x0 + m % bk.bx, y = y0 + (m / bk.bx) % bk.by, z = z0 + m / (bk.bx * bk.by);
+                if (x >= g.w || y >= g.h || z >= g.d) continue;
+                float val = acc[mb][nb][j] + bb;
+                if (relu) val = val > 0.f ? val : 0.f;
+                Y[(((long long)(b * g.d + z) * g.h + y) * g.w + x) * N + n] = val;
+            }
     }
 }
 
-// forward: M = voxels, N = c_out, K = (offset, c_in)
-template <int TK>
-__global__ void __launch_bounds__(256) conv_fwd_t(const float* __restrict__ X, Grid3 g, int V, int ci,
-                                                  const float* __restrict__ W, const float* __restrict__ bias, int co,
-                                                  int k, int relu, float* __restrict__ Y) {
-    __shared__ Tiles<TK> t;
-    constexpr int PER = TK / 4;   // values staged per thread and row (64 rows x TK = 256 threads x PER)
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
-    const int ntn = (co + TN - 1) / TN;
-    const int m0 = (blockIdx.x / ntn) * TM, n0 = (blockIdx.x % ntn) * TN;
-    const int K3 = k * k * k;
-    const int srow = tid >> 2, scol = (tid & 3) * PER;
-    const int sv = m0 + srow, so = n0 + srow;
-    floatx4 acc[2][2] = {};
-    for (int kk = 0; kk < K3; ++kk) {
-        int dz, dy, dx;
-        koff(kk, k, dz, dy, dx);
-        const int vs = sv < V ? g.shift(sv, dz, dy, dx) : 0;
-        for (int c0 = 0; c0 < ci; c0 += TK) {
-            short av[PER], bv[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int c = c0 + scol + j;
-                av[j] = to_bf16((sv < V && c < ci) ? X[(size_t)vs * ci + c] : 0.f);
-                bv[j] = to_bf16((so < co && c < ci) ? W[((size_t)so * K3 + kk) * ci + c] : 0.f);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                t.a[srow][scol + j] = av[j];
-                t.b[srow][scol + j] = bv[j];
-            }
-            __syncthreads();
-            mma_stage<TK>(t, wave, q, r, acc);
-        }
-    }
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int o = n0 + wn + j * 16 + r;
-        if (o >= co) continue;
-        const float bb = bias ? bias[o] : 0.f;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int v = m0 + wm + i * 16 + 4 * q + e;
-                if (v >= V) continue;
-                float y = acc[i][j][e] + bb;
-                if (relu) y = y > 0.f ? y : 0.f;
-                Y[(size_t)v * co + o] = y;
-            }
-    }
-}
+// Weight gradient dW[o][tap][i] = sum_v dY[v][o] X[v + off(tap)][i].
+// MFMA M = output channels (16 MO per workgroup), N = input channels (16 NI),
+// K = voxels of a brick, in groups of four along x.  A workgroup owns one x
+// offset dx of the taps (the nine (dz, dy) taps sharing it), so the input is
+// staged with that x shift applied and every operand read stays aligned.
+// Wavefront `wave` takes the voxel groups 16 (wave + 4 j) of every brick.
+// The four wavefronts' sums are added in LDS in wavefront order and the
+// chunk's sum goes to part[chunk][o][tap][i].
+template <int K, int MO, int NI>
+struct WgradCfg {
+    static constexpr int R = K / 2, K3 = K * K * K, T = K == 3 ? 9 : 1, NDX = K == 3 ? 3 : 1;
+    static constexpr int LDY = BRICK + 4;
+    static constexpr int XMAX = K == 1 ? BRICK : MAX_XS;
+    static constexpr int YPT = BRICK * 4 * MO / 256;                  // dY float4 per thread
+    static constexpr int XPT = (XMAX * 4 * NI + 255) / 256;           // X float4 per thread
+    static constexpr size_t stage_bytes = ((size_t)16 * MO * LDY + (size_t)16 * NI * (XMAX + 4)) * 2;
+    static constexpr size_t red_bytes = (size_t)T * MO * NI * 256 * 4;
+    static constexpr size_t lds_bytes = stage_bytes > red_bytes ? stage_bytes : red_bytes;
+};
 
-// data gradient: M = voxels, N = c_in, K = (offset, c_out)
-template <int TK>
-__global__ void __launch_bounds__(256) conv_dgrad_t(const float* __restrict__ dY, Grid3 g, int V, int co,
-                                                    const float* __restrict__ W, int ci, int k,
-                                                    float* __restrict__ dX) {
-    __shared__ Tiles<TK> t;
-    constexpr int PER = TK / 4;
+template <int K, int MO, int NI>
+__global__ void __launch_bounds__(256) wgrad_brick(const float* __restrict__ X, int ci,
+                                                   const float* __restrict__ dY, int co, Grid3 g, Brick bk,
+                                                   int bricks_per_chunk, int nbricks, float* __restrict__ part) {
+    using F = WgradCfg<K, MO, NI>;
+    static_assert(F::lds_bytes <= 65536, "wgrad_brick staging exceeds 64 KiB of LDS");
+    constexpr int R = F::R, K3 = F::K3, T = F::T, NDX = F::NDX, LDY = F::LDY;
+    extern __shared__ short lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
-    const int ntn = (ci + TN - 1) / TN;
-    const int m0 = (blockIdx.x / ntn) * TM, n0 = (blockIdx.x % ntn) * TN;
-    const int K3 = k * k * k;
-    const int srow = tid >> 2, scol = (tid & 3) * PER;   // A staging: voxel row, c_out columns
-    const int sv = m0 + srow;
-    // B staging: TK c_out rows of W (contiguous in c_in) -> t.b[c_in][c_out]
-    constexpr int BPER = TN * TK / 256;                   // c_in values per thread
-    const int bo = tid / (TN / BPER), bi = (tid % (TN / BPER)) * BPER;
-    floatx4 acc[2][2] = {};
-    for (int kk = 0; kk < K3; ++kk) {
-        int dz, dy, dx;
-        koff(kk, k, dz, dy, dx);
-        const int vs = sv < V ? g.shift(sv, -dz, -dy, -dx) : 0;
-        for (int c0 = 0; c0 < co; c0 += TK) {
-            short av[PER], bv[BPER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int o = c0 + scol + j;
-                av[j] = to_bf16((sv < V && o < co) ? dY[(size_t)vs * co + o] : 0.f);
-            }
-            const int o = c0 + bo;
-#pragma unroll
-            for (int j = 0; j < BPER; ++j) {
-                const int i = n0 + bi + j;
-                bv[j] = to_bf16((o < co && i < ci) ? W[((size_t)o * K3 + kk) * ci + i] : 0.f);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < PER; ++j) t.a[srow][scol + j] = av[j];
-#pragma unroll
-            for (int j = 0; j < BPER; ++j) t.b[bi + j][bo] = bv[j];
-            __syncthreads();
-            mma_stage<TK>(t, wave, q, r, acc);
-        }
-    }
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int i = n0 + wn + j * 16 + r;
-        if (i >= ci) continue;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int v = m0 + wm + a * 16 + 4 * q + e;
-                if (v < V) dX[(size_t)v * ci + i] = acc[a][j][e];
-            }
-    }
-}
+    const int nci = (ci + 16 * NI - 1) / (16 * NI), nco = (co + 16 * MO - 1) / (16 * MO);
+    int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int cot = lb % nco;
+    lb /= nco;
+    const int cit = lb % nci;
+    lb /= nci;
+    const int dx = lb % NDX - R;
+    const int chunk = lb / NDX;
+    const int o0 = cot * 16 * MO, i0 = cit * 16 * NI;
+    const int HY = bk.by + 2 * R, XS = (bk.bz + 2 * R) * HY * bk.bx, LDX = XS + 4;
+    short* dyt = lds;                       // [16 MO][LDY]
+    short* xs = lds + 16 * MO * LDY;        // [16 NI][LDX]
+    const bool vy = (co & 3) == 0, vx = (ci & 3) == 0;
 
-// weight gradient: M = c_out, N = c_in, K = voxels of one chunk; one offset per
-// workgroup; partial[chunk][o][kk][i]
-__global__ void __launch_bounds__(256) conv_wgrad_t(const float* __restrict__ X, const float* __restrict__ dY,
-                                                    Grid3 g, int V, int ci, int co, int k,
-                                                    float* __restrict__ part) {
-    constexpr int TK = 32;
-    __shared__ Tiles<TK> t;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r = lane & 15;
-    const int K3 = k * k * k;
-    const int nmt = (co + TM - 1) / TM, nnt = (ci + TN - 1) / TN;
-    int b = blockIdx.x;
-    const int mt = b % nmt;
-    b /= nmt;
-    const int nt = b % nnt;
-    b /= nnt;
-    const int kk = b % K3;
-    const int ch = b / K3;
-    const int m0 = mt * TM, n0 = nt * TN;
-    int dz, dy, dx;
-    koff(kk, k, dz, dy, dx);
-    // staging: voxel row tid / 8 (32 voxels per stage), 8 channels at (tid % 8) * 8, written transposed
-    const int sv = tid >> 3, sc = (tid & 7) * 8;
-    const int vbeg = ch * WG_CHUNK, vend = min(V, vbeg + WG_CHUNK);
-    floatx4 acc[2][2] = {};
-    for (int v0 = vbeg; v0 < vend; v0 += TK) {
-        const int v = v0 + sv;
-        const bool ok = v < vend;
-        const int vs = ok ? g.shift(v, dz, dy, dx) : 0;
-        short av[8], bv[8];
+    float4 yreg[F::YPT], xreg[F::XPT];
+    auto load_brick = [&](int bi) {
+        int b, z0, y0, x0;
+        brick_origin(bk, bi, b, z0, y0, x0);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int o = m0 + sc + j, i = n0 + sc + j;
-            av[j] = to_bf16((ok && o < co) ? dY[(size_t)v * co + o] : 0.f);
-            bv[j] = to_bf16((ok && i < ci) ? X[(size_t)vs * ci + i] : 0.f);
+        for (int j = 0; j < F::YPT; ++j) {
+            const int it = tid + 256 * j;
+            const int m = it / (4 * MO), o = o0 + 4 * (it % (4 * MO));
+            const int x = x0 + m % bk.bx, y = y0 + (m / bk.bx) % bk.by, z = z0 + m / (bk.bx * bk.by);
+            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (x < g.w && y < g.h && z < g.d) {
+                const float* src = dY + (((long long)(b * g.d + z) * g.h + y) * g.w + x) * co + o;
+                if (vy && o + 3 < co) {
+                    t = *(const float4*)src;
+                } else {
+                    t.x = o < co ? src[0] : 0.f;
+                    t.y = o + 1 < co ? src[1] : 0.f;
+                    t.z = o + 2 < co ? src[2] : 0.f;
+                    t.w = o + 3 < co ? src[3] : 0.f;
+                }
+            }
+            yreg[j] = t;
         }
+#pragma unroll
+        for (int j = 0; j < F::XPT; ++j) {
+            const int it = tid + 256 * j;
+            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (it < XS * 4 * NI) {
+                const int p = it / (4 * NI), i = i0 + 4 * (it % (4 * NI));
+                const int px = p % bk.bx, py = (p / bk.bx) % HY, pz = p / (bk.bx * HY);
+                const long long vox =
+                    ((long long)(b * g.d + wrap(z0 + pz - R, g.d)) * g.h + wrap(y0 + py - R, g.h)) * g.w +
+                    wrap(x0 + px + dx, g.w);
+                const float* src = X + vox * ci + i;
+                if (vx && i + 3 < ci) {
+                    t = *(const float4*)src;
+                } else {
+                    t.x = i < ci ? src[0] : 0.f;
+                    t.y = i + 1 < ci ? src[1] : 0.f;
+                    t.z = i + 2 < ci ? src[2] : 0.f;
+                    t.w = i + 3 < ci ? src[3] : 0.f;
+                }
+            }
+            xreg[j] = t;
+        }
+    };
+    auto store_brick = [&]() {
+#pragma unroll
+        for (int j = 0; j < F::YPT; ++j) {
+            const int it = tid + 256 * j;
+            const int m = it / (4 * MO), o = 4 * (it % (4 * MO));
+            dyt[(o + 0) * LDY + m] = to_bf16(yreg[j].x);
+            dyt[(o + 1) * LDY + m] = to_bf16(yreg[j].y);
+            dyt[(o + 2) * LDY + m] = to_bf16(yreg[j].z);
+            dyt[(o + 3) * LDY + m] = to_bf16(yreg[j].w);
+        }
+#pragma unroll
+        for (int j = 0; j < F::XPT; ++j) {
+            const int it = tid + 256 * j;
+            if (it < XS * 4 * NI) {
+                const int p = it / (4 * NI), i = 4 * (it % (4 * NI));
+                xs[(i + 0) * LDX + p] = to_bf16(xreg[j].x);
+                xs[(i + 1) * LDX + p] = to_bf16(xreg[j].y);
+                xs[(i + 2) * LDX + p] = to_bf16(xreg[j].z);
+                xs[(i + 3) * LDX + p] = to_bf16(xreg[j].w);
+            }
+        }
+    };
+
+    floatx4 acc[T][MO][NI] = {};
+    const int bbeg = chunk * bricks_per_chunk, bend = min(nbricks, bbeg + bricks_per_chunk);
+    for (int bi = bbeg; bi < bend; ++bi) {
+        load_brick(bi);
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            t.a[sc + j][sv] = av[j];
-            t.b[sc + j][sv] = bv[j];
-        }
+        store_brick();
         __syncthreads();
-        mma_stage<TK>(t, wave, q, r, acc);
-    }
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+#pragma unroll 1
+        for (int kq = wave; kq < BRICK / 16; kq += 4) {
+            const int m = kq * 16 + 4 * q;   // first of this lane's four voxels (one x row)
+            const int mx = m % bk.bx, my = (m / bk.bx) % bk.by, mz = m / (bk.bx * bk.by);
+            bf16x4 af[MO];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int i = n0 + wn + j * 16 + r;
-        if (i >= ci) continue;
+            for (int mo = 0; mo < MO; ++mo) af[mo] = *(const bf16x4*)&dyt[(mo * 16 + r) * LDY + m];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int t = 0; t < T; ++t) {
+                const int dz = K == 3 ? t / 3 - 1 : 0, dy = K == 3 ? t % 3 - 1 : 0;
+                const int p = ((mz + dz + R) * HY + my + dy + R) * bk.bx + mx;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int o = m0 + wm + a * 16 + 4 * q + e;
-                if (o < co) part[(((size_t)ch * co + o) * K3 + kk) * ci + i] = acc[a][j][e];
+                for (int ni = 0; ni < NI; ++ni) {
+                    const bf16x4 bfr = *(const bf16x4*)&xs[(ni * 16 + r) * LDX + p];
+#pragma unroll
+                    for (int mo = 0; mo < MO; ++mo)
+                        acc[t][mo][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[mo], bfr, acc[t][mo][ni], 0, 0, 0);
+                }
             }
+        }
+    }
+    // add the four wavefronts' sums in wavefront order
+    float* red = (float*)lds;
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int mo = 0; mo < MO; ++mo)
+#pragma unroll
+                    for (int ni = 0; ni < NI; ++ni) {
+                        float* dst = red + ((t * MO + mo) * NI + ni) * 256 + lane * 4;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) dst[j] = w == 0 ? acc[t][mo][ni][j] : dst[j] + acc[t][mo][ni][j];
+                    }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < T * MO * NI * 256; e += 256) {
+        const int tile = e / 256, l = (e % 256) / 4, j = e % 4;
+        const int ni = tile % NI, mo = (tile / NI) % MO, t = tile / (NI * MO);
+        const int o = o0 + mo * 16 + 4 * (l >> 4) + j, i = i0 + ni * 16 + (l & 15);
+        if (o >= co || i >= ci) continue;
+        const int kk = K == 3 ? t * 3 + dx + 1 : 0;
+        part[(((size_t)chunk * co + o) * K3 + kk) * ci + i] = red[e];
     }
 }
 
 // ---------------------------------------------------------------------------
 // small layers
 // ---------------------------------------------------------------------------
-// bias gradient, stage 1: block b sums rows [b * BG_ROWS, ...) of dy [V][co];
-// thread t owns column t % co of rows t / co + j * (256 / co), so each pass
-// reads a contiguous run of whole rows; partial[b][o] in fixed order
-constexpr int BG_ROWS = 512;
+// bias gradient, stage 1: thread t owns column t % co (co <= 256) and every
+// (256 / co)-th row from t / co on, BG_PER rows in all (independent loads);
+// the block's BG_PER * (256 / co) rows are summed in LDS in a fixed order
+// into part[block][o]
+constexpr int BG_PER = 16;
+
+__host__ __device__ inline long long bg_rows(int co) { return (long long)BG_PER * (256 / co); }
 
 __global__ void __launch_bounds__(256) bias_grad_part(const float* __restrict__ dy, long long V, int co,
                                                       float* __restrict__ part) {
     __shared__ float red[256];
     const int t = threadIdx.x;
-    const int rpp = 256 / co;                // rows per pass (co <= 256)
+    const int rpp = 256 / co;
     const int o = t % co, r = t / co;
-    const long long v0 = (long long)blockIdx.x * BG_ROWS, v1 = min(V, v0 + BG_ROWS);
+    const long long v0 = (long long)blockIdx.x * bg_rows(co);
     float s = 0.f;
-    if (r < rpp)
-        for (long long v = v0 + r; v < v1; v += rpp) s += dy[v * co + o];
+    if (r < rpp) {
+        float v[BG_PER];
+#pragma unroll
+        for (int j = 0; j < BG_PER; ++j) {
+            const long long row = v0 + r + (long long)j * rpp;
+            v[j] = row < V ? dy[row * co + o] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < BG_PER; ++j) s += v[j];
+    }
     red[t] = s;
     __syncthreads();
     if (t < co) {
@@ -305,13 +526,20 @@ __global__ void __launch_bounds__(256) bias_grad_part(const float* __restrict__ 
     }
 }
 
+// stage 2: block o adds part[.][o] (strided per thread, then a fixed tree)
 __global__ void __launch_bounds__(256) bias_grad_final(const float* __restrict__ part, int nblk, int co,
                                                        float* __restrict__ db) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= co) return;
+    __shared__ float red[256];
+    const int o = blockIdx.x, t = threadIdx.x;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * co + o];
-    db[o] = s;
+    for (int b = t; b < nblk; b += 256) s += part[(size_t)b * co + o];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) db[o] = red[0];
 }
 
 __global__ void __launch_bounds__(256) relu_bwd_k(const float* __restrict__ y, float* __restrict__ g, long long n) {
@@ -505,66 +733,143 @@ bool shape_ok(int n, int d, int h, int w, int c) {
     return V % 16 == 0 && V * c < (1LL << 31);
 }
 
+// ---- convolution launch plans --------------------------------------------
+template <int K, int CK, int NR>
+void conv_go(const float* X, int C, Grid3 g, Brick bk, const float* W, int dgrad, const float* bias, int N, int relu,
+             float* Y, int blocks, hipStream_t st) {
+    const size_t bytes = ConvCfg<K, CK, NR>::lds_bytes;
+    hipLaunchKernelGGL((conv_brick<K, CK, NR>), dim3(blocks), dim3(256), bytes, st, X, C, g, bk, W, dgrad, bias, N,
+                       relu, Y);
+}
+
+template <int K, int CK>
+void conv_nr(int NR, const float* X, int C, Grid3 g, Brick bk, const float* W, int dgrad, const float* bias, int N,
+             int relu, float* Y, int blocks, hipStream_t st) {
+    switch (NR) {
+        case 1: conv_go<K, CK, 1>(X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st); break;
+        case 2: conv_go<K, CK, 2>(X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st); break;
+        case 3: conv_go<K, CK, 3>(X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st); break;
+        default: conv_go<K, CK, 4>(X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st); break;
+    }
+}
+
+// channel chunk: 32 unless that pads C further than 16 does; output tile:
+// up to 64 channels, split into 16-channel tiles when the bricks alone leave
+// the chip with too few workgroups
+void launch_conv(const float* X, int C, Grid3 g, const float* W, int dgrad, const float* bias, int N, int k, int relu,
+                 float* Y, hipStream_t st) {
+    const Brick bk = choose_brick(g.d, g.h, g.w);
+    const int nbricks = g.n * bk.nbx * bk.nby * bk.nbz;
+    const int nb16 = (N + 15) / 16;
+    int ntile = (nb16 + 3) / 4;
+    int NR = (nb16 + ntile - 1) / ntile;
+    if (nbricks * ntile < 1024) {
+        NR = 1;
+        ntile = nb16;
+    }
+    const int blocks = nbricks * ntile;
+    const bool ck32 = (C + 31) / 32 * 32 == (C + 15) / 16 * 16;
+    if (k == 3) {
+        if (ck32) conv_nr<3, 32>(NR, X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st);
+        else conv_nr<3, 16>(NR, X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st);
+    } else {
+        if (ck32) conv_nr<1, 32>(NR, X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st);
+        else conv_nr<1, 16>(NR, X, C, g, bk, W, dgrad, bias, N, relu, Y, blocks, st);
+    }
+}
+
+struct WgradPlan {
+    Brick bk;
+    int MO, NI, nbricks, bricks_per_chunk, nchunk, blocks;
+};
+
+// output-channel tile 16 MO (MO in 1, 2, 4) and input-channel chunk 16 NI
+// (NI in 1, 2; 1 when MO = 4), the one padding c_in least; about a thousand
+// workgroups, each summing a run of consecutive bricks
+WgradPlan wgrad_plan(int n, int d, int h, int w, int ci, int co, int k) {
+    WgradPlan p;
+    p.bk = choose_brick(d, h, w);
+    p.nbricks = n * p.bk.nbx * p.bk.nby * p.bk.nbz;
+    const int cb = (co + 15) / 16;
+    p.MO = cb == 1 ? 1 : cb == 2 ? 2 : 4;
+    p.NI = 1;
+    if (p.MO < 4 && (ci + 31) / 32 * 32 == (ci + 15) / 16 * 16) p.NI = 2;
+    const int nci = (ci + 16 * p.NI - 1) / (16 * p.NI), nco = (co + 16 * p.MO - 1) / (16 * p.MO);
+    const int per = (k == 3 ? 3 : 1) * nci * nco;
+    const int target = std::max(1, 1024 / per);
+    p.bricks_per_chunk = (p.nbricks + target - 1) / target;
+    p.nchunk = (p.nbricks + p.bricks_per_chunk - 1) / p.bricks_per_chunk;
+    p.blocks = p.nchunk * per;
+    return p;
+}
+
+template <int K, int MO, int NI>
+void wgrad_go(const WgradPlan& pl, const float* X, int ci, const float* dY, int co, Grid3 g, float* part,
+              hipStream_t st) {
+    const size_t bytes = WgradCfg<K, MO, NI>::lds_bytes;
+    hipLaunchKernelGGL((wgrad_brick<K, MO, NI>), dim3(pl.blocks), dim3(256), bytes, st, X, ci, dY, co, g, pl.bk,
+                       pl.bricks_per_chunk, pl.nbricks, part);
+}
+
+template <int K>
+void wgrad_k(const WgradPlan& pl, const float* X, int ci, const float* dY, int co, Grid3 g, float* part,
+             hipStream_t st) {
+    if (pl.MO == 1 && pl.NI == 1) wgrad_go<K, 1, 1>(pl, X, ci, dY, co, g, part, st);
+    else if (pl.MO == 1) wgrad_go<K, 1, 2>(pl, X, ci, dY, co, g, part, st);
+    else if (pl.MO == 2 && pl.NI == 1) wgrad_go<K, 2, 1>(pl, X, ci, dY, co, g, part, st);
+    else if (pl.MO == 2) wgrad_go<K, 2, 2>(pl, X, ci, dY, co, g, part, st);
+    else wgrad_go<K, 4, 1>(pl, X, ci, dY, co, g, part, st);
+}
+
+void launch_wgrad(const WgradPlan& pl, const float* X, int ci, const float* dY, int co, Grid3 g, int k, float* part,
+                  hipStream_t st) {
+    if (k == 3) wgrad_k<3>(pl, X, ci, dY, co, g, part, st);
+    else wgrad_k<1>(pl, X, ci, dY, co, g, part, st);
+}
+
 }  // namespace
 
 extern "C" {
 
 int wn_conv3d_fwd(const float* x, int n, int d, int h, int w, int ci, const float* W, const float* b, int co, int k,
                   int relu, float* y, void* stream) {
-    if (!x || !W || !y || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || co < 1)
+    if (!x || !W || !y || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || !shape_ok(n, d, h, w, co))
         return err(-1, "wn_conv3d_fwd: bad arguments");
-    const int V = n * d * h * w;
-    const unsigned blocks = (unsigned)(((V + TM - 1) / TM) * ((co + TN - 1) / TN));
-    if (ci <= 16)
-        hipLaunchKernelGGL(conv_fwd_t<16>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, x, Grid3{n, d, h, w}, V,
-                           ci, W, b, co, k, relu, y);
-    else
-        hipLaunchKernelGGL(conv_fwd_t<32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, x, Grid3{n, d, h, w}, V,
-                           ci, W, b, co, k, relu, y);
+    launch_conv(x, ci, Grid3{n, d, h, w}, W, 0, b, co, k, relu, y, (hipStream_t)stream);
     return hip_result("conv_fwd");
 }
 
 int wn_conv3d_dgrad(const float* dy, int n, int d, int h, int w, int co, const float* W, int ci, int k, float* dx,
                     void* stream) {
-    if (!dy || !W || !dx || (k != 1 && k != 3) || !shape_ok(n, d, h, w, co) || ci < 1)
+    if (!dy || !W || !dx || (k != 1 && k != 3) || !shape_ok(n, d, h, w, co) || !shape_ok(n, d, h, w, ci))
         return err(-1, "wn_conv3d_dgrad: bad arguments");
-    const int V = n * d * h * w;
-    const unsigned blocks = (unsigned)(((V + TM - 1) / TM) * ((ci + TN - 1) / TN));
-    if (co <= 16)
-        hipLaunchKernelGGL(conv_dgrad_t<16>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, dy, Grid3{n, d, h, w},
-                           V, co, W, ci, k, dx);
-    else
-        hipLaunchKernelGGL(conv_dgrad_t<32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, dy, Grid3{n, d, h, w},
-                           V, co, W, ci, k, dx);
+    launch_conv(dy, co, Grid3{n, d, h, w}, W, 1, nullptr, ci, k, 0, dx, (hipStream_t)stream);
     return hip_result("conv_dgrad");
 }
 
 size_t wn_wgrad_workspace_bytes(int n, int d, int h, int w, int ci, int co, int k) {
-    const long long V = (long long)n * d * h * w;
-    const long long nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
-    return (size_t)nchunk * co * k * k * k * ci * sizeof(float);
+    if (n < 1 || d < 1 || h < 1 || w < 1 || ci < 1 || co < 1 || (k != 1 && k != 3)) return 0;
+    const WgradPlan pl = wgrad_plan(n, d, h, w, ci, co, k);
+    return (size_t)pl.nchunk * co * k * k * k * ci * sizeof(float);
 }
 
 int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w, int ci, int co, int k, float* dW,
                     void* workspace, size_t workspace_bytes, void* stream) {
-    if (!x || !dy || !dW || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || co < 1)
+    if (!x || !dy || !dW || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || !shape_ok(n, d, h, w, co))
         return err(-1, "wn_conv3d_wgrad: bad arguments");
     if (!workspace || workspace_bytes < wn_wgrad_workspace_bytes(n, d, h, w, ci, co, k))
         return err(-1, "wn_conv3d_wgrad: workspace too small");
-    const int V = n * d * h * w;
-    const int K3 = k * k * k;
-    const int nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
-    const long long blocks = (long long)((co + TM - 1) / TM) * ((ci + TN - 1) / TN) * K3 * nchunk;
-    hipLaunchKernelGGL(conv_wgrad_t, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, x, dy,
-                       Grid3{n, d, h, w}, V, ci, co, k, (float*)workspace);
-    const long long nw = (long long)co * K3 * ci;
-    hipLaunchKernelGGL(sum_chunks, blocks_for(nw), dim3(256), 0, (hipStream_t)stream, (const float*)workspace,
-                       nchunk, nw, dW);
+    const WgradPlan pl = wgrad_plan(n, d, h, w, ci, co, k);
+    launch_wgrad(pl, x, ci, dy, co, Grid3{n, d, h, w}, k, (float*)workspace, (hipStream_t)stream);
+    const long long nw = (long long)co * k * k * k * ci;
+    hipLaunchKernelGGL(sum_chunks, dim3((unsigned)((nw + 15) / 16)), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)workspace, pl.nchunk, nw, dW);
     return hip_result("conv_wgrad");
 }
 
 size_t wn_bias_grad_workspace_bytes(long long V, int co) {
-    return (size_t)((V + BG_ROWS - 1) / BG_ROWS) * (size_t)(co > 0 ? co : 0) * sizeof(float);
+    if (V < 1 || co < 1 || co > 256) return 0;
+    return (size_t)((V + bg_rows(co) - 1) / bg_rows(co)) * (size_t)co * sizeof(float);
 }
 
 int wn_bias_grad(const float* dy, long long V, int co, float* db, void* workspace, size_t workspace_bytes,
@@ -572,10 +877,12 @@ int wn_bias_grad(const float* dy, long long V, int co, float* db, void* workspac
     if (!dy || !db || V < 1 || co < 1 || co > 256) return err(-1, "wn_bias_grad: bad arguments");
     if (!workspace || workspace_bytes < wn_bias_grad_workspace_bytes(V, co))
         return err(-1, "wn_bias_grad: workspace too small");
-    const int nblk = (int)((V + BG_ROWS - 1) / BG_ROWS);
-    hipLaunchKernelGGL(bias_grad_part, dim3(nblk), dim3(256), 0, (hipStream_t)stream, dy, V, co, (float*)workspace);
-    hipLaunchKernelGGL(bias_grad_final, dim3((co + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                       (const float*)workspace, nblk, co, db);
+    const long long nblk = (V + bg_rows(co) - 1) / bg_rows(co);
+    if (nblk > (1LL << 31) - 1) return err(-1, "wn_bias_grad: too many voxels");
+    hipLaunchKernelGGL(bias_grad_part, dim3((unsigned)nblk), dim3(256), 0, (hipStream_t)stream, dy, V, co,
+                       (float*)workspace);
+    hipLaunchKernelGGL(bias_grad_final, dim3(co), dim3(256), 0, (hipStream_t)stream, (const float*)workspace,
+                       (int)nblk, co, db);
     return hip_result("bias_grad");
 }
 

@@ -357,6 +357,29 @@ class UNet:
             for p, g, m, v in l.params():
                 adam(p, g, m, v, lr, self.step_count)
 
+    def save(self, path):
+        """Weights and biases as a plain .npz (no pickled objects)."""
+        arrs = {}
+        for i, l in enumerate(self.layers()):
+            arrs[f"W{i}"] = l.W.cpu().numpy()
+            arrs[f"b{i}"] = l.b.cpu().numpy()
+        np.savez(path, widths=np.asarray(self.widths), residual=np.asarray(self.residual, dtype=np.int64).reshape(-1, 2),
+                 **arrs)
+
+    def load_params(self, path):
+        """Weights and biases written by ``save`` for a network of the same shape."""
+        import torch
+
+        with np.load(path, allow_pickle=False) as z:
+            if tuple(z["widths"]) != tuple(self.widths):
+                raise ValueError(f"{path}: widths {tuple(z['widths'])} != {tuple(self.widths)}")
+            for i, l in enumerate(self.layers()):
+                W, b = z[f"W{i}"], z[f"b{i}"]
+                if W.shape != tuple(l.W.shape) or b.shape != tuple(l.b.shape):
+                    raise ValueError(f"{path}: layer {i} shape mismatch")
+                l.W.copy_(torch.tensor(W, device=l.W.device))
+                l.b.copy_(torch.tensor(b, device=l.b.device))
+
 
 def conv_flops(net, shape, batch=1):
     """Multiply-add flops (x2) of one forward pass over ``batch`` samples of ``shape`` (d, h, w)."""

@@ -131,44 +131,47 @@ class Trainer:
         return float(torch.stack(losses).mean().item())
 
 
-def run(args):
+def solve_all(samples, args, scale, init=None, tag=""):
+    """``solve`` in batches of ``args.batch_solve``; keeps per sample the step
+    count, the divergence flag and the steady fields as float32 targets."""
+    out = dict(steps=[], diverged=[], wall=0.0, fields=[])
+    for i in range(0, len(samples), args.batch_solve):
+        part = samples[i: i + args.batch_solve]
+        shape = part[0]["mask"].shape
+        r = solve(part, args.tol, args.max_steps, args.storage,
+                  None if init is None else init[i: i + args.batch_solve])
+        out["steps"] += r["steps"]
+        out["diverged"] += r["diverged"]
+        out["wall"] += r["wall"]
+        out["fields"] += [targets(rr, uu, shape, scale) for rr, uu in zip(r["rho"], r["u"])]
+        print(f"[warmstart] {tag} solved {i + len(part)}/{len(samples)} median steps "
+              f"{int(np.median(r['steps']))} wall {r['wall']:.1f}s", flush=True)
+    return out
+
+
+def train(args, rep):
+    """Generate the training pairs with the solver and train the network."""
     import torch
 
-    t_all = time.perf_counter()
     dev = torch.device("cuda:0")
-    rep = dict(n=args.n, train=args.train, test=args.test, tol=args.tol, storage=args.storage)
     train_s = make_samples(args.n, args.train, 0)
-    test_s = make_samples(args.n, args.test, 100000)
     scale = u_scale(train_s[0]["params"], 8)
     shape = (args.n,) * 3
-
-    def solve_all(samples, init=None):
-        out = dict(steps=[], diverged=[], wall=0.0, rho=[], u=[])
-        for i in range(0, len(samples), args.batch_solve):
-            part = samples[i: i + args.batch_solve]
-            r = solve(part, args.tol, args.max_steps, args.storage,
-                      None if init is None else init[i: i + args.batch_solve])
-            out["steps"] += r["steps"]
-            out["diverged"] += r["diverged"]
-            out["wall"] += r["wall"]
-            out["rho"] += r["rho"]
-            out["u"] += r["u"]
-            print(f"[warmstart] solved {i + len(part)}/{len(samples)} steps {r['steps']} "
-                  f"wall {r['wall']:.1f}s", flush=True)
-        return out
-
-    gen = solve_all(train_s)
+    gen = solve_all(train_s, args, scale, tag="train")
     keep = [i for i, d in enumerate(gen["diverged"]) if not d]
     conv = [gen["steps"][i] for i in keep if gen["steps"][i] > 0]
     rep.update(train_converged=len(conv), train_diverged=len(train_s) - len(keep),
-               train_steps_mean=float(np.mean(conv)) if conv else None, train_solve_wall_s=gen["wall"])
+               train_at_cap=len(keep) - len(conv),
+               train_steps_median=float(np.median(conv)) if conv else None, train_solve_wall_s=gen["wall"])
     X = np.stack([features(train_s[i]["mask"], train_s[i]["rho"].reshape((2,) + shape)) for i in keep])
-    T = np.stack([targets(gen["rho"][i], gen["u"][i], shape, scale) for i in keep])
+    T = np.stack([gen["fields"][i] for i in keep])
+    del gen
     var_u = float(np.mean(T[..., :3] ** 2))
     var_p = float(np.mean(T[..., 3] ** 2))
     wt = [var_p / max(var_u, 1e-30)] * 3 + [1.0]
     x = torch.tensor(X, device=dev)
     t = torch.tensor(T, device=dev)
+    del X, T
     net = warmnet.UNet(cin=2, cout=4, widths=tuple(args.widths), seed=args.seed, residual=[(3, 1)],
                        zero_head=True)
     tr = Trainer(net, x, t, wt, batch=args.batch)
@@ -186,38 +189,74 @@ def run(args):
     fl = 3.0 * warmnet.conv_flops(net, shape) * it
     rep.update(params=net.n_params(), loss_history=hist, train_wall_s=train_wall,
                train_tflops=fl / train_wall / 1e12)
+    if args.weights:
+        net.save(args.weights)
+    return net, scale
 
-    # held-out: from rest vs from the prediction
-    cold = solve_all(test_s)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    init = []
-    for s in test_s:
-        xf = torch.tensor(features(s["mask"], s["rho"].reshape((2,) + shape))[None], device=dev)
-        y, _ = net.forward(xf)
-        pred = y[0].cpu().numpy()
-        init.append(fields_from_prediction(pred, (s["rho"].sum(0) == 0).astype(np.uint8), scale))
-    torch.cuda.synchronize()
-    infer = time.perf_counter() - t0
-    warm = solve_all(test_s, init)
-    ratio = [w / c for w, c in zip(warm["steps"], cold["steps"]) if w > 0 and c > 0]
-    rep.update(cold_converged=sum(c > 0 for c in cold["steps"]), warm_converged=sum(w > 0 for w in warm["steps"]),
-               cold_diverged=sum(cold["diverged"]), warm_diverged=sum(warm["diverged"]))
-    dphi, du = [], []
-    for i, (rc, rw, uc, uw) in enumerate(zip(cold["rho"], warm["rho"], cold["u"], warm["u"])):
-        if cold["diverged"][i] or warm["diverged"][i]:
-            continue      # non-finite fields: no comparison
-        pc = targets(rc, uc, shape, scale)
-        pw = targets(rw, uw, shape, scale)
-        dphi.append(float(np.mean(np.abs(pc[..., 3] - pw[..., 3]))))
-        du.append(float(np.linalg.norm(pc[..., :3] - pw[..., :3]) / max(np.linalg.norm(pc[..., :3]), 1e-30)))
-    rep.update(cold_steps=cold["steps"], warm_steps=warm["steps"], cold_wall_s=cold["wall"],
-               warm_wall_s=warm["wall"], inference_wall_s=infer,
+
+def evaluate(args, net, scale, rep):
+    """Held-out samples of edge ``args.test_n``: steps to tolerance from rest
+    and from the prediction, batch by batch (the network is fully
+    convolutional with periodic padding, so it applies to any edge divisible
+    by 2^(levels - 1))."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    test_s = make_samples(args.test_n, args.test, args.test_first)
+    shape = (args.test_n,) * 3
+    res = dict(cold_steps=[], warm_steps=[], cold_diverged=[], warm_diverged=[], cold_wall_s=0.0, warm_wall_s=0.0,
+               inference_wall_s=0.0, final_phi_mean_abs_diff=[], final_u_rel_diff=[])
+    for i in range(0, len(test_s), args.batch_solve):
+        part = test_s[i: i + args.batch_solve]
+        cold = solve_all(part, args, scale, tag="cold")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        init = []
+        for s in part:
+            xf = torch.tensor(features(s["mask"], s["rho"].reshape((2,) + shape))[None], device=dev)
+            y, _ = net.forward(xf)
+            init.append(fields_from_prediction(y[0].cpu().numpy(), (s["rho"].sum(0) == 0).astype(np.uint8), scale))
+        torch.cuda.synchronize()
+        res["inference_wall_s"] += time.perf_counter() - t0
+        warm = solve_all(part, args, scale, init=init, tag="warm")
+        for key in ("steps", "diverged"):
+            res["cold_" + key] += cold[key]
+            res["warm_" + key] += warm[key]
+        res["cold_wall_s"] += cold["wall"]
+        res["warm_wall_s"] += warm["wall"]
+        for j in range(len(part)):
+            if cold["diverged"][j] or warm["diverged"][j]:
+                continue      # non-finite fields: no comparison
+            pc, pw = cold["fields"][j], warm["fields"][j]
+            res["final_phi_mean_abs_diff"].append(float(np.mean(np.abs(pc[..., 3] - pw[..., 3]))))
+            res["final_u_rel_diff"].append(
+                float(np.linalg.norm(pc[..., :3] - pw[..., :3]) / max(np.linalg.norm(pc[..., :3]), 1e-30)))
+        del cold, warm, init
+    ratio = [w / c for w, c in zip(res["warm_steps"], res["cold_steps"]) if w > 0 and c > 0]
+    res.update(test_n=args.test_n, test=args.test, test_first=args.test_first,
+               cold_converged=sum(c > 0 for c in res["cold_steps"]),
+               warm_converged=sum(w > 0 for w in res["warm_steps"]),
+               cold_steps_median=float(np.median([c for c in res["cold_steps"] if c > 0])) if ratio else None,
+               warm_steps_median=float(np.median([w for w in res["warm_steps"] if w > 0])) if ratio else None,
                step_ratio_median=float(np.median(ratio)) if ratio else None,
                step_ratio_mean=float(np.mean(ratio)) if ratio else None,
-               wall_ratio_incl_inference=(warm["wall"] + infer) / cold["wall"],
-               final_phi_mean_abs_diff=dphi, final_u_rel_diff=du,
-               total_wall_s=time.perf_counter() - t_all)
+               wall_ratio_incl_inference=(res["warm_wall_s"] + res["inference_wall_s"]) / max(res["cold_wall_s"], 1e-9))
+    rep.update(res)
+
+
+def run(args):
+    t_all = time.perf_counter()
+    rep = dict(n=args.n, train=args.train, tol=args.tol, storage=args.storage, phase=args.phase)
+    if args.phase in ("all", "train"):
+        net, scale = train(args, rep)
+    else:
+        net = warmnet.UNet(cin=2, cout=4, widths=tuple(args.widths), seed=args.seed, residual=[(3, 1)],
+                           zero_head=True)
+        net.load_params(args.weights)
+        scale = u_scale(make_samples(args.n, 1, 0)[0]["params"], 8)
+    if args.phase in ("all", "eval"):
+        evaluate(args, net, scale, rep)
+    rep["total_wall_s"] = time.perf_counter() - t_all
     return rep
 
 
@@ -226,6 +265,10 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=64, help="cubic sample edge")
     ap.add_argument("--train", type=int, default=256)
     ap.add_argument("--test", type=int, default=32)
+    ap.add_argument("--test-n", type=int, default=None, help="edge of the held-out samples (default: --n)")
+    ap.add_argument("--test-first", type=int, default=100000, help="seed of the first held-out sample")
+    ap.add_argument("--phase", choices=("all", "train", "eval"), default="all")
+    ap.add_argument("--weights", default=None, help="network weights (.npz) written by train, read by eval")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-steps", type=int, default=100000)
     ap.add_argument("--storage", default="f32")
@@ -237,6 +280,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    if args.test_n is None:
+        args.test_n = args.n
+    if args.phase == "eval" and not args.weights:
+        ap.error("--phase eval needs --weights")
     rep = run(args)
     line = json.dumps(rep)
     print(line)

@@ -63,4 +63,6 @@ def test_warmnet_header_declarations_are_exported():
     # argument checks happen before any device call
     assert lib.wn_conv3d_fwd(None, 1, 4, 4, 4, 2, None, None, 4, 3, 0, None, None) == -1
     assert b"bad arguments" in lib.wn_last_error()
-    assert lib.wn_wgrad_workspace_bytes(1, 16, 16, 32, 3, 5, 3) == 2 * 5 * 27 * 3 * 4
+    # 16 x 16 x 32 voxels = 32 bricks of 256; this small layer sums one brick per chunk
+    assert lib.wn_wgrad_workspace_bytes(1, 16, 16, 32, 3, 5, 3) == 32 * 5 * 27 * 3 * 4
+    assert lib.wn_bias_grad_workspace_bytes(ct.c_longlong(4096), 16) == 4096 // 256 * 16 * 4
