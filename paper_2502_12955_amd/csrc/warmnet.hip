@@ -123,9 +123,12 @@ Brick choose_brick(int d, int h, int w) {
     return best;
 }
 
+// periodic image of a halo coordinate v in [-1, n + 255]: exact for v in
+// [-1, n] (every coordinate a voxel inside the volume reads); beyond that
+// only voxels outside the volume read it, and it is clamped into range
 __device__ __forceinline__ int wrap(int v, int n) {
-    v %= n;
-    return v < 0 ? v + n : v;
+    v = v < 0 ? v + n : (v >= n ? v - n : v);
+    return v < n ? v : n - 1;
 }
 
 // blocks are dealt to the eight XCDs round robin; give each XCD a contiguous
@@ -170,11 +173,11 @@ struct ConvCfg {
     static constexpr size_t lds_bytes = (size_t)HMAX * LDA * 2 + (size_t)WITEMS * 8;
 };
 
-template <int K, int CK, int NR>
+template <int K, int CK, int NR, bool DGRAD>
 __global__ void __launch_bounds__(256) conv_brick(const float* __restrict__ X, int C, Grid3 g, Brick bk,
-                                                  const float* __restrict__ W, int dgrad,
-                                                  const float* __restrict__ bias, int N, int relu,
-                                                  float* __restrict__ Y) {
+                                                  const float* __restrict__ W, const float* __restrict__ bias,
+                                                  int N, int relu, float* __restrict__ Y) {
+    constexpr bool dgrad = DGRAD;
     using F = ConvCfg<K, CK, NR>;
     static_assert(F::lds_bytes <= 65536 && F::WITEMS * 8 <= W_LDS, "conv_brick staging exceeds 64 KiB of LDS");
     constexpr int R = F::R, K3 = F::K3, LDA = F::LDA, C4 = F::C4, KS = F::KS, TPG = F::TPG, NG = F::NG;
@@ -228,6 +231,12 @@ __global__ void __launch_bounds__(256) conv_brick(const float* __restrict__ X, i
         }
     };
     float4 wreg[F::WPT];
+    // Weight fragments: lane (q, r) of fragment (tt, ks, nb) holds
+    // B[4q + j][r] = W'(c = c0 + 16 ks + 4q + j, n = n0 + 16 nb + r) of tap
+    // grp TPG + tt.  Item `it` loads four values contiguous in W: along c for
+    // the forward pass (fragment `it`, lane it % 64), along n for the data
+    // gradient (fragment it / 64, c offset (it % 64) / 4, lanes r = 4 ((it % 64) % 4) + j).
+    const bool wvec = DGRAD ? (N & 3) == 0 : (C & 3) == 0;
     auto load_w = [&](int c0, int grp) {
 #pragma unroll
         for (int j = 0; j < F::WPT; ++j) {
@@ -236,16 +245,33 @@ __global__ void __launch_bounds__(256) conv_brick(const float* __restrict__ X, i
             if (it < F::WITEMS) {
                 const int l = it & 63, nb = (it >> 6) % NR, ks = (it >> 6) / NR % KS, tt = (it >> 6) / NR / KS;
                 const int kk = grp * TPG + tt;
-                const int n = n0 + nb * 16 + (l & 15), cb = c0 + ks * 16 + 4 * (l >> 4);
-                float v[4];
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int c = cb + jj;
-                    v[jj] = !(n < N && c < C) ? 0.f
-                            : dgrad           ? W[((size_t)c * K3 + (K3 - 1 - kk)) * N + n]
-                                              : W[((size_t)n * K3 + kk) * C + c];
+                if constexpr (!dgrad) {
+                    const int n = n0 + nb * 16 + (l & 15), c = c0 + ks * 16 + 4 * (l >> 4);
+                    const float* src = W + ((size_t)n * K3 + kk) * C + c;
+                    if (n < N) {
+                        if (wvec && c + 3 < C) {
+                            t = *(const float4*)src;
+                        } else {
+                            t.x = c < C ? src[0] : 0.f;
+                            t.y = c + 1 < C ? src[1] : 0.f;
+                            t.z = c + 2 < C ? src[2] : 0.f;
+                            t.w = c + 3 < C ? src[3] : 0.f;
+                        }
+                    }
+                } else {
+                    const int c = c0 + ks * 16 + (l >> 2), n = n0 + nb * 16 + 4 * (l & 3);
+                    const float* src = W + ((size_t)c * K3 + (K3 - 1 - kk)) * N + n;
+                    if (c < C) {
+                        if (wvec && n + 3 < N) {
+                            t = *(const float4*)src;
+                        } else {
+                            t.x = n < N ? src[0] : 0.f;
+                            t.y = n + 1 < N ? src[1] : 0.f;
+                            t.z = n + 2 < N ? src[2] : 0.f;
+                            t.w = n + 3 < N ? src[3] : 0.f;
+                        }
+                    }
                 }
-                t = make_float4(v[0], v[1], v[2], v[3]);
             }
             wreg[j] = t;
         }
@@ -255,10 +281,21 @@ __global__ void __launch_bounds__(256) conv_brick(const float* __restrict__ X, i
         for (int j = 0; j < F::WPT; ++j) {
             const int it = tid + 256 * j;
             if (it < F::WITEMS) {
-                bf16x4 o;
-                o[0] = to_bf16(wreg[j].x), o[1] = to_bf16(wreg[j].y), o[2] = to_bf16(wreg[j].z),
-                o[3] = to_bf16(wreg[j].w);
-                wl[it] = o;
+                if constexpr (!dgrad) {
+                    bf16x4 o;
+                    o[0] = to_bf16(wreg[j].x), o[1] = to_bf16(wreg[j].y), o[2] = to_bf16(wreg[j].z),
+                    o[3] = to_bf16(wreg[j].w);
+                    wl[it] = o;
+                } else {
+                    // c offset cc = (it % 64) / 4 -> q = cc / 4, element cc % 4; r = 4 (it % 4) + jj
+                    const int l = it & 63, cc = l >> 2;
+                    short* frag = (short*)&wl[it & ~63];
+                    const int e = cc & 3, lb = (cc >> 2) * 16 + 4 * (l & 3);
+                    frag[(lb + 0) * 4 + e] = to_bf16(wreg[j].x);
+                    frag[(lb + 1) * 4 + e] = to_bf16(wreg[j].y);
+                    frag[(lb + 2) * 4 + e] = to_bf16(wreg[j].z);
+                    frag[(lb + 3) * 4 + e] = to_bf16(wreg[j].w);
+                }
             }
         }
     };
@@ -738,8 +775,12 @@ template <int K, int CK, int NR>
 void conv_go(const float* X, int C, Grid3 g, Brick bk, const float* W, int dgrad, const float* bias, int N, int relu,
              float* Y, int blocks, hipStream_t st) {
     const size_t bytes = ConvCfg<K, CK, NR>::lds_bytes;
-    hipLaunchKernelGGL((conv_brick<K, CK, NR>), dim3(blocks), dim3(256), bytes, st, X, C, g, bk, W, dgrad, bias, N,
-                       relu, Y);
+    if (dgrad)
+        hipLaunchKernelGGL((conv_brick<K, CK, NR, true>), dim3(blocks), dim3(256), bytes, st, X, C, g, bk, W, bias, N,
+                           relu, Y);
+    else
+        hipLaunchKernelGGL((conv_brick<K, CK, NR, false>), dim3(blocks), dim3(256), bytes, st, X, C, g, bk, W, bias, N,
+                           relu, Y);
 }
 
 template <int K, int CK>
