@@ -49,11 +49,13 @@ def make_samples(n, count, first, config=5, radius=8, blob_radius=6, saturation=
     return out
 
 
-def solve(samples, tol, max_steps, storage="f32", init=None):
+def solve(samples, tol, max_steps, storage="f32", init=None, progress=0):
     """Run a batch to tolerance.  ``init``: optional list of (rho, u) per sample
     (default: rest with the seeded phases).  Returns per-sample steps (-1: not
     converged within max_steps), per-sample divergence flags, the final fields
-    and the wall time."""
+    and the wall time.  With ``progress`` > 0 the run is cut into pieces of that
+    many steps (a multiple of the monitor interval; the result is the same) and
+    the number of settled samples is printed after each."""
     plist = [dict(s["params"], storage=storage) for s in samples]
     b = mclbm.Batch(plist)
     b.set_graph(True)
@@ -64,7 +66,16 @@ def solve(samples, tol, max_steps, storage="f32", init=None):
         b.init_fields([r for r, _ in init], [u for _, u in init])
     b.synchronize()
     t0 = time.perf_counter()
-    ok, steps = b.run_to_residual(tol, max_steps, allow_diverged=True)
+    ok, steps, piece = False, 0, progress if progress > 0 else max_steps
+    while steps < max_steps:
+        ok, n = b.run_to_residual(tol, min(piece, max_steps - steps), allow_diverged=True)
+        steps += n
+        settled = sum(m[12] > 0 for m in (b.sample_monitors(i) for i in range(len(samples))))
+        if progress > 0:
+            print(f"[solve] step {steps}: {settled}/{len(samples)} settled, {time.perf_counter() - t0:.0f}s",
+                  flush=True)
+        if ok or n == 0 or settled == len(samples):
+            break
     b.synchronize()
     wall = time.perf_counter() - t0
     mons = [b.sample_monitors(i) for i in range(len(samples))]
@@ -139,7 +150,7 @@ def solve_all(samples, args, scale, init=None, tag=""):
         part = samples[i: i + args.batch_solve]
         shape = part[0]["mask"].shape
         r = solve(part, args.tol, args.max_steps, args.storage,
-                  None if init is None else init[i: i + args.batch_solve])
+                  None if init is None else init[i: i + args.batch_solve], progress=args.progress)
         out["steps"] += r["steps"]
         out["diverged"] += r["diverged"]
         out["wall"] += r["wall"]
@@ -273,6 +284,7 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=100000)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--batch-solve", type=int, default=64)
+    ap.add_argument("--progress", type=int, default=5000, help="print the settled count every this many steps")
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--batch", type=int, default=2)
     ap.add_argument("--lr", type=float, default=2e-3)
