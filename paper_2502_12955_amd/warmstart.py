@@ -257,7 +257,9 @@ def evaluate(args, net, scale, rep):
 
 def run(args):
     t_all = time.perf_counter()
-    rep = dict(n=args.n, train=args.train, tol=args.tol, storage=args.storage, phase=args.phase)
+    rep = dict(n=args.n, tol=args.tol, storage=args.storage, phase=args.phase)
+    if args.phase != "eval":
+        rep["train"] = args.train
     if args.phase in ("all", "train"):
         net, scale = train(args, rep)
     else:
