@@ -83,6 +83,13 @@ typedef struct {
     double J0;             /* solute rest weight, in [0, 1) */
     double k_wall;         /* first-order wall reaction rate k = A exp(-E / R_u T), >= 0 */
     double C_in;           /* inlet concentration (INLET_OUTLET_X) */
+    int32_t product;       /* 1: a second solute species (CO2) that every reacting wall link
+                              produces at the reacting species' consumption rate k C_b
+                              (eq:react, eq:reactCO2); needs the solute on; 0: off */
+    int32_t rate_field;    /* 1: the reaction rate is a per-node field set with
+                              mclbm_set_wall_rate (k_wall until then); 0: uniform k_wall */
+    double D2;             /* product diffusivity, > 0 when the product is on */
+    double C_in2;          /* product inlet concentration (INLET_OUTLET_X) */
 } mclbm_params;
 
 /* Device bytes the lattice needs for these parameters (populations A and B,
@@ -97,7 +104,8 @@ int mclbm_required_bytes(const mclbm_params* p, size_t* bytes);
  * which every kernel and copy of this handle is queued.  *out receives the
  * handle.  Errors: EINVAL (parameters: tau <= 1/2, bad dimensions or enums,
  * D <= 0 with the solute on, J0 outside [0, 1), k_wall < 0, rho0 <= 0,
- * monitor_every < 1), ENOMEM (arena too small), EHIP. */
+ * monitor_every < 1, product or rate_field without the solute, D2 <= 0 with
+ * the product, nonzero reserved field), ENOMEM (arena too small), EHIP. */
 int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_bytes,
                        void* hip_stream, mclbm_handle** out);
 
@@ -122,9 +130,18 @@ int mclbm_get_geometry(mclbm_handle* h, uint8_t* mask_out, uint32_t* flow_links,
 /* Initial state at equilibrium without force term: f_i = f^eq_i(rho_s, u),
  * h_k = h^eq_k(C, u).  rho: host FP64 [ncomp][N] (must be > 0 on fluid
  * nodes); u: host FP64 [3][N] or NULL (rest); C: host FP64 [N] or NULL
- * (zero).  Resets the step counter and the residual snapshot, and fixes the
+ * (zero).  The product species (if on) starts at zero concentration.
+ * Resets the step counter and the residual snapshot, and fixes the
  * storage shift rhobar_s.  Errors: ESTATE before set_geometry, EINVAL. */
 int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const double* C);
+
+/* Per-node first-order reaction rate, e.g. k(x) = A exp(-E / (R_u T(x))) of a
+ * prescribed temperature field (eq:reactO2): k_box is host FP64 [N] (box
+ * nodes, x fastest; concatenated per sample for a batch), >= 0 and finite on
+ * fluid nodes.  A reacting link uses the rate of its wall (wet) node.  Needs
+ * rate_field = 1 and set_geometry first (set_geometry resets the field to
+ * k_wall).  Errors: ESTATE (no rate field, or before set_geometry), EINVAL. */
+int mclbm_set_wall_rate(mclbm_handle* h, const double* k_box);
 
 /* Advance n >= 0 time steps (queued on the stream).  Monitors run after
  * every step whose index is a multiple of monitor_every; if any ran, the
@@ -134,7 +151,8 @@ int mclbm_step(mclbm_handle* h, int64_t n);
 
 /* Macroscopic fields of the current (post-streaming) state: rho_s = sum_i f,
  * u = barycentric velocity with half force (eq:1.19, evaluated after
- * streaming), C = sum_k h_k.  rho: [ncomp][N], u: [3][N], C: [N]; any may be
+ * streaming), C = sum_k h_k.  rho: [ncomp][N], u: [3][N], C: [N], or [2][N]
+ * (reacting species, then the product) when the product is on; any may be
  * NULL.  dst_is_device != 0: the pointers are device memory (no host sync
  * beyond the stream).  Solid nodes are 0. */
 int mclbm_get_moments(mclbm_handle* h, double* rho, double* u, double* C, int32_t dst_is_device);
@@ -154,8 +172,9 @@ int mclbm_get_monitors(mclbm_handle* h, double out[16]);
 int mclbm_monitor_now(mclbm_handle* h);
 
 /* Populations of the current pre-collision state (after streaming, before
- * the next collision).  raw == 0: FP64 decoded values [ncomp*Q + QS][N]
- * (flow [s][i], then solute [k]; QS = 0 without solute); raw != 0: the stored
+ * the next collision).  raw == 0: FP64 decoded values [ncomp*Q + HS][N]
+ * (flow [s][i], then solute [species][k]; HS = QS per solute species, 0
+ * without solute, 2 QS with the product); raw != 0: the stored
  * bytes in the same order (8, 4 or 2 bytes per value; shifted values for
  * *_SHIFT).  Solid nodes read 0. */
 int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw);

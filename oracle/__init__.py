@@ -29,7 +29,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "mclbm_oracle.c")
 
 PARAM_KEYS = ("lattice", "nx", "ny", "nz", "ncomp", "forcing", "solute", "tau", "G",
-              "G_ads", "rho0", "accel", "D", "J0", "k_wall", "C_in")
+              "G_ads", "rho0", "accel", "D", "J0", "k_wall", "C_in", "product", "D2", "C_in2", "k_node")
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 FORCINGS = {"guo": 0, "sc": 1}
@@ -54,7 +54,9 @@ class _Params(ct.Structure):
                 ("tau", ct.c_double * 2), ("G", (ct.c_double * 2) * 2),
                 ("G_ads", ct.c_double * 2), ("rho0", ct.c_double),
                 ("accel", ct.c_double * 3), ("D", ct.c_double), ("J0", ct.c_double),
-                ("k_wall", ct.c_double), ("C_in", ct.c_double)]
+                ("k_wall", ct.c_double), ("C_in", ct.c_double),
+                ("product", ct.c_int32), ("pad2_", ct.c_int32), ("D2", ct.c_double), ("C_in2", ct.c_double),
+                ("k_node", ct.POINTER(ct.c_double))]
 
 
 _lib = None
@@ -101,6 +103,13 @@ def _struct(p: dict) -> _Params:
     s.J0 = float(p.get("J0", 0.1))
     s.k_wall = float(p.get("k_wall", 0.0))
     s.C_in = float(p.get("C_in", 0.0))
+    s.product = int(p.get("product", 0))
+    s.D2 = float(p.get("D2", 0.1))
+    s.C_in2 = float(p.get("C_in2", 0.0))
+    kn = p.get("k_node")
+    if kn is not None:     # per-node reaction rate [N]; the array must outlive the call
+        s._k_node = np.ascontiguousarray(kn, np.float64).reshape(-1)
+        s.k_node = s._k_node.ctypes.data_as(ct.POINTER(ct.c_double))
     return s
 
 
@@ -114,6 +123,13 @@ def _q(p):
 
 def _qs(p):
     return 7 if _enum(p["lattice"], LATTICES) == 1 else 5
+
+
+def n_species(p):
+    """Solute species carried: 0 (solute off), 1 (O2), 2 (O2 and the product CO2)."""
+    if _enum(p.get("solute", "off"), SOLUTES) == 0:
+        return 0
+    return 2 if int(p.get("product", 0)) else 1
 
 
 def n_nodes(p):
@@ -199,7 +215,7 @@ def init(p, mask, rho, u=None, C=None):
     m = np.ascontiguousarray(mask, np.uint8)
     rho = np.ascontiguousarray(rho, np.float64).reshape(nc, N)
     f = np.zeros((nc * _q(p), N))
-    h = np.zeros((_qs(p), N))
+    h = np.zeros((_qs(p) * max(1, n_species(p)), N))
     up = None if u is None else np.ascontiguousarray(u, np.float64).reshape(3, N)
     Cp = None if C is None else np.ascontiguousarray(C, np.float64).reshape(N)
     s = _struct(p)
@@ -227,7 +243,7 @@ def step_nodes(p, mask, f, h, nodes):
     nodes = np.ascontiguousarray(nodes, np.int64)
     nc = int(p.get("ncomp", 2))
     fo = np.zeros((len(nodes), nc * _q(p)))
-    ho = np.zeros((len(nodes), _qs(p)))
+    ho = np.zeros((len(nodes), _qs(p) * max(1, n_species(p))))
     f = np.ascontiguousarray(f, np.float64)
     h = np.ascontiguousarray(h, np.float64)
     s = _struct(p)
@@ -251,13 +267,14 @@ def forces(p, mask, f):
 
 
 def moments(p, mask, f, h):
-    """rho_s [ncomp][N], barycentric u with half force [3][N], C [N]; solid nodes -> 0."""
+    """rho_s [ncomp][N], barycentric u with half force [3][N], C [N] (with the
+    product species: [2][N], O2 then CO2); solid nodes -> 0."""
     N = n_nodes(p)
     nc = int(p.get("ncomp", 2))
     m = np.ascontiguousarray(mask, np.uint8)
     rho = np.zeros((nc, N))
     u = np.zeros((3, N))
-    C = np.zeros(N)
+    C = np.zeros((2, N)) if n_species(p) == 2 else np.zeros(N)
     f = np.ascontiguousarray(f, np.float64)
     h = np.ascontiguousarray(h, np.float64)
     s = _struct(p)

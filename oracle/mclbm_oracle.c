@@ -15,7 +15,10 @@
  *   rho_s   component density, psi_s pseudo-potential, F^s total force
  *   u       barycentric velocity, tau_s, tau_d relaxation times
  *
- * Layout: node index n = x + nx*(y + ny*z); f[(s*Q + i)*N + n]; h[k*N + n].
+ *   h_{k,CO2} populations of the optional product species (eq:reactCO2)
+ *
+ * Layout: node index n = x + nx*(y + ny*z); f[(s*Q + i)*N + n]; h[(sp*QS + k)*N + n]
+ * for solute species sp (0: the reacting species O2, 1: the product CO2).
  * Solid nodes carry no populations (their slots are left untouched).
  *
  * Readings taken where the paper is silent or ambiguous (listed with reasons
@@ -27,6 +30,9 @@
  *     D2Q5 lattice: J0 and (1-J0)/4.  Solute c_s^2 = sum_k W_k e_kx^2.
  *   - the solute is advected by the barycentric velocity with half force.
  *   - the wet-node reaction is applied per missing link.
+ *   - the product is created at every reacting link at the O2 consumption
+ *     rate k C_b of that link (one CO2 per O2, eq:react), entering through
+ *     the link in the product's own flux convention.
  *   - inlet (x = 0) anti-bounce-back Dirichlet, outlet (x = nx-1) zero
  *     gradient, when the solute runs in inlet/outlet mode.
  *   - fluid voxels pinched between two solids along one axis are made solid
@@ -51,6 +57,10 @@ typedef struct {
     double rho0;
     double accel[3];
     double D, J0, k_wall, C_in;
+    int32_t product;   /* 1: a second species (CO2) produced at the reacting walls */
+    int32_t pad2_;
+    double D2, C_in2;  /* its diffusivity and inlet concentration */
+    const double* k_node; /* per-node reaction rate [N] (e.g. A exp(-E / R_u T(x))), or NULL: k_wall */
 } orc_params;
 
 /* ---------------------------------------------------------------------------
@@ -285,6 +295,7 @@ void orc_link_masks(const orc_params* p, const uint8_t* mask, uint32_t* flow_bit
 /* ---------------------------------------------------------------------------
  * Initialisation: f^s_i = f^eq_i(rho_s, u), h_k = h^eq_k(C, u), no force term.
  * rho: [ncomp][N]; u: [3][N] or NULL (rest); C: [N] or NULL (zero).
+ * The product species (if on) starts at zero: h = 0 in its planes.
  * ------------------------------------------------------------------------- */
 void orc_init(const orc_params* p, const uint8_t* mask, const double* rho, const double* u,
               const double* C, double* f, double* h) {
@@ -300,6 +311,8 @@ void orc_init(const orc_params* p, const uint8_t* mask, const double* rho, const
         if (p->solute && h) {
             double c0 = C ? C[n] : 0.0;
             for (int k = 0; k < S.Q; ++k) h[(int64_t)k * N + n] = heq_k(&S, k, c0, v);
+            if (p->product)
+                for (int k = 0; k < S.Q; ++k) h[(int64_t)(S.Q + k) * N + n] = 0.0;   /* no product at t = 0 */
         }
     }
 }
@@ -371,7 +384,7 @@ static void bary_u(const orc_params* p, const flow_lat* L, const double* f, int6
 static void collide_at(const orc_params* p, const flow_lat* L, const sol_lat* S,
                        const uint8_t* mask, const double* f, const double* h,
                        const double* rho, const double* psi, int64_t n,
-                       double fs[2][19], double hs[7]) {
+                       double fs[2][19], double hs[14]) {
     int64_t N = nnodes(p);
     double F[2][3];
     force_at(p, L, mask, rho, psi, n, F);
@@ -410,12 +423,16 @@ static void collide_at(const orc_params* p, const flow_lat* L, const sol_lat* S,
     }
 
     if (p->solute) {
-        double tau_d = p->D / S->cs2 + 0.5;
-        double C = 0.0;
-        for (int k = 0; k < S->Q; ++k) C += h[(int64_t)k * N + n];
-        for (int k = 0; k < S->Q; ++k) {
-            double hk = h[(int64_t)k * N + n];
-            hs[k] = hk - (hk - heq_k(S, k, C, u)) / tau_d;
+        /* species 0 (O2) and, with the product, species 1 (CO2): the same
+         * collision (eq:therpop_species) with each species' own tau_d */
+        for (int sp = 0; sp <= (p->product ? 1 : 0); ++sp) {
+            double tau_d = (sp ? p->D2 : p->D) / S->cs2 + 0.5;
+            double C = 0.0;
+            for (int k = 0; k < S->Q; ++k) C += h[(int64_t)(sp * S->Q + k) * N + n];
+            for (int k = 0; k < S->Q; ++k) {
+                double hk = h[(int64_t)(sp * S->Q + k) * N + n];
+                hs[sp * S->Q + k] = hk - (hk - heq_k(S, k, C, u)) / tau_d;
+            }
         }
     }
 }
@@ -431,36 +448,48 @@ static double flow_stream_value(const orc_params* p, const flow_lat* L, const ui
     return fstar[((int64_t)s * L->Q + i) * N + src];
 }
 
-/* Value of solute population k at fluid node y after streaming.
+/* Reaction rate at the wall node y: the prescribed field, else the uniform k_wall. */
+static double rate_at(const orc_params* p, int64_t y) { return p->k_node ? p->k_node[y] : p->k_wall; }
+
+/* Value of solute population k of species sp at fluid node y after streaming.
  * Precedence: inlet/outlet seam > wet (reactive) link > plain pull.
  *   inlet  (x = 0, e_kx = +1):      h_k = 2 W_k C_in - h_kbar(y, t+1)
  *   outlet (x = nx-1, e_kx = -1):   h_k = h_k(nx-2, t+1) = h*_k(y)
- *   wet link (y - e_k solid):       C_b = 2 h_in / (2 W_k + k tau/(tau - 1/2)),
+ *   wet link (y - e_k solid), O2:   C_b = 2 h_in / (2 W_k + k tau/(tau - 1/2)),
  *                                   h_k = 2 W_k C_b - h_in,  h_in = h_kbar(y, t+1)
- * (eq:wetnode9 generalised to any missing link; the node sits on the wall.)
+ *   wet link, product (CO2):        h_k = h_in + k tau2/(tau2 - 1/2) C_b
+ * (eq:wetnode9 generalised to any missing link; the node sits on the wall.
+ * The O2 rule moves k C_b out of the fluid through the link in the flux
+ * convention (1 - 1/(2 tau)) (h_in - h_k); the product rule moves the same
+ * k C_b in, eq:reactCO2, in its own species' convention.)
  * h_kbar(y, t+1) is always a plain value h*_kbar(y + e_k): pinch-fill
  * guarantees that y + e_k is a fluid node inside the domain. */
 static double solute_stream_value(const orc_params* p, const sol_lat* S, const uint8_t* mask,
-                                  const double* hstar, int k, int64_t y) {
+                                  const double* hstar, int sp, int k, int64_t y) {
     int64_t N = nnodes(p);
     int x, yy, z;
     coords(p, y, &x, &yy, &z);
     int kb = S->opp[k];
+    int64_t base = (int64_t)sp * S->Q;
     if (p->solute == 2 && x == 0 && S->c[k][0] == 1) {
-        double hin = hstar[(int64_t)kb * N + nbr(p, y, S->c[k])];
-        return 2.0 * S->w[k] * p->C_in - hin;
+        double hin = hstar[(base + kb) * N + nbr(p, y, S->c[k])];
+        return 2.0 * S->w[k] * (sp ? p->C_in2 : p->C_in) - hin;
     }
     if (p->solute == 2 && x == p->nx - 1 && S->c[k][0] == -1) {
-        return hstar[(int64_t)k * N + y];
+        return hstar[(base + k) * N + y];
     }
     int64_t src = nbr_back(p, y, S->c[k]);
     if (mask[src]) {
         double tau_d = p->D / S->cs2 + 0.5;
-        double hin = hstar[(int64_t)kb * N + nbr(p, y, S->c[k])];
-        double Cb = 2.0 * hin / (2.0 * S->w[k] + p->k_wall * tau_d / (tau_d - 0.5));
-        return 2.0 * S->w[k] * Cb - hin;
+        double hin0 = hstar[(int64_t)kb * N + nbr(p, y, S->c[k])];
+        double kr = rate_at(p, y);
+        double Cb = 2.0 * hin0 / (2.0 * S->w[k] + kr * tau_d / (tau_d - 0.5));
+        if (sp == 0) return 2.0 * S->w[k] * Cb - hin0;
+        double tau2 = p->D2 / S->cs2 + 0.5;
+        double hin = hstar[(base + kb) * N + nbr(p, y, S->c[k])];
+        return hin + kr * tau2 / (tau2 - 0.5) * Cb;
     }
-    return hstar[(int64_t)k * N + src];
+    return hstar[(base + k) * N + src];
 }
 
 /* ---------------------------------------------------------------------------
@@ -477,19 +506,19 @@ void orc_step(const orc_params* p, const uint8_t* mask, double* f, double* h, in
     double* rho = (double*)calloc((size_t)(NC * N), sizeof(double));
     double* psi = (double*)calloc((size_t)(NC * N), sizeof(double));
     double* fstar = (double*)calloc((size_t)(NC * L.Q * N), sizeof(double));
-    double* hstar = p->solute ? (double*)calloc((size_t)(S.Q * N), sizeof(double)) : NULL;
+    int NS = p->solute ? (p->product ? 2 : 1) : 0;   /* solute species */
+    double* hstar = NS ? (double*)calloc((size_t)(NS * S.Q * N), sizeof(double)) : NULL;
 
     for (int64_t t = 0; t < nsteps; ++t) {
         densities(p, &L, mask, f, rho, psi);
 #pragma omp parallel for schedule(static)
         for (int64_t n = 0; n < N; ++n) {
             if (mask[n]) continue;
-            double fs[2][19], hs[7];
+            double fs[2][19], hs[14];
             collide_at(p, &L, &S, mask, f, h, rho, psi, n, fs, hs);
             for (int s = 0; s < NC; ++s)
                 for (int i = 0; i < L.Q; ++i) fstar[((int64_t)s * L.Q + i) * N + n] = fs[s][i];
-            if (p->solute)
-                for (int k = 0; k < S.Q; ++k) hstar[(int64_t)k * N + n] = hs[k];
+            for (int k = 0; k < NS * S.Q; ++k) hstar[(int64_t)k * N + n] = hs[k];
         }
 #pragma omp parallel for schedule(static)
         for (int64_t n = 0; n < N; ++n) {
@@ -497,9 +526,9 @@ void orc_step(const orc_params* p, const uint8_t* mask, double* f, double* h, in
             for (int s = 0; s < NC; ++s)
                 for (int i = 0; i < L.Q; ++i)
                     f[((int64_t)s * L.Q + i) * N + n] = flow_stream_value(p, &L, mask, fstar, s, i, n);
-            if (p->solute)
+            for (int sp = 0; sp < NS; ++sp)
                 for (int k = 0; k < S.Q; ++k)
-                    h[(int64_t)k * N + n] = solute_stream_value(p, &S, mask, hstar, k, n);
+                    h[(int64_t)(sp * S.Q + k) * N + n] = solute_stream_value(p, &S, mask, hstar, sp, k, n);
         }
     }
     free(rho);
@@ -511,7 +540,7 @@ void orc_step(const orc_params* p, const uint8_t* mask, double* f, double* h, in
 /* Post-step populations at selected fluid nodes only, from the state at t.
  * Needs post-collision values at the nodes' upstream neighbours, which are
  * computed one by one from the densities of the whole field.
- * f_out: [count][ncomp*Q], h_out: [count][QS] (may be NULL without solute). */
+ * f_out: [count][ncomp*Q], h_out: [count][QS * species] (may be NULL without solute). */
 void orc_step_nodes(const orc_params* p, const uint8_t* mask, const double* f, const double* h,
                     const int64_t* nodes, int64_t count, double* f_out, double* h_out) {
     flow_lat L = make_flow(p->lattice);
@@ -527,7 +556,7 @@ void orc_step_nodes(const orc_params* p, const uint8_t* mask, const double* f, c
         int64_t y = nodes[q];
         int x, yy, z;
         coords(p, y, &x, &yy, &z);
-        double fs[2][19], hs[7], fs_n[2][19], hs_n[7];
+        double fs[2][19], hs[14], fs_n[2][19], hs_n[14];
         collide_at(p, &L, &S, mask, f, h, rho, psi, y, fs, hs);
         for (int i = 0; i < L.Q; ++i) {
             int64_t src = nbr_back(p, y, L.c[i]);
@@ -537,27 +566,34 @@ void orc_step_nodes(const orc_params* p, const uint8_t* mask, const double* f, c
                 f_out[q * NC * L.Q + s * L.Q + i] = solid ? fs[s][L.opp[i]] : fs_n[s][i];
         }
         if (p->solute && h_out) {
-            for (int k = 0; k < S.Q; ++k) {
-                int kb = S.opp[k];
-                double v;
-                int64_t src = nbr_back(p, y, S.c[k]);
-                if (p->solute == 2 && x == 0 && S.c[k][0] == 1) {
-                    collide_at(p, &L, &S, mask, f, h, rho, psi, nbr(p, y, S.c[k]), fs_n, hs_n);
-                    v = 2.0 * S.w[k] * p->C_in - hs_n[kb];
-                } else if (p->solute == 2 && x == p->nx - 1 && S.c[k][0] == -1) {
-                    v = hs[k];
-                } else if (mask[src]) {
-                    double tau_d = p->D / S.cs2 + 0.5;
-                    collide_at(p, &L, &S, mask, f, h, rho, psi, nbr(p, y, S.c[k]), fs_n, hs_n);
-                    double hin = hs_n[kb];
-                    double Cb = 2.0 * hin / (2.0 * S.w[k] + p->k_wall * tau_d / (tau_d - 0.5));
-                    v = 2.0 * S.w[k] * Cb - hin;
-                } else {
-                    collide_at(p, &L, &S, mask, f, h, rho, psi, src, fs_n, hs_n);
-                    v = hs_n[k];
+            int NS = p->product ? 2 : 1, QT = NS * S.Q;
+            for (int sp = 0; sp < NS; ++sp)
+                for (int k = 0; k < S.Q; ++k) {
+                    int kb = S.opp[k], b = sp * S.Q;
+                    double v;
+                    int64_t src = nbr_back(p, y, S.c[k]);
+                    if (p->solute == 2 && x == 0 && S.c[k][0] == 1) {
+                        collide_at(p, &L, &S, mask, f, h, rho, psi, nbr(p, y, S.c[k]), fs_n, hs_n);
+                        v = 2.0 * S.w[k] * (sp ? p->C_in2 : p->C_in) - hs_n[b + kb];
+                    } else if (p->solute == 2 && x == p->nx - 1 && S.c[k][0] == -1) {
+                        v = hs[b + k];
+                    } else if (mask[src]) {
+                        double tau_d = p->D / S.cs2 + 0.5;
+                        collide_at(p, &L, &S, mask, f, h, rho, psi, nbr(p, y, S.c[k]), fs_n, hs_n);
+                        double kr = rate_at(p, y);
+                        double Cb = 2.0 * hs_n[kb] / (2.0 * S.w[k] + kr * tau_d / (tau_d - 0.5));
+                        if (sp == 0) {
+                            v = 2.0 * S.w[k] * Cb - hs_n[kb];
+                        } else {
+                            double tau2 = p->D2 / S.cs2 + 0.5;
+                            v = hs_n[b + kb] + kr * tau2 / (tau2 - 0.5) * Cb;
+                        }
+                    } else {
+                        collide_at(p, &L, &S, mask, f, h, rho, psi, src, fs_n, hs_n);
+                        v = hs_n[b + k];
+                    }
+                    h_out[q * QT + b + k] = v;
                 }
-                h_out[q * S.Q + k] = v;
-            }
         }
     }
     free(rho);
@@ -584,7 +620,8 @@ void orc_forces(const orc_params* p, const uint8_t* mask, const double* f, doubl
 
 /* Macroscopic fields of the current (post-streaming) state: rho_s = sum_i f,
  * u = barycentric velocity with half force (eq:1.19, taken after streaming),
- * C = sum_k h_k.  Solid nodes -> 0.  rho: [ncomp][N], u: [3][N], C: [N] or NULL. */
+ * C = sum_k h_k per solute species.  Solid nodes -> 0.  rho: [ncomp][N], u: [3][N],
+ * C: [species][N] or NULL. */
 void orc_moments(const orc_params* p, const uint8_t* mask, const double* f, const double* h,
                  double* rho_out, double* u_out, double* C_out) {
     flow_lat L = make_flow(p->lattice);
@@ -604,10 +641,12 @@ void orc_moments(const orc_params* p, const uint8_t* mask, const double* f, cons
         for (int s = 0; s < NC; ++s) rho_out[(int64_t)s * N + n] = mask[n] ? 0.0 : rho[(int64_t)s * N + n];
         for (int a = 0; a < 3; ++a) u_out[(int64_t)a * N + n] = u[a];
         if (C_out) {
-            double C = 0.0;
-            if (p->solute && !mask[n])
-                for (int k = 0; k < S.Q; ++k) C += h[(int64_t)k * N + n];
-            C_out[n] = C;
+            for (int sp = 0; sp <= (p->product ? 1 : 0); ++sp) {
+                double C = 0.0;
+                if (p->solute && !mask[n])
+                    for (int k = 0; k < S.Q; ++k) C += h[(int64_t)(sp * S.Q + k) * N + n];
+                C_out[(int64_t)sp * N + n] = C;
+            }
         }
     }
     free(rho);

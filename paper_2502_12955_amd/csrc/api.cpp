@@ -107,6 +107,7 @@ struct SampleHost {
 struct mclbm_handle {
     mclbm_params p{};  // physics (sample 0's dimensions)
     int Q = 0, QS = 0, NC = 0;
+    int HP = 0;        // solute planes per fluid node: QS per species, 0 without solute
     int S = 0;
     std::vector<SampleHost> smp;
     long long Ntot = 0;      // box nodes of all samples
@@ -118,6 +119,7 @@ struct mclbm_handle {
     size_t arena_bytes = 0;
     // device regions
     void *fA = nullptr, *fB = nullptr, *hA = nullptr, *hB = nullptr;
+    void* kfield = nullptr;   // per fluid node reaction rate (arithmetic type), rate_field only
     uint32_t* links = nullptr;
     int* map = nullptr;
     unsigned* pos = nullptr;
@@ -151,7 +153,7 @@ struct mclbm_handle {
 namespace {
 
 struct Layout {
-    size_t fA, fB, hA, hB, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample, work, nwork,
+    size_t fA, fB, hA, hB, kfield, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample, work, nwork,
         total;
 };
 
@@ -174,6 +176,11 @@ Ctx base_ctx(const mclbm_params& p) {
     c.J0 = p.J0;
     c.k_wall = p.k_wall;
     c.C_in = p.C_in;
+    c.product = p.solute ? p.product : 0;
+    c.D2 = p.D2;
+    c.C_in2 = p.C_in2;
+    c.hplanes = p.solute ? solute_q(p.lattice) * (1 + c.product) : 0;
+    c.kfield = nullptr;
     return c;
 }
 
@@ -197,15 +204,16 @@ Layout layout_for(const mclbm_params* ps, int n) {
     };
     L.fA = take((size_t)NC * Q * M * sb);
     L.fB = take((size_t)NC * Q * M * sb);
-    const size_t hb = p.solute ? (size_t)QS * M * sb : 0;
+    const size_t hb = p.solute ? (size_t)QS * (p.product ? 2 : 1) * M * sb : 0;
     L.hA = take(hb);
     L.hB = take(hb);
+    L.kfield = take(p.solute && p.rate_field ? (size_t)M * ab : 0);
     L.map = take((size_t)Ntot * 4);
     L.pos = take((size_t)M * 4);
     L.links = take((size_t)M * 4);
     L.psi = take((size_t)NC * Ntot * ab);
     L.snap = take((size_t)5 * M * ab);
-    L.stage = take((size_t)(NC + 4) * Ntot * 8);
+    L.stage = take((size_t)(NC + 4 + (p.solute && p.product ? 1 : 0)) * Ntot * 8);
     L.partials = take(nch * MON_NV * 8);
     L.result = take((size_t)n * 16 * 8);
     L.smp = take((size_t)n * sizeof(SampleDev));
@@ -260,6 +268,22 @@ bool validate_one(const mclbm_params* p, std::string& why) {
     }
     if (p->reserved != 0) {
         why = "reserved field must be 0";
+        return false;
+    }
+    if ((p->rate_field != 0 && p->rate_field != 1) || (p->rate_field && !p->solute)) {
+        why = "rate_field must be 0 or 1, and 1 needs the solute on";
+        return false;
+    }
+    if (p->product != 0 && p->product != 1) {
+        why = "product must be 0 or 1";
+        return false;
+    }
+    if (p->product && !p->solute) {
+        why = "the product species needs the solute on";
+        return false;
+    }
+    if (p->product && (!(p->D2 > 0) || !isfinite(p->D2))) {
+        why = "product diffusivity D2 must be > 0";
         return false;
     }
     for (int s = 0; s < p->ncomp; ++s)
@@ -350,6 +374,7 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     c.fB = h->fB;
     c.hA = h->hA;
     c.hB = h->hB;
+    c.kfield = h->kfield;
     c.smp = h->smp_dev;
     c.chunk_sample = h->chunk_sample;
     c.pos = h->pos;
@@ -461,7 +486,7 @@ int upload_work(mclbm_handle* h) {
 // A/B swaps keep presenting its final state.
 int mirror_sample(mclbm_handle* h, const SampleHost& s) {
     const size_t sb = store_bytes(h->p.storage);
-    const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
+    const size_t PF = (size_t)h->NC * h->Q, PS = (size_t)h->HP;
     const size_t c0 = (size_t)(s.kbase / 64), nc = (size_t)((s.nf + 63) / 64);
     HIPCHK(h, hipMemcpyAsync((char*)h->fB + c0 * PF * 64 * sb, (char*)h->fA + c0 * PF * 64 * sb, nc * PF * 64 * sb,
                              hipMemcpyDeviceToDevice, h->stream));
@@ -566,6 +591,7 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
     h->p = p[0];
     h->Q = flow_q(p[0].lattice);
     h->QS = solute_q(p[0].lattice);
+    h->HP = p[0].solute ? h->QS * (p[0].product ? 2 : 1) : 0;
     h->NC = p[0].ncomp;
     h->S = n;
     h->smp.resize(n);
@@ -605,6 +631,7 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
     h->fB = base + L.fB;
     h->hA = p[0].solute ? base + L.hA : nullptr;
     h->hB = p[0].solute ? base + L.hB : nullptr;
+    h->kfield = (p[0].solute && p[0].rate_field) ? base + L.kfield : nullptr;
     h->map = (int*)(base + L.map);
     h->pos = (unsigned*)(base + L.pos);
     h->links = (uint32_t*)(base + L.links);
@@ -716,6 +743,34 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
     int rc = upload_work(h);
     if (rc != MCLBM_OK) return rc;
     h->geom_set = true;
+    if (h->kfield) {   // the rate field starts uniform at k_wall
+        std::vector<double> kb((size_t)h->Ntot, h->p.k_wall);
+        rc = mclbm_set_wall_rate(h, kb.data());
+        if (rc != MCLBM_OK) return rc;
+    }
+    return MCLBM_OK;
+}
+
+int mclbm_set_wall_rate(mclbm_handle* h, const double* k_box) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->kfield) return fail(h, MCLBM_ESTATE, "the lattice was created without rate_field");
+    if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
+    if (!k_box) return fail(h, MCLBM_EINVAL, "k_box is NULL");
+    const size_t M = (size_t)h->nchunks * 64;
+    const bool dbl = h->p.storage == MCLBM_F64;
+    std::vector<double> kd(dbl ? M : 0, 0.0);
+    std::vector<float> kf(dbl ? 0 : M, 0.0f);
+    for (const auto& sm : h->smp)
+        for (long long k = 0; k < sm.nf; ++k) {
+            const double v = k_box[sm.dbase + sm.pos[k]];
+            if (!(v >= 0) || !isfinite(v)) return fail(h, MCLBM_EINVAL, "reaction rates must be >= 0 and finite");
+            if (dbl) kd[(size_t)(sm.kbase + k)] = v;
+            else kf[(size_t)(sm.kbase + k)] = (float)v;
+        }
+    if (dbl) HIPCHK(h, hipMemcpyAsync(h->kfield, kd.data(), M * 8, hipMemcpyHostToDevice, h->stream));
+    else HIPCHK(h, hipMemcpyAsync(h->kfield, kf.data(), M * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
     return MCLBM_OK;
 }
 
@@ -838,7 +893,8 @@ int mclbm_get_moments(mclbm_handle* h, double* rho, double* u, double* C, int32_
     HIPCHK(h, k_moments(c, rho ? st_rho : nullptr, u ? st_u : nullptr, C ? st_C : nullptr));
     if (rho) HIPCHK(h, hipMemcpyAsync(rho, st_rho, (size_t)h->NC * N * 8, hipMemcpyDeviceToHost, h->stream));
     if (u) HIPCHK(h, hipMemcpyAsync(u, st_u, (size_t)3 * N * 8, hipMemcpyDeviceToHost, h->stream));
-    if (C) HIPCHK(h, hipMemcpyAsync(C, st_C, (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
+    const size_t nsp = (h->p.solute && h->p.product) ? 2 : 1;   // C: [species][N] per sample
+    if (C) HIPCHK(h, hipMemcpyAsync(C, st_C, nsp * (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return MCLBM_OK;
 }
@@ -863,7 +919,7 @@ int mclbm_get_sample_monitors(mclbm_handle* h, int32_t s, double out[16]) {
 
 int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes) {
     if (!h || !bytes) return MCLBM_EINVAL;
-    const size_t nval = (size_t)(h->NC * h->Q + (h->p.solute ? h->QS : 0)) * (size_t)h->Ntot;
+    const size_t nval = (size_t)(h->NC * h->Q + h->HP) * (size_t)h->Ntot;
     *bytes = nval * (raw ? store_bytes(h->p.storage) : 8);
     return MCLBM_OK;
 }
@@ -876,7 +932,7 @@ int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw) {
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const size_t sb = store_bytes(h->p.storage);
     const size_t M = (size_t)h->nchunks * 64;
-    const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
+    const size_t PF = (size_t)h->NC * h->Q, PS = (size_t)h->HP;
     std::vector<unsigned char> dev((PF + PS) * M * sb);
     HIPCHK(h, hipMemcpyAsync(dev.data(), h->fA, PF * M * sb, hipMemcpyDeviceToHost, h->stream));
     if (PS) HIPCHK(h, hipMemcpyAsync(dev.data() + PF * M * sb, h->hA, PS * M * sb, hipMemcpyDeviceToHost, h->stream));
@@ -919,7 +975,7 @@ int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw) {
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
     const size_t sb = store_bytes(h->p.storage);
     const size_t M = (size_t)h->nchunks * 64;
-    const size_t PF = (size_t)h->NC * h->Q, PS = h->p.solute ? (size_t)h->QS : 0;
+    const size_t PF = (size_t)h->NC * h->Q, PS = (size_t)h->HP;
     const size_t nplanes = PF + PS, ib = raw ? sb : 8;
     std::vector<unsigned char> dev((PF + PS) * M * sb, 0);
     const Ctx c = make_ctx(h);

@@ -53,7 +53,7 @@ constexpr uint32_t SOLID_BIT = 0x80000000u;
 
 // ---------------------------------------------------------------------------
 // Storage policies.  R = arithmetic type, T = stored type.  Each population
-// is read once per pass, so the FP64 and FP32 loads are non-temporal: they
+// is read once per pass, so the population loads are non-temporal: they
 // do not displace the pseudo-potentials and indices that neighbouring
 // nodes gather from the caches (measured: 0.89 -> 0.83 ms per 256^3 step).
 // ---------------------------------------------------------------------------
@@ -87,9 +87,13 @@ template <>
 struct Store<ST_F16S> {
     using R = float;
     using T = __half;
-    __device__ static inline R load(const T* p, R shift) { return __half2float(*p) + shift; }
+    __device__ static inline R load(const T* p, R shift) {
+        return __half2float(__ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p))) + shift;
+    }
     __device__ static inline void store(T* p, R v, R shift) { *p = __float2half_rn(v - shift); }
-    __device__ static inline R load_plain(const T* p) { return __half2float(*p); }
+    __device__ static inline R load_plain(const T* p) {
+        return __half2float(__ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p)));
+    }
     __device__ static inline void store_plain(T* p, R v) { *p = __float2half_rn(v); }
 };
 
@@ -117,9 +121,9 @@ template <>
 struct Store<ST_BF16S> {
     using R = float;
     using T = bf16_t;
-    __device__ static inline R load(const T* p, R shift) { return bf16_to_float(p->bits) + shift; }
+    __device__ static inline R load(const T* p, R shift) { return bf16_to_float(__builtin_nontemporal_load(&p->bits)) + shift; }
     __device__ static inline void store(T* p, R v, R shift) { p->bits = float_to_bf16_rne(v - shift); }
-    __device__ static inline R load_plain(const T* p) { return bf16_to_float(p->bits); }
+    __device__ static inline R load_plain(const T* p) { return bf16_to_float(__builtin_nontemporal_load(&p->bits)); }
     __device__ static inline void store_plain(T* p, R v) { p->bits = float_to_bf16_rne(v); }
 };
 
@@ -143,6 +147,13 @@ struct Phys {
     R inv_tau_d;          // 1 / tau_d
     R wet_inv_den;        // 1 / (2 W + k tau_d / (tau_d - 1/2))
     R C_in;
+    int product;          // 1: product species in solute planes QS..2QS-1
+    int hplanes;          // solute planes per fluid node
+    R inv_tau_d2;         // 1 / tau_d of the product
+    R prod_gain;          // k tau_d2 / (tau_d2 - 1/2): product entering per unit C_b
+    R C_in2;
+    const R* kfield;      // per fluid node rate k, or nullptr: the uniform k_wall above
+    R tfac, tfac2;        // tau_d / (tau_d - 1/2) and tau_d2 / (tau_d2 - 1/2)
 };
 
 }  // namespace mclbm

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
 //   dest(i): fluid index of x + c_i (called only where that node is fluid)
 //   x, nx: x coordinate of the node and the box edge (solute seams)
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC, class PsiNb, class Dest>
+template <int LAT, int ST, int NC, int FC, class PsiNb, class Dest>
 __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& P,
                                              const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q], unsigned k,
                                              uint32_t lw, int x, int nx, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q],
@@ -196,7 +196,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
     using R = typename S::R;
     constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
     R u[3];
-    flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
+    flow_collide<LAT, NC, R, decltype(psi_nb), FC>(P, lw, f, psi_nb, u);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
@@ -208,11 +208,12 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
     }
     if (P.solute) {
         // loaded only now: fewer registers live through the flow part
+        const int HP = P.hplanes;
         R h[QS];
 #pragma unroll
-        for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, QS, q, k));
-        solute_collide<LAT, R>(P, h, u);
-        S::store_plain(blk(hB, QS, 0, k), h[0]);
+        for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, HP, q, k));
+        solute_collide<LAT, R>(P, h, u, P.inv_tau_d);
+        S::store_plain(blk(hB, HP, 0, k), h[0]);
         const bool seam_mode = (P.solute == 2);
 #pragma unroll
         for (int d = 1; d < QS; ++d) {
@@ -220,15 +221,49 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
             if (!seam && !(lw & (1u << L::opp[d]))) {
                 const unsigned kd = dest(d);
-                S::store_plain(blk(hB, QS, d, kd), h[d]);
+                S::store_plain(blk(hB, HP, d, kd), h[d]);
                 if (lw & (1u << (L::HOP_SHIFT + d))) {
-                    const R Cb = R(2) * h[d] * P.wet_inv_den;
-                    S::store_plain(blk(hB, QS, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
+                    const R Cb = P.kfield ? R(2) * h[d] / (R(2) * P.Ws + P.kfield[kd] * P.tfac)
+                                          : R(2) * h[d] * P.wet_inv_den;
+                    S::store_plain(blk(hB, HP, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
                 }
                 if (seam_mode && d == L::SXM && x == 1)
-                    S::store_plain(blk(hB, QS, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
+                    S::store_plain(blk(hB, HP, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
             }
-            if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, QS, d, k), h[d]);
+            if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, HP, d, k), h[d]);
+        }
+        if (P.product) {
+            // the product (planes QS..2QS-1): same collision with its own tau, same
+            // streaming; a reacting link creates k C_b of it (C_b of the reacting
+            // species on that link, from h[d] above), entering in its own flux
+            // convention: h2_out = h2_in + k tau2 / (tau2 - 1/2) C_b
+            R h2[QS];
+#pragma unroll
+            for (int q = 0; q < QS; ++q) h2[q] = S::load_plain(blk(hA, HP, QS + q, k));
+            solute_collide<LAT, R>(P, h2, u, P.inv_tau_d2);
+            S::store_plain(blk(hB, HP, QS, k), h2[0]);
+#pragma unroll
+            for (int d = 1; d < QS; ++d) {
+                const int dx = L::cx[d];
+                const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
+                if (!seam && !(lw & (1u << L::opp[d]))) {
+                    const unsigned kd = dest(d);
+                    S::store_plain(blk(hB, HP, QS + d, kd), h2[d]);
+                    if (lw & (1u << (L::HOP_SHIFT + d))) {
+                        if (P.kfield) {
+                            const R kk = P.kfield[kd];
+                            const R Cb = R(2) * h[d] / (R(2) * P.Ws + kk * P.tfac);
+                            S::store_plain(blk(hB, HP, QS + L::opp[d], kd), h2[d] + kk * P.tfac2 * Cb);
+                        } else {
+                            const R Cb = R(2) * h[d] * P.wet_inv_den;
+                            S::store_plain(blk(hB, HP, QS + L::opp[d], kd), h2[d] + P.prod_gain * Cb);
+                        }
+                    }
+                    if (seam_mode && d == L::SXM && x == 1)
+                        S::store_plain(blk(hB, HP, QS + L::SXP, kd), R(2) * P.Ws * P.C_in2 - h2[d]);
+                }
+                if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, HP, QS + d, k), h2[d]);
+            }
         }
     }
 }
@@ -236,7 +271,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC>
+template <int LAT, int ST, int NC, int FC>
 __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, Geo g,
                                                  const typename Store<ST>::T* __restrict__ fA,
                                                  typename Store<ST>::T* __restrict__ fB,
@@ -271,7 +306,7 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
 
         auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
         auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
-        collide_push<LAT, ST, NC>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, fB, hA, hB);
+        collide_push<LAT, ST, NC, FC>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, fB, hA, hB);
     });
 }
 
@@ -322,8 +357,10 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
             for (int q = 0; q < L::QS; ++q) {
                 const R W = (q == 0) ? P.Ws0 : P.Ws;
                 const R eu = R(L::cx[q]) * v[0] + R(L::cy[q]) * v[1] + R(L::cz[q]) * v[2];
-                S::store_plain(blk(hA, L::QS, q, k), W * c0 * (R(1) + eu * P.inv_cs2s));
+                S::store_plain(blk(hA, P.hplanes, q, k), W * c0 * (R(1) + eu * P.inv_cs2s));
             }
+            if (P.product)   // no product at t = 0
+                for (int q = 0; q < L::QS; ++q) S::store_plain(blk(hA, P.hplanes, L::QS + q, k), R(0));
         }
     });
 }
@@ -340,7 +377,7 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
                                              const typename Store<ST>::T* __restrict__ hA,
                                              const typename Store<ST>::R* __restrict__ psi,
                                              typename Store<ST>::R (&rho)[NC], typename Store<ST>::R (&u)[3],
-                                             typename Store<ST>::R& C) {
+                                             typename Store<ST>::R& C, typename Store<ST>::R& C2) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
@@ -366,9 +403,12 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
     auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
     flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
     C = 0;
+    C2 = 0;
     if (P.solute) {
 #pragma unroll
-        for (int q = 0; q < L::QS; ++q) C += S::load_plain(blk(hA, L::QS, q, k));
+        for (int q = 0; q < L::QS; ++q) C += S::load_plain(blk(hA, P.hplanes, q, k));
+        if (P.product)
+            for (int q = 0; q < L::QS; ++q) C2 += S::load_plain(blk(hA, P.hplanes, L::QS + q, k));
     }
 }
 
@@ -395,15 +435,20 @@ __global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R>
         const SampleDev sd = sample_of(g, ch);
         const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
         if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
-        R rho[NC], u[3], C;
-        node_moments<LAT, ST, NC>(P, g, sd, k, fA, hA, psi, rho, u, C);
+        R rho[NC], u[3], C, C2;
+        node_moments<LAT, ST, NC>(P, g, sd, k, fA, hA, psi, rho, u, C, C2);
         const size_t N = sd.N;
         const unsigned n = g.pos[k];
         if (rho_out)
             for (int s = 0; s < NC; ++s) rho_out[(size_t)NC * sd.dbase + s * N + n] = (double)rho[s];
         if (u_out)
             for (int a = 0; a < 3; ++a) u_out[(size_t)3 * sd.dbase + a * N + n] = (double)u[a];
-        if (C_out) C_out[(size_t)sd.dbase + n] = (double)C;
+        if (C_out) {
+            // [species][N] per sample block: the product follows the reacting species
+            const int nsp = P.product ? 2 : 1;
+            C_out[(size_t)nsp * sd.dbase + n] = (double)C;
+            if (P.product) C_out[(size_t)2 * sd.dbase + N + n] = (double)C2;
+        }
     });
 }
 
@@ -436,7 +481,8 @@ __global__ void __launch_bounds__(256) k_monitor(Phys<typename Store<ST>::R> P, 
         for (int q = 0; q < MON_NV; ++q) v[q] = 0.0;
         if ((int)(k - (unsigned)sd.kbase) < sd.Nf) {
             R rho[NC], u[3], C;
-            node_moments<LAT, ST, NC>(P, g, sd, k, fA, hA, psi, rho, u, C);
+            R C2;
+            node_moments<LAT, ST, NC>(P, g, sd, k, fA, hA, psi, rho, u, C, C2);
             R phi = 0;
             if (NC == 2) {
                 const R tot = rho[0] + rho[NC - 1];
@@ -547,6 +593,15 @@ Phys<R> make_phys(const Ctx& c) {
     P.inv_tau_d = (R)(1.0 / tau_d);
     P.wet_inv_den = (R)(1.0 / (2.0 * Ws + c.k_wall * tau_d / (tau_d - 0.5)));
     P.C_in = (R)c.C_in;
+    P.product = c.product;
+    P.hplanes = c.hplanes;
+    const double tau_d2 = (c.D2 > 0 ? c.D2 : 1.0) / cs2s + 0.5;
+    P.inv_tau_d2 = (R)(1.0 / tau_d2);
+    P.prod_gain = (R)(c.k_wall * tau_d2 / (tau_d2 - 0.5));
+    P.C_in2 = (R)c.C_in2;
+    P.kfield = (const R*)c.kfield;
+    P.tfac = (R)(tau_d / (tau_d - 0.5));
+    P.tfac2 = (R)(tau_d2 / (tau_d2 - 0.5));
     return P;
 }
 template Phys<float> make_phys<float>(const Ctx&);
@@ -595,8 +650,12 @@ static hipError_t step_t(const Ctx& c) {
     // pass, so it starts on the chunks the density pass read last
     Geo gr = g;
     gr.reverse = 1;
-    hipLaunchKernelGGL((k_collide<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,
-                       (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
+    if (c.forcing == 0)
+        hipLaunchKernelGGL((k_collide<LAT, ST, NC, 0>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,
+                           (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
+    else
+        hipLaunchKernelGGL((k_collide<LAT, ST, NC, 1>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,
+                           (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
     return hipGetLastError();
 }
 
@@ -623,7 +682,7 @@ static hipError_t moments_t(const Ctx& c, double* rho, double* u, double* C) {
     };
     fill(rho, (long long)NC * c.Ntot);
     fill(u, 3LL * c.Ntot);
-    fill(C, c.Ntot);
+    fill(C, (1LL + c.product) * c.Ntot);   // one plane per solute species; solid nodes stay 0
     hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,
                        (SR<ST>*)c.psi);
     hipLaunchKernelGGL((k_moments_out<LAT, ST, NC>), grid, dim3(256), 0, c.stream, P, g, (const STT<ST>*)c.fA,

@@ -27,6 +27,10 @@ struct Ctx {
     int forcing, solute;
     double tau[2], G[2][2], Gads[2], rho0, accel[3];
     double D, J0, k_wall, C_in;
+    const void* kfield;         // per fluid node reaction rate (arith type) or nullptr: k_wall
+    int product;                // second solute species produced at the reacting walls
+    int hplanes;                // solute planes per fluid node (QS per species, 0 without solute)
+    double D2, C_in2;
     double rhobar[2];           // storage shift (used by *_SHIFT storage only)
     hipStream_t stream;
     void *fA, *fB, *hA, *hB;    // populations (current state in A), blocks of 64 fluid nodes

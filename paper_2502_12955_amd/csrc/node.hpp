@@ -71,7 +71,10 @@ __device__ __forceinline__ R cdot(int i, R x, R y, R z) {
     return r;
 }
 
-template <int LAT, int NC, typename R, class PsiNb>
+// FC: forcing scheme fixed at compile time (0 Guo, 1 Shan-Chen velocity
+// shift) or -1 to follow P.forcing; the step kernel is compiled per scheme, so
+// only one branch occupies its registers.
+template <int LAT, int NC, typename R, class PsiNb, int FC = -1>
 __device__ __forceinline__ void flow_collide(const Phys<R>& P, uint32_t lw, R (&f)[NC][Lat<LAT>::Q],
                                              PsiNb psi_nb, R (&u)[3]) {
     using L = Lat<LAT>;
@@ -154,7 +157,7 @@ __device__ __forceinline__ void flow_collide(const Phys<R>& P, uint32_t lw, R (&
     auto wclass = [](int i) { return i == 0 ? 0 : (L::wn[i] == WN1 ? 1 : 2); };
     const R w0 = R(WN0) / R(36), w1 = R(WN1) / R(36), w2 = R(WN2) / R(36);
 
-    if (P.forcing == 0) {
+    if (FC == 0 || (FC < 0 && P.forcing == 0)) {
         const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const R K = R(1) - R(1.5) * uu;
         R wr[NC][3], lw3[NC][3], uF[NC], om[NC];
@@ -215,7 +218,8 @@ __device__ __forceinline__ void flow_collide(const Phys<R>& P, uint32_t lw, R (&
 
 // per-node solute collision; h overwritten with post-collision values
 template <int LAT, typename R>
-__device__ __forceinline__ void solute_collide(const Phys<R>& P, R (&h)[Lat<LAT>::QS], const R (&u)[3]) {
+__device__ __forceinline__ void solute_collide(const Phys<R>& P, R (&h)[Lat<LAT>::QS], const R (&u)[3],
+                                               R inv_tau) {
     using L = Lat<LAT>;
     R C = 0;
 #pragma unroll
@@ -225,7 +229,7 @@ __device__ __forceinline__ void solute_collide(const Phys<R>& P, R (&h)[Lat<LAT>
         const R W = (k == 0) ? P.Ws0 : P.Ws;
         const R eu = R(L::cx[k]) * u[0] + R(L::cy[k]) * u[1] + R(L::cz[k]) * u[2];
         const R heq = W * C * (R(1) + eu * P.inv_cs2s);
-        h[k] = h[k] + P.inv_tau_d * (heq - h[k]);
+        h[k] = h[k] + inv_tau * (heq - h[k]);
     }
 }
 

@@ -39,7 +39,8 @@ class Params(ct.Structure):
                 ("storage", ct.c_int32), ("monitor_every", ct.c_int32), ("reserved", ct.c_int32),
                 ("tau", ct.c_double * 2), ("G", (ct.c_double * 2) * 2), ("G_ads", ct.c_double * 2),
                 ("rho0", ct.c_double), ("accel", ct.c_double * 3), ("D", ct.c_double),
-                ("J0", ct.c_double), ("k_wall", ct.c_double), ("C_in", ct.c_double)]
+                ("J0", ct.c_double), ("k_wall", ct.c_double), ("C_in", ct.c_double),
+                ("product", ct.c_int32), ("rate_field", ct.c_int32), ("D2", ct.c_double), ("C_in2", ct.c_double)]
 
 
 def _enum(v, table):
@@ -72,7 +73,18 @@ def params_from_dict(p: dict) -> Params:
     s.J0 = float(p.get("J0", 0.1))
     s.k_wall = float(p.get("k_wall", 0.0))
     s.C_in = float(p.get("C_in", 0.0))
+    s.product = int(p.get("product", 0))
+    s.rate_field = int(p.get("rate_field", 0))
+    s.D2 = float(p.get("D2", 0.1))
+    s.C_in2 = float(p.get("C_in2", 0.0))
     return s
+
+
+def n_species(p: dict) -> int:
+    """Solute species carried: 0 (solute off), 1, or 2 with the product."""
+    if _enum(p.get("solute", "off"), SOLUTE) == 0:
+        return 0
+    return 2 if int(p.get("product", 0)) else 1
 
 
 _lib = None
@@ -82,7 +94,7 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
-           "mclbm_synchronize", "mclbm_autotune", "mclbm_destroy", "mclbm_last_error")
+           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_destroy", "mclbm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -98,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_required_bytes.argtypes = [P, ct.POINTER(sz)]
     lib.mclbm_init_lattice.argtypes = [P, vp, sz, vp, ct.POINTER(vp)]
     lib.mclbm_set_geometry.argtypes = [vp, vp, ct.POINTER(i64)]
+    lib.mclbm_set_wall_rate.argtypes = [vp, vp]
     lib.mclbm_get_geometry.argtypes = [vp, vp, vp, vp]
     lib.mclbm_init_fields.argtypes = [vp, vp, vp, vp]
     lib.mclbm_step.argtypes = [vp, i64]
@@ -183,10 +196,23 @@ def step(h, n: int, allow_diverged=False):
     return _check(load().mclbm_step(h, int(n)), h, allow)
 
 
-def get_moments(h, ncomp, N):
+def arrhenius(T, A, E_over_R):
+    """First-order wall reaction rate k = A exp(-E / (R_u T)) (eq:reactO2) of a
+    temperature field T [K]; E_over_R = E / R_u in K."""
+    return A * np.exp(-E_over_R / np.asarray(T, np.float64))
+
+
+def set_wall_rate(h, k_box):
+    """Per-node reaction rate [N] (box nodes; needs rate_field=1 and set_geometry first)."""
+    k = np.ascontiguousarray(k_box, np.float64).reshape(-1)
+    _check(load().mclbm_set_wall_rate(h, _ptr(k)), h)
+
+
+def get_moments(h, ncomp, N, nspecies=1):
+    """rho [ncomp][N], u [3][N], C [N] (or [2][N] with the product species)."""
     rho = np.zeros((ncomp, N))
     u = np.zeros((3, N))
-    C = np.zeros(N)
+    C = np.zeros((2, N)) if nspecies == 2 else np.zeros(N)
     _check(load().mclbm_get_moments(h, _ptr(rho), _ptr(u), _ptr(C), 0), h)
     return rho, u, C
 
@@ -344,11 +370,14 @@ class Lattice:
                     None if u is None else np.asarray(u).reshape(3, self.N),
                     None if C is None else np.asarray(C).reshape(self.N))
 
+    def set_wall_rate(self, k_box):
+        set_wall_rate(self.h, np.asarray(k_box).reshape(self.N))
+
     def step(self, n=1, allow_diverged=False):
         return step(self.h, n, allow_diverged)
 
     def moments(self):
-        return get_moments(self.h, self.ncomp, self.N)
+        return get_moments(self.h, self.ncomp, self.N, n_species(self.params))
 
     def monitors(self):
         return get_monitors(self.h)
@@ -452,9 +481,10 @@ class Batch(Lattice):
     def moments(self):
         rho = np.zeros(self.ncomp * self.N)
         u = np.zeros(3 * self.N)
-        C = np.zeros(self.N)
+        nsp = max(1, n_species(self.plist[0]))
+        C = np.zeros(nsp * self.N)
         _check(load().mclbm_get_moments(self.h, _ptr(rho), _ptr(u), _ptr(C), 0), self.h)
-        return self.split(rho, self.ncomp), self.split(u, 3), self.split(C, 1)
+        return self.split(rho, self.ncomp), self.split(u, 3), self.split(C, nsp)
 
     def sample_monitors(self, s):
         return get_sample_monitors(self.h, s)

@@ -41,6 +41,19 @@ def test_required_bytes_and_validation():
         mclbm.required_bytes(dict(p, D=0.0))
     with pytest.raises(mclbm.MclbmError):
         mclbm.required_bytes(dict(p, solute="inlet_outlet_x", nx=1))
+    # the product species: needs the solute and D2 > 0, and adds one more set of solute planes
+    nbp = mclbm.required_bytes(dict(p, product=1, D2=0.2))
+    assert nbp - nb >= 2 * 7 * 4 * 64 ** 3
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, product=1, D2=0.0))
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, product=1, solute="off"))
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, product=2))
+    # a per-node rate field needs the solute and adds one value per fluid node
+    assert mclbm.required_bytes(dict(p, rate_field=1)) >= nb + 4 * 64 ** 3
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, rate_field=1, solute="off"))
 
 
 def test_arena_too_small_is_rejected_before_any_device_call():

@@ -341,3 +341,85 @@ def test_guo_forcing_coexistence_is_independent_of_tau():
     s1, _, _ = _flat_slab("sc", 1.0)
     s2, _, _ = _flat_slab("sc", 0.8)
     assert abs(s1[32] - s2[32]) > 1e-2
+
+
+# ----------------------------------------------------------------------------- product species
+@pytest.mark.parametrize("lat,J0,k,D2", [("D3Q19", 0.1, 1e-2, 0.12), ("D2Q9", 0.4, 3e-2, 0.5),
+                                         ("D3Q19", 0.1, 5.0, 0.3)])
+def test_product_steady_state_balances_the_consumed_flux(lat, J0, k, D2):
+    """eq:reactO2 and eq:reactCO2 with one CO2 per O2 (eq:react), 1-D, inlet at node 0
+    (C_O2 = C_in, C_CO2 = 0), reactive wet node at m = nx - 2, u = 0.  At steady state
+    both profiles are linear and the fluxes cancel everywhere: D C_O2 + D2 C_CO2 =
+    D C_in, so C_CO2(x) = D (C_in - C_O2(x)) / D2 = D C_in k x / (D2 (D + k m)).  A
+    product rule written in the reacting species' flux convention instead of its own
+    would miss this whenever D2 != D."""
+    nx, D, C_in = 18, 0.3, 0.7
+    p = inputs.base_params(lattice=lat, nx=nx, ny=1, nz=1, ncomp=1, G=((0, 0), (0, 0)),
+                           solute="inlet_outlet_x", D=D, J0=J0, k_wall=k, C_in=C_in, product=1, D2=D2,
+                           C_in2=0.0)
+    mask = np.zeros((1, 1, nx), np.uint8)
+    mask[0, 0, nx - 1] = 1
+    rho = np.where(mask == 0, 1.0, 0.0)[None]
+    m, f, h = _state(p, mask, rho, None, np.zeros((1, 1, nx)))
+    oracle.step(p, m, f, h, 60000)
+    _, _, Cn = oracle.moments(p, m, f, h)
+    c1, c2 = Cn[0][: nx - 1], Cn[1][: nx - 1]
+    mm = nx - 2
+    x = np.arange(nx - 1)
+    assert np.max(np.abs(c1 - C_in * (1 - k * x / (D + k * mm)))) < 1e-11
+    assert np.max(np.abs(c2 - D * C_in * k * x / (D2 * (D + k * mm)))) < 1e-10
+
+
+def test_no_product_without_reaction_and_growth_with_it():
+    """k = 0: the product planes stay exactly zero (no source anywhere); k > 0: the
+    product appears only where a reacting wall feeds it, and only while O2 is there."""
+    p, mask, rho, _, _ = inputs.porous_case(shape=(10, 12, 14), radius=3, porosity=0.55, blob_radius=2)
+    p.update(solute="periodic", k_wall=0.0, D=0.15, product=1, D2=0.2)
+    C = np.where(mask == 0, 0.8, 0.0)
+    m, f, h = _state(p, mask, rho, None, C)
+    oracle.step(p, m, f, h, 50)
+    _, _, Cn = oracle.moments(p, m, f, h)
+    assert np.all(Cn[1] == 0.0)
+    p["k_wall"] = 0.05
+    m, f, h = _state(p, mask, rho, None, C)
+    oracle.step(p, m, f, h, 50)
+    _, _, Cn = oracle.moments(p, m, f, h)
+    assert Cn[1].min() >= 0.0 and Cn[1].sum() > 0.0 and Cn[0].sum() < C.sum()
+    p2 = dict(p, product=1)
+    m, f, h = _state(p2, mask, rho, None, np.zeros_like(C))      # no O2: nothing to convert
+    oracle.step(p2, m, f, h, 50)
+    _, _, Cz = oracle.moments(p2, m, f, h)
+    assert np.all(Cz[1] == 0.0)
+
+
+# ----------------------------------------------------------------------------- rate field
+def test_arrhenius_rate_field_enters_at_the_wall_node():
+    """A prescribed per-node rate k(x) = A exp(-E / (R_u T(x))) (eq:reactO2 with a
+    temperature field): only the rate at the reacting wet node matters, so the 1-D
+    steady state is the uniform-k closed form with k = k(m); a field equal to k_wall
+    everywhere reproduces the uniform run bit for bit."""
+    nx, D, C_in, J0 = 18, 0.3, 0.7, 0.1
+    T = 600.0 + 40.0 * np.arange(nx)                      # prescribed temperature, K
+    A, E_R = 2.0, 3000.0
+    k_node = A * np.exp(-E_R / T)
+    p = inputs.base_params(lattice="D3Q19", nx=nx, ny=1, nz=1, ncomp=1, G=((0, 0), (0, 0)),
+                           solute="inlet_outlet_x", D=D, J0=J0, k_wall=0.0, C_in=C_in, k_node=k_node)
+    mask = np.zeros((1, 1, nx), np.uint8)
+    mask[0, 0, nx - 1] = 1
+    rho = np.where(mask == 0, 1.0, 0.0)[None]
+    m, f, h = _state(p, mask, rho, None, np.zeros((1, 1, nx)))
+    oracle.step(p, m, f, h, 40000)
+    _, _, Cn = oracle.moments(p, m, f, h)
+    mm = nx - 2
+    km = k_node[mm]
+    x = np.arange(nx - 1)
+    assert np.max(np.abs(Cn[: nx - 1] - C_in * (1 - km * x / (D + km * mm)))) < 1e-11
+    # a field equal to k_wall everywhere = the uniform rate
+    pu = dict(p, k_wall=0.05)
+    pu.pop("k_node")
+    pf = dict(pu, k_node=np.full(nx, 0.05))
+    m, f1, h1 = _state(pu, mask, rho, None, np.zeros((1, 1, nx)))
+    _, f2, h2 = _state(pf, mask, rho, None, np.zeros((1, 1, nx)))
+    oracle.step(pu, m, f1, h1, 500)
+    oracle.step(pf, m, f2, h2, 500)
+    assert np.array_equal(h1, h2)
