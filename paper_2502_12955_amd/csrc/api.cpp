@@ -207,7 +207,7 @@ Layout layout_for(const mclbm_params* ps, int n) {
     const size_t hb = p.solute ? (size_t)QS * (p.product ? 2 : 1) * M * sb : 0;
     L.hA = take(hb);
     L.hB = take(hb);
-    L.kfield = take(p.solute && p.rate_field ? (size_t)M * ab : 0);
+    L.kfield = take(p.solute && p.rate_field ? (size_t)2 * M * ab : 0);
     L.map = take((size_t)Ntot * 4);
     L.pos = take((size_t)M * 4);
     L.links = take((size_t)M * 4);
@@ -756,20 +756,31 @@ int mclbm_set_wall_rate(mclbm_handle* h, const double* k_box) {
     if (!h->kfield) return fail(h, MCLBM_ESTATE, "the lattice was created without rate_field");
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
     if (!k_box) return fail(h, MCLBM_EINVAL, "k_box is NULL");
+    // stored per fluid node as the two factors the wall rule uses (plane 0: the
+    // reacting species' 1 / (2 W + k tau_d / (tau_d - 1/2)), plane 1: the product's
+    // gain k tau_d2 / (tau_d2 - 1/2)), in the kernels' arithmetic type
     const size_t M = (size_t)h->nchunks * 64;
     const bool dbl = h->p.storage == MCLBM_F64;
-    std::vector<double> kd(dbl ? M : 0, 0.0);
-    std::vector<float> kf(dbl ? 0 : M, 0.0f);
+    const int QS = h->QS;
+    const double Ws = (1.0 - h->p.J0) / (double)(QS - 1), cs2s = 2.0 * Ws;
+    const double tau_d = h->p.D / cs2s + 0.5;
+    const double tau_d2 = (h->p.D2 > 0 ? h->p.D2 : 1.0) / cs2s + 0.5;
+    std::vector<double> kv(2 * M, 0.0);
     for (const auto& sm : h->smp)
         for (long long k = 0; k < sm.nf; ++k) {
             const double v = k_box[sm.dbase + sm.pos[k]];
             if (!(v >= 0) || !isfinite(v)) return fail(h, MCLBM_EINVAL, "reaction rates must be >= 0 and finite");
-            if (dbl) kd[(size_t)(sm.kbase + k)] = v;
-            else kf[(size_t)(sm.kbase + k)] = (float)v;
+            kv[(size_t)(sm.kbase + k)] = 1.0 / (2.0 * Ws + v * tau_d / (tau_d - 0.5));
+            kv[M + (size_t)(sm.kbase + k)] = v * tau_d2 / (tau_d2 - 0.5);
         }
-    if (dbl) HIPCHK(h, hipMemcpyAsync(h->kfield, kd.data(), M * 8, hipMemcpyHostToDevice, h->stream));
-    else HIPCHK(h, hipMemcpyAsync(h->kfield, kf.data(), M * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (dbl) {
+        HIPCHK(h, hipMemcpyAsync(h->kfield, kv.data(), 2 * M * 8, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> kf(kv.begin(), kv.end());
+        HIPCHK(h, hipMemcpyAsync(h->kfield, kf.data(), 2 * M * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
     drop_graphs(h);
     return MCLBM_OK;
 }

@@ -152,8 +152,10 @@ struct Phys {
     R inv_tau_d2;         // 1 / tau_d of the product
     R prod_gain;          // k tau_d2 / (tau_d2 - 1/2): product entering per unit C_b
     R C_in2;
-    const R* kfield;      // per fluid node rate k, or nullptr: the uniform k_wall above
-    R tfac, tfac2;        // tau_d / (tau_d - 1/2) and tau_d2 / (tau_d2 - 1/2)
+    // per fluid node rate field (nullptr: the uniform k_wall above), two planes
+    // of kstride values: 1 / (2 W + k tau_d / (tau_d - 1/2)) and k tau_d2 / (tau_d2 - 1/2)
+    const R* kfield;
+    unsigned kstride;
 };
 
 }  // namespace mclbm

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
 //   dest(i): fluid index of x + c_i (called only where that node is fluid)
 //   x, nx: x coordinate of the node and the box edge (solute seams)
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC, int FC, class PsiNb, class Dest>
+template <int LAT, int ST, int NC, int FC, int PR, int KF, class PsiNb, class Dest>
 __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& P,
                                              const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q], unsigned k,
                                              uint32_t lw, int x, int nx, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q],
@@ -208,7 +208,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
     }
     if (P.solute) {
         // loaded only now: fewer registers live through the flow part
-        const int HP = P.hplanes;
+        constexpr int HP = QS * (1 + PR);   // solute planes per node (= P.hplanes)
         R h[QS];
 #pragma unroll
         for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, HP, q, k));
@@ -223,8 +223,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
                 const unsigned kd = dest(d);
                 S::store_plain(blk(hB, HP, d, kd), h[d]);
                 if (lw & (1u << (L::HOP_SHIFT + d))) {
-                    const R Cb = P.kfield ? R(2) * h[d] / (R(2) * P.Ws + P.kfield[kd] * P.tfac)
-                                          : R(2) * h[d] * P.wet_inv_den;
+                    const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
                     S::store_plain(blk(hB, HP, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
                 }
                 if (seam_mode && d == L::SXM && x == 1)
@@ -232,7 +231,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             }
             if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, HP, d, k), h[d]);
         }
-        if (P.product) {
+        if (PR) {
             // the product (planes QS..2QS-1): same collision with its own tau, same
             // streaming; a reacting link creates k C_b of it (C_b of the reacting
             // species on that link, from h[d] above), entering in its own flux
@@ -250,14 +249,9 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
                     const unsigned kd = dest(d);
                     S::store_plain(blk(hB, HP, QS + d, kd), h2[d]);
                     if (lw & (1u << (L::HOP_SHIFT + d))) {
-                        if (P.kfield) {
-                            const R kk = P.kfield[kd];
-                            const R Cb = R(2) * h[d] / (R(2) * P.Ws + kk * P.tfac);
-                            S::store_plain(blk(hB, HP, QS + L::opp[d], kd), h2[d] + kk * P.tfac2 * Cb);
-                        } else {
-                            const R Cb = R(2) * h[d] * P.wet_inv_den;
-                            S::store_plain(blk(hB, HP, QS + L::opp[d], kd), h2[d] + P.prod_gain * Cb);
-                        }
+                        const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
+                        const R gain = KF ? P.kfield[P.kstride + kd] : P.prod_gain;
+                        S::store_plain(blk(hB, HP, QS + L::opp[d], kd), h2[d] + gain * Cb);
                     }
                     if (seam_mode && d == L::SXM && x == 1)
                         S::store_plain(blk(hB, HP, QS + L::SXP, kd), R(2) * P.Ws * P.C_in2 - h2[d]);
@@ -271,7 +265,10 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC, int FC>
+// FC: forcing scheme (0 Guo, 1 Shan-Chen); SV: solute variant, bit 0 the
+// product species, bit 1 the per-node rate field (each compiled in or out, so
+// the plain path keeps its registers and schedule)
+template <int LAT, int ST, int NC, int FC, int SV>
 __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, Geo g,
                                                  const typename Store<ST>::T* __restrict__ fA,
                                                  typename Store<ST>::T* __restrict__ fB,
@@ -306,7 +303,7 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
 
         auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
         auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
-        collide_push<LAT, ST, NC, FC>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, fB, hA, hB);
+        collide_push<LAT, ST, NC, FC, (SV & 1), (SV >> 1)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, fB, hA, hB);
     });
 }
 
@@ -600,8 +597,7 @@ Phys<R> make_phys(const Ctx& c) {
     P.prod_gain = (R)(c.k_wall * tau_d2 / (tau_d2 - 0.5));
     P.C_in2 = (R)c.C_in2;
     P.kfield = (const R*)c.kfield;
-    P.tfac = (R)(tau_d / (tau_d - 0.5));
-    P.tfac2 = (R)(tau_d2 / (tau_d2 - 0.5));
+    P.kstride = (unsigned)(c.nchunks * 64);
     return P;
 }
 template Phys<float> make_phys<float>(const Ctx&);
@@ -650,12 +646,25 @@ static hipError_t step_t(const Ctx& c) {
     // pass, so it starts on the chunks the density pass read last
     Geo gr = g;
     gr.reverse = 1;
-    if (c.forcing == 0)
-        hipLaunchKernelGGL((k_collide<LAT, ST, NC, 0>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,
-                           (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
-    else
-        hipLaunchKernelGGL((k_collide<LAT, ST, NC, 1>), grid, dim3(bs), 0, c.stream, P, gr, (const STT<ST>*)c.fA,
-                           (STT<ST>*)c.fB, (const STT<ST>*)c.hA, (STT<ST>*)c.hB, (const SR<ST>*)c.psi);
+    const STT<ST>* fA = (const STT<ST>*)c.fA;
+    STT<ST>* fB = (STT<ST>*)c.fB;
+    const STT<ST>* hA = (const STT<ST>*)c.hA;
+    STT<ST>* hB = (STT<ST>*)c.hB;
+    const SR<ST>* psi = (const SR<ST>*)c.psi;
+#define MCLBM_COLLIDE(FC, SV)                                                                              \
+    hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, hA, hB, psi)
+    const int sv = (c.product ? 1 : 0) + (c.kfield ? 2 : 0);
+    switch (c.forcing * 4 + sv) {
+        case 0: MCLBM_COLLIDE(0, 0); break;
+        case 1: MCLBM_COLLIDE(0, 1); break;
+        case 2: MCLBM_COLLIDE(0, 2); break;
+        case 3: MCLBM_COLLIDE(0, 3); break;
+        case 4: MCLBM_COLLIDE(1, 0); break;
+        case 5: MCLBM_COLLIDE(1, 1); break;
+        case 6: MCLBM_COLLIDE(1, 2); break;
+        default: MCLBM_COLLIDE(1, 3); break;
+    }
+#undef MCLBM_COLLIDE
     return hipGetLastError();
 }
 

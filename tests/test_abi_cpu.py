@@ -54,6 +54,10 @@ def test_required_bytes_and_validation():
     assert mclbm.required_bytes(dict(p, rate_field=1)) >= nb + 4 * 64 ** 3
     with pytest.raises(mclbm.MclbmError):
         mclbm.required_bytes(dict(p, rate_field=1, solute="off"))
+    # sizes beyond the 32-bit fluid and box indexing are refused before any allocation
+    with pytest.raises(mclbm.MclbmError) as e:
+        mclbm.required_bytes(dict(p, nx=2048, ny=2048, nz=1024))
+    assert e.value.code == mclbm.EINVAL and "32-bit" in mclbm.last_error()
 
 
 def test_arena_too_small_is_rejected_before_any_device_call():
