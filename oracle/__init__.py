@@ -237,6 +237,29 @@ def step(p, mask, f, h, nsteps=1):
     return f, h
 
 
+def deposit(p, mask, f, h, Cps, DP):
+    """Particle deposition after a step (sec:particle_deposition,
+    eq:surface_deposition): deposits grow at nodes next to a solid, nodes whose
+    deposit exceeds 1 turn solid (then the pinch rule again).  mask (uint8),
+    f, h and Cps ([N]) are updated in place; returns the nodes made solid."""
+    for a, dt in ((mask, np.uint8), (f, np.float64), (h, np.float64), (Cps, np.float64)):
+        assert a.dtype == dt and a.flags.c_contiguous
+    s = _struct(p)
+    lib = _load()
+    lib.orc_deposit.restype = ct.c_int64
+    return int(lib.orc_deposit(ct.byref(s), _ptr(mask, ct.c_uint8), _ptr(f, ct.c_double), _ptr(h, ct.c_double),
+                               _ptr(Cps, ct.c_double), ct.c_double(float(DP))))
+
+
+def step_deposit(p, mask, f, h, Cps, DP, nsteps):
+    """nsteps of (one step, then deposit); returns the nodes made solid."""
+    total = 0
+    for _ in range(int(nsteps)):
+        step(p, mask, f, h, 1)
+        total += deposit(p, mask, f, h, Cps, DP)
+    return total
+
+
 def step_nodes(p, mask, f, h, nodes):
     """Populations after one step at the given fluid nodes, from the state at t."""
     m = np.ascontiguousarray(mask, np.uint8)

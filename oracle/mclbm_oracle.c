@@ -38,6 +38,10 @@
  *   - fluid voxels pinched between two solids along one axis are made solid
  *     before anything else (in inlet/outlet mode the planes beyond x = 0 and
  *     x = nx-1 count as solid for this test).
+ *   - particle deposition: "near the substrate" means a solid neighbour along
+ *     any flow-lattice link; the deposit does not remove particles from the
+ *     fluid (the paper's update has no sink term); nodes that turn solid lose
+ *     their populations, and the pinch rule is applied again afterwards.
  */
 #include <math.h>
 #include <stdint.h>
@@ -535,6 +539,54 @@ void orc_step(const orc_params* p, const uint8_t* mask, double* f, double* h, in
     free(psi);
     free(fstar);
     free(hstar);
+}
+
+/* ---------------------------------------------------------------------------
+ * Particle deposition (sec:particle_deposition, eq:surface_deposition), applied
+ * after a full step.  The reacting solute species (planes 0..QS-1 of h) is the
+ * particle mass fraction C_p.
+ *   1. every fluid node n next to the substrate (some flow-lattice neighbour
+ *      n + c_i, i >= 1, is solid; periodic wrap) adds DP times the sum of its
+ *      particle populations after streaming to its deposit:
+ *        C_ps(n, t+1) = C_ps(n, t) + DP * sum_k h_k(n, t+1)
+ *   2. every fluid node whose deposit exceeds 1 turns solid (all at once);
+ *   3. the pinch rule of the geometry is applied again to the new mask;
+ *   4. every node that turned solid in 2 or 3 loses its populations and its
+ *      deposit (set to 0).
+ * mask, f, h and Cps ([N]) are updated in place; returns the number of nodes
+ * that turned solid.
+ * ------------------------------------------------------------------------- */
+int64_t orc_deposit(const orc_params* p, uint8_t* mask, double* f, double* h, double* Cps, double DP) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    int NC = p->ncomp;
+    int NS = p->solute ? (p->product ? 2 : 1) : 0;
+    uint8_t* before = (uint8_t*)malloc((size_t)N);
+    memcpy(before, mask, (size_t)N);
+    for (int64_t n = 0; n < N; ++n) {
+        if (before[n]) continue;
+        int near = 0;
+        for (int i = 1; i < L.Q; ++i)
+            if (before[nbr(p, n, L.c[i])]) near = 1;
+        if (!near) continue;
+        double C = 0.0;
+        for (int k = 0; k < S.Q; ++k) C += h[(int64_t)k * N + n];
+        Cps[n] += DP * C;
+    }
+    for (int64_t n = 0; n < N; ++n)
+        if (!before[n] && Cps[n] > 1.0) mask[n] = 1;
+    orc_pinch_fill(p, mask);
+    int64_t count = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        if (!mask[n] || before[n]) continue;
+        ++count;
+        for (int j = 0; j < NC * L.Q; ++j) f[(int64_t)j * N + n] = 0.0;
+        for (int j = 0; j < NS * S.Q; ++j) h[(int64_t)j * N + n] = 0.0;
+        Cps[n] = 0.0;
+    }
+    free(before);
+    return count;
 }
 
 /* Post-step populations at selected fluid nodes only, from the state at t.
