@@ -90,6 +90,14 @@ typedef struct {
                               mclbm_set_wall_rate (k_wall until then); 0: uniform k_wall */
     double D2;             /* product diffusivity, > 0 when the product is on */
     double C_in2;          /* product inlet concentration (INLET_OUTLET_X) */
+    int32_t deposition;    /* 1: particle deposition (sec:particle_deposition, eq:surface_deposition):
+                              the reacting solute species is the particle mass fraction C_p;
+                              after every step each fluid node with a solid flow-lattice
+                              neighbour adds dep_prob * C_p to its deposit C_ps, and the
+                              nodes whose deposit exceeds 1 turn solid (see mclbm_step);
+                              needs the solute on and a single lattice (not a batch); 0: off */
+    int32_t reserved2;     /* must be 0 */
+    double dep_prob;       /* deposition probability DP, > 0 when deposition is on */
 } mclbm_params;
 
 /* Device bytes the lattice needs for these parameters (populations A and B,
@@ -105,7 +113,8 @@ int mclbm_required_bytes(const mclbm_params* p, size_t* bytes);
  * handle.  Errors: EINVAL (parameters: tau <= 1/2, bad dimensions or enums,
  * D <= 0 with the solute on, J0 outside [0, 1), k_wall < 0, rho0 <= 0,
  * monitor_every < 1, product or rate_field without the solute, D2 <= 0 with
- * the product, nonzero reserved field), ENOMEM (arena too small), EHIP. */
+ * the product, deposition without the solute or with dep_prob <= 0, nonzero
+ * reserved fields), ENOMEM (arena too small), EHIP. */
 int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_bytes,
                        void* hip_stream, mclbm_handle** out);
 
@@ -146,8 +155,26 @@ int mclbm_set_wall_rate(mclbm_handle* h, const double* k_box);
 /* Advance n >= 0 time steps (queued on the stream).  Monitors run after
  * every step whose index is a multiple of monitor_every; if any ran, the
  * call synchronises and returns MCLBM_EDIVERGED when the last one counted a
- * non-finite value.  Errors: ESTATE before init_fields, EINVAL (n < 0). */
+ * non-finite value.  Errors: ESTATE before init_fields, EINVAL (n < 0).
+ *
+ * With deposition on, every step is followed by the deposit update
+ * (eq:surface_deposition) and a synchronisation that reads how many deposits
+ * exceed 1.  If any do, those nodes turn solid before the next step: the
+ * geometry is rebuilt as by mclbm_set_geometry from the current solid mask
+ * plus those nodes (the pinch rule applies again, and the nodes it fills turn
+ * solid too), the populations and deposits of the remaining fluid nodes are
+ * carried over bit for bit, and those of the new solid nodes are dropped.  A
+ * per-node rate field set with mclbm_set_wall_rate is kept.  The residual
+ * snapshot starts over.  Graph replay is not used with deposition.  Returns
+ * EINVAL (handle unusable) if deposition leaves no fluid node. */
 int mclbm_step(mclbm_handle* h, int64_t n);
+
+/* Deposit C_ps of every box node (host FP64 [N], x fastest; 0 on solid nodes
+ * and on nodes that never had a solid neighbour) and the number of nodes that
+ * deposition has turned solid since init_fields (the pinch rule's included;
+ * may be NULL).  Needs deposition = 1.  Errors: ESTATE before init_fields,
+ * EINVAL. */
+int mclbm_get_deposit(mclbm_handle* h, double* Cps, int64_t* converted);
 
 /* Macroscopic fields of the current (post-streaming) state: rho_s = sum_i f,
  * u = barycentric velocity with half force (eq:1.19, evaluated after
@@ -239,7 +266,7 @@ int mclbm_set_graph(mclbm_handle* h, int32_t enable);
  * <= tol, keeps running the others, and returns MCLBM_OK when every sample has
  * converged.  mclbm_get_monitors then reports masses and counts summed over
  * samples and residuals maximised over the samples still running.  A single
- * lattice is a batch of one. */
+ * lattice is a batch of one.  Deposition needs a batch of one (EINVAL). */
 int mclbm_required_bytes_batch(const mclbm_params* p, int32_t n, size_t* bytes);
 int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_t arena_bytes,
                      void* hip_stream, mclbm_handle** out);

@@ -120,6 +120,9 @@ struct mclbm_handle {
     // device regions
     void *fA = nullptr, *fB = nullptr, *hA = nullptr, *hB = nullptr;
     void* kfield = nullptr;   // per fluid node reaction rate (arithmetic type), rate_field only
+    double* dep = nullptr;    // per fluid node particle deposit C_ps, deposition only
+    int* dep_count = nullptr; // per step of a batch: deposits above 1 after that step
+    void* dep_snap = nullptr; // populations (A) and deposits at the start of a batch
     uint32_t* links = nullptr;
     int* map = nullptr;
     unsigned* pos = nullptr;
@@ -135,6 +138,9 @@ struct mclbm_handle {
     long long nactive = 0;          // chunks in the work list
     double* host_result = nullptr;  // pinned [S][16]
     int* host_nwork = nullptr;      // pinned
+    int* host_dep = nullptr;        // pinned [DEP_BATCH], deposition only
+    int64_t dep_converted = 0;      // nodes turned solid by deposition since init_fields
+    std::vector<double> k_box;      // the caller's rate field, re-applied after a deposition rebuild
     // state
     bool geom_set = false, fields_set = false;
     int64_t step = 0;
@@ -152,9 +158,12 @@ struct mclbm_handle {
 
 namespace {
 
+// steps per speculative batch of a deposition run (one synchronisation each)
+constexpr int DEP_BATCH = 64;
+
 struct Layout {
-    size_t fA, fB, hA, hB, kfield, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample, work, nwork,
-        total;
+    size_t fA, fB, hA, hB, kfield, dep, depcnt, dsnap, map, pos, links, psi, snap, stage, partials, result, smp, chunk_sample,
+        work, nwork, total;
 };
 
 Ctx base_ctx(const mclbm_params& p) {
@@ -208,6 +217,9 @@ Layout layout_for(const mclbm_params* ps, int n) {
     L.hA = take(hb);
     L.hB = take(hb);
     L.kfield = take(p.solute && p.rate_field ? (size_t)2 * M * ab : 0);
+    L.dep = take(p.deposition ? (size_t)M * 8 : 0);
+    L.depcnt = take(p.deposition ? DEP_BATCH * 4 : 0);
+    L.dsnap = take(p.deposition ? (size_t)NC * Q * M * sb + hb + (size_t)M * 8 : 0);
     L.map = take((size_t)Ntot * 4);
     L.pos = take((size_t)M * 4);
     L.links = take((size_t)M * 4);
@@ -266,8 +278,16 @@ bool validate_one(const mclbm_params* p, std::string& why) {
         why = "monitor_every must be >= 1";
         return false;
     }
-    if (p->reserved != 0) {
-        why = "reserved field must be 0";
+    if (p->reserved != 0 || p->reserved2 != 0) {
+        why = "reserved fields must be 0";
+        return false;
+    }
+    if ((p->deposition != 0 && p->deposition != 1) || (p->deposition && !p->solute)) {
+        why = "deposition must be 0 or 1, and 1 needs the solute on";
+        return false;
+    }
+    if (p->deposition && (!(p->dep_prob > 0) || !isfinite(p->dep_prob))) {
+        why = "deposition probability dep_prob must be > 0";
         return false;
     }
     if ((p->rate_field != 0 && p->rate_field != 1) || (p->rate_field && !p->solute)) {
@@ -317,6 +337,10 @@ bool validate_one(const mclbm_params* p, std::string& why) {
 bool validate(const mclbm_params* p, int n, std::string& why) {
     if (!p || n < 1) {
         why = "need at least one sample";
+        return false;
+    }
+    if (n > 1 && p[0].deposition) {
+        why = "deposition needs a single lattice (a batch of one)";
         return false;
     }
     long long Ntot = 0, M = 0;
@@ -632,6 +656,9 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
     h->hA = p[0].solute ? base + L.hA : nullptr;
     h->hB = p[0].solute ? base + L.hB : nullptr;
     h->kfield = (p[0].solute && p[0].rate_field) ? base + L.kfield : nullptr;
+    h->dep = p[0].deposition ? (double*)(base + L.dep) : nullptr;
+    h->dep_count = p[0].deposition ? (int*)(base + L.depcnt) : nullptr;
+    h->dep_snap = p[0].deposition ? base + L.dsnap : nullptr;
     h->map = (int*)(base + L.map);
     h->pos = (unsigned*)(base + L.pos);
     h->links = (uint32_t*)(base + L.links);
@@ -646,8 +673,10 @@ int mclbm_init_batch(const mclbm_params* p, int32_t n, void* device_arena, size_
     h->nwork = (int*)(base + L.nwork);
     hipError_t e = hipHostMalloc((void**)&h->host_result, (size_t)n * 16 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_nwork, 64, hipHostMallocDefault);
+    if (e == hipSuccess && p[0].deposition) e = hipHostMalloc((void**)&h->host_dep, DEP_BATCH * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
         if (h->host_result) (void)hipHostFree(h->host_result);
+        if (h->host_nwork) (void)hipHostFree(h->host_nwork);
         if (h->own_arena) (void)hipFree(h->arena);
         delete h;
         return fail(nullptr, MCLBM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
@@ -743,6 +772,11 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
     int rc = upload_work(h);
     if (rc != MCLBM_OK) return rc;
     h->geom_set = true;
+    if (h->dep) {   // no deposit yet
+        HIPCHK(h, hipMemsetAsync(h->dep, 0, (size_t)h->nchunks * 64 * 8, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        h->dep_converted = 0;
+    }
     if (h->kfield) {   // the rate field starts uniform at k_wall
         std::vector<double> kb((size_t)h->Ntot, h->p.k_wall);
         rc = mclbm_set_wall_rate(h, kb.data());
@@ -782,6 +816,7 @@ int mclbm_set_wall_rate(mclbm_handle* h, const double* k_box) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
     }
     drop_graphs(h);
+    if (h->dep) h->k_box.assign(k_box, k_box + h->Ntot);   // re-applied when deposition rebuilds the geometry
     return MCLBM_OK;
 }
 
@@ -840,7 +875,9 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     if (rc != MCLBM_OK) return rc;
     Ctx c = make_ctx(h);
     HIPCHK(h, k_init(c, st_rho, u ? st_u : nullptr, (C && h->p.solute) ? st_C : nullptr));
+    if (h->dep) HIPCHK(h, hipMemsetAsync(h->dep, 0, (size_t)h->nchunks * 64 * 8, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->dep_converted = 0;
     h->step = 0;
     h->snap_valid = false;
     for (int k = 0; k < 16; ++k) h->mon[k] = 0.0;
@@ -849,10 +886,137 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     return MCLBM_OK;
 }
 
+static int convert_deposits(mclbm_handle* h) {
+    SampleHost& sm = h->smp[0];   // deposition runs on a single lattice
+    const long long nf_before = sm.nf;
+    std::vector<double> dv((size_t)sm.nf);
+    HIPCHK(h, hipMemcpyAsync(dv.data(), h->dep + sm.kbase, dv.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    size_t pb = 0;
+    int rc = mclbm_population_bytes(h, 1, &pb);
+    if (rc != MCLBM_OK) return rc;
+    std::vector<unsigned char> pops(pb);
+    rc = mclbm_get_populations(h, pops.data(), 1);   // synchronises the stream
+    if (rc != MCLBM_OK) return rc;
+    // new solid mask: the current one plus every node whose deposit exceeds 1;
+    // the deposits of the others, by box node
+    std::vector<uint8_t> mask = sm.mask;
+    std::vector<double> dbox((size_t)sm.N, 0.0);
+    for (long long k = 0; k < sm.nf; ++k) {
+        if (dv[(size_t)k] > 1.0)
+            mask[sm.pos[k]] = 1;
+        else
+            dbox[sm.pos[k]] = dv[(size_t)k];
+    }
+    const int64_t converted = h->dep_converted;
+    const std::vector<double> kb = h->k_box;
+    rc = mclbm_set_geometry(h, mask.data(), nullptr);   // pinch rule, numbering, link words; zeroes dep
+    if (rc != MCLBM_OK) return rc;
+    if (!kb.empty()) {
+        rc = mclbm_set_wall_rate(h, kb.data());
+        if (rc != MCLBM_OK) return rc;
+    }
+    h->fields_set = true;
+    rc = mclbm_set_populations(h, pops.data(), 1);   // the new solid nodes are left out
+    if (rc != MCLBM_OK) return rc;
+    // the dense pseudo-potential field is written only at fluid nodes (each step's
+    // density pass): the nodes that just turned solid must read 0 there, as every
+    // solid node does after init_fields
+    HIPCHK(h, hipMemsetAsync(h->psi, 0, (size_t)h->NC * h->Ntot * arith_bytes(h->p.storage), h->stream));
+    std::vector<double> dn((size_t)sm.nf);
+    for (long long k = 0; k < sm.nf; ++k) dn[(size_t)k] = dbox[sm.pos[k]];
+    HIPCHK(h, hipMemcpyAsync(h->dep + sm.kbase, dn.data(), dn.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->dep_converted = converted + (nf_before - sm.nf);
+    return MCLBM_OK;
+}
+
+int mclbm_get_deposit(mclbm_handle* h, double* Cps, int64_t* converted) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->dep) return fail(h, MCLBM_EINVAL, "the lattice was created without deposition");
+    if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
+    if (Cps) {
+        const SampleHost& sm = h->smp[0];
+        std::vector<double> dv((size_t)sm.nf);
+        HIPCHK(h, hipMemcpyAsync(dv.data(), h->dep + sm.kbase, dv.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        memset(Cps, 0, (size_t)sm.N * 8);
+        for (long long k = 0; k < sm.nf; ++k) Cps[sm.pos[k]] = dv[(size_t)k];
+    }
+    if (converted) *converted = h->dep_converted;
+    return MCLBM_OK;
+}
+
+// Steps with particle deposition (eq:surface_deposition).  Steps run in batches
+// of up to DEP_BATCH, never past the next monitor step; each step is followed by
+// the deposit update, which counts the deposits above 1 into a slot of its own,
+// and one synchronisation per batch reads the counts.  The populations and
+// deposits at the start of the batch are kept in a device snapshot: if the j-th
+// step of the batch made some deposit exceed 1 and later steps ran on, the
+// snapshot is restored and the first j steps are run again (every kernel on this
+// path is deterministic, so they reproduce the same state bit for bit); those
+// nodes then turn solid before the next step.
+static int step_deposition(mclbm_handle* h, int64_t n) {
+    const int K = h->p.monitor_every;
+    const size_t sb = store_bytes(h->p.storage);
+    bool monitored = false, had = false;
+    int64_t left = n;
+    while (left > 0) {
+        const int64_t to_monitor = K - (h->step % K);
+        const int B = (int)std::min(std::min(left, (int64_t)DEP_BATCH), to_monitor);
+        const size_t M = (size_t)h->nchunks * 64;
+        const size_t fbytes = (size_t)h->NC * h->Q * M * sb, hbytes = (size_t)h->HP * M * sb;
+        char* snap = (char*)h->dep_snap;
+        if (B > 1) {
+            HIPCHK(h, hipMemcpyAsync(snap, h->fA, fbytes, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(snap + fbytes, h->hA, hbytes, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(snap + fbytes + hbytes, h->dep, M * 8, hipMemcpyDeviceToDevice, h->stream));
+        }
+        const int64_t step0 = h->step;
+        HIPCHK(h, hipMemsetAsync(h->dep_count, 0, DEP_BATCH * 4, h->stream));
+        for (int j = 0; j < B; ++j) {
+            int rc = launch_step(h, h->stream);
+            if (rc != MCLBM_OK) return rc;
+            HIPCHK(h, k_deposit_step(make_ctx(h), h->dep, h->p.dep_prob, h->dep_count + j));
+        }
+        HIPCHK(h, hipMemcpyAsync(h->host_dep, h->dep_count, (size_t)B * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        int first = -1;
+        for (int j = 0; j < B && first < 0; ++j)
+            if (h->host_dep[j] > 0) first = j;
+        if (first < 0) {
+            left -= B;
+        } else {
+            if (first < B - 1) {   // back to the start of the batch, then up to the crossing step
+                HIPCHK(h, hipMemcpyAsync(h->fA, snap, fbytes, hipMemcpyDeviceToDevice, h->stream));
+                HIPCHK(h, hipMemcpyAsync(h->hA, snap + fbytes, hbytes, hipMemcpyDeviceToDevice, h->stream));
+                HIPCHK(h, hipMemcpyAsync(h->dep, snap + fbytes + hbytes, M * 8, hipMemcpyDeviceToDevice, h->stream));
+                h->step = step0;
+                for (int j = 0; j <= first; ++j) {
+                    int rc = launch_step(h, h->stream);
+                    if (rc != MCLBM_OK) return rc;
+                    HIPCHK(h, k_deposit_step(make_ctx(h), h->dep, h->p.dep_prob, h->dep_count + j));
+                }
+            }
+            int rc = convert_deposits(h);
+            if (rc != MCLBM_OK) return rc;
+            left -= first + 1;
+        }
+        if (h->step % K == 0) {
+            had = h->snap_valid;
+            HIPCHK(h, k_monitor(make_ctx(h), had ? 1 : 0));
+            h->snap_valid = true;
+            monitored = true;
+        }
+    }
+    if (monitored) return collect_monitor(h, had);
+    return MCLBM_OK;
+}
+
 int mclbm_step(mclbm_handle* h, int64_t n) {
     if (!h) return MCLBM_EINVAL;
     if (n < 0) return fail(h, MCLBM_EINVAL, "n must be >= 0");
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
+    if (h->dep) return step_deposition(h, n);
     const int K = h->p.monitor_every;
     bool monitored = false, had = false;
     int64_t left = n;
@@ -1209,6 +1373,7 @@ void mclbm_destroy(mclbm_handle* h) {
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     if (h->host_result) (void)hipHostFree(h->host_result);
     if (h->host_nwork) (void)hipHostFree(h->host_nwork);
+    if (h->host_dep) (void)hipHostFree(h->host_dep);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     delete h;
 }

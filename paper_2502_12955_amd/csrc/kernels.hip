@@ -450,6 +450,34 @@ __global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R>
 }
 
 // ---------------------------------------------------------------------------
+// particle deposition (sec:particle_deposition, eq:surface_deposition): after
+// a step, every fluid node with a solid flow-lattice neighbour adds DP times
+// its particle concentration (the reacting solute species: the sum of its
+// populations after streaming, in FP64) to its deposit.  Nodes whose deposit
+// then exceeds 1 are counted; the host turns them solid.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ void __launch_bounds__(256) k_deposit(Phys<typename Store<ST>::R> P, Geo g,
+                                                 const typename Store<ST>::T* __restrict__ hA,
+                                                 double* __restrict__ dep, double DP, int* __restrict__ count) {
+    using L = Lat<LAT>;
+    using S = Store<ST>;
+    for_each_chunk(g, [&](int ch) {
+        const SampleDev sd = sample_of(g, ch);
+        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+        const uint32_t lw = g.links[k];
+        if ((lw & ((1u << L::Q) - 2u)) == 0u) return;   // no solid neighbour
+        double C = 0.0;
+#pragma unroll
+        for (int q = 0; q < L::QS; ++q) C += (double)S::load_plain(blk(hA, P.hplanes, q, k));
+        const double d = dep[k] + DP * C;
+        dep[k] = d;
+        if (d > 1.0) atomicAdd(count, 1);
+    });
+}
+
+// ---------------------------------------------------------------------------
 // monitors: FP64 per-chunk partials (one wavefront each), then a fixed-order
 // reduction per sample.
 //   v[0] mass_0  v[1] mass_1  v[2] mass_C  v[3] |du|^2  v[4] |u|^2
@@ -714,6 +742,15 @@ static hipError_t monitor_t(const Ctx& c, int have_snapshot) {
     return hipGetLastError();
 }
 
+template <int LAT, int ST, int NC>
+static hipError_t deposit_t(const Ctx& c, double* dep, double DP, int* count) {
+    auto P = make_phys<SR<ST>>(c);
+    const Geo g = make_geo(c, false);
+    hipLaunchKernelGGL((k_deposit<LAT, ST>), grid_for(c, 256, false), dim3(256), 0, c.stream, P, g,
+                       (const STT<ST>*)c.hA, dep, DP, count);
+    return hipGetLastError();
+}
+
 #define MCLBM_DISPATCH(FN, ...)                                \
     do {                                                       \
         const int key = c.lat * 100 + c.st * 10 + c.nc;        \
@@ -744,5 +781,8 @@ hipError_t k_init(const Ctx& c, const double* rho, const double* u, const double
 hipError_t k_step(const Ctx& c) { MCLBM_DISPATCH(step_t, c); }
 hipError_t k_moments(const Ctx& c, double* rho, double* u, double* C) { MCLBM_DISPATCH(moments_t, c, rho, u, C); }
 hipError_t k_monitor(const Ctx& c, int have_snapshot) { MCLBM_DISPATCH(monitor_t, c, have_snapshot); }
+hipError_t k_deposit_step(const Ctx& c, double* dep, double DP, int* count) {
+    MCLBM_DISPATCH(deposit_t, c, dep, DP, count);
+}
 
 }  // namespace mclbm

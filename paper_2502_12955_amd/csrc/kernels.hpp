@@ -64,5 +64,8 @@ hipError_t k_init(const Ctx& c, const double* rho, const double* u, const double
 hipError_t k_step(const Ctx& c);
 hipError_t k_moments(const Ctx& c, double* rho, double* u, double* C);
 hipError_t k_monitor(const Ctx& c, int have_snapshot);
+// particle deposition after a step: dep[k] += DP * C at fluid nodes with a solid
+// neighbour; *count (zeroed by the caller) receives the nodes whose deposit exceeds 1
+hipError_t k_deposit_step(const Ctx& c, double* dep, double DP, int* count);
 
 }  // namespace mclbm

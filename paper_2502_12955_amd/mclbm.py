@@ -40,7 +40,8 @@ class Params(ct.Structure):
                 ("tau", ct.c_double * 2), ("G", (ct.c_double * 2) * 2), ("G_ads", ct.c_double * 2),
                 ("rho0", ct.c_double), ("accel", ct.c_double * 3), ("D", ct.c_double),
                 ("J0", ct.c_double), ("k_wall", ct.c_double), ("C_in", ct.c_double),
-                ("product", ct.c_int32), ("rate_field", ct.c_int32), ("D2", ct.c_double), ("C_in2", ct.c_double)]
+                ("product", ct.c_int32), ("rate_field", ct.c_int32), ("D2", ct.c_double), ("C_in2", ct.c_double),
+                ("deposition", ct.c_int32), ("reserved2", ct.c_int32), ("dep_prob", ct.c_double)]
 
 
 def _enum(v, table):
@@ -77,6 +78,9 @@ def params_from_dict(p: dict) -> Params:
     s.rate_field = int(p.get("rate_field", 0))
     s.D2 = float(p.get("D2", 0.1))
     s.C_in2 = float(p.get("C_in2", 0.0))
+    s.deposition = int(p.get("deposition", 0))
+    s.reserved2 = 0
+    s.dep_prob = float(p.get("dep_prob", 0.0))
     return s
 
 
@@ -94,7 +98,8 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
-           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_destroy", "mclbm_last_error")
+           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_get_deposit", "mclbm_destroy",
+           "mclbm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -111,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_init_lattice.argtypes = [P, vp, sz, vp, ct.POINTER(vp)]
     lib.mclbm_set_geometry.argtypes = [vp, vp, ct.POINTER(i64)]
     lib.mclbm_set_wall_rate.argtypes = [vp, vp]
+    lib.mclbm_get_deposit.argtypes = [vp, vp, ct.POINTER(i64)]
     lib.mclbm_get_geometry.argtypes = [vp, vp, vp, vp]
     lib.mclbm_init_fields.argtypes = [vp, vp, vp, vp]
     lib.mclbm_step.argtypes = [vp, i64]
@@ -206,6 +212,15 @@ def set_wall_rate(h, k_box):
     """Per-node reaction rate [N] (box nodes; needs rate_field=1 and set_geometry first)."""
     k = np.ascontiguousarray(k_box, np.float64).reshape(-1)
     _check(load().mclbm_set_wall_rate(h, _ptr(k)), h)
+
+
+def get_deposit(h, N):
+    """Particle deposit C_ps per box node [N] (eq:surface_deposition; 0 on solid
+    nodes) and the number of nodes deposition has turned solid."""
+    Cps = np.zeros(N)
+    n = ct.c_int64()
+    _check(load().mclbm_get_deposit(h, _ptr(Cps), ct.byref(n)), h)
+    return Cps, n.value
 
 
 def get_moments(h, ncomp, N, nspecies=1):
@@ -372,6 +387,9 @@ class Lattice:
 
     def set_wall_rate(self, k_box):
         set_wall_rate(self.h, np.asarray(k_box).reshape(self.N))
+
+    def get_deposit(self):
+        return get_deposit(self.h, self.N)
 
     def step(self, n=1, allow_diverged=False):
         return step(self.h, n, allow_diverged)

@@ -54,6 +54,18 @@ def test_required_bytes_and_validation():
     assert mclbm.required_bytes(dict(p, rate_field=1)) >= nb + 4 * 64 ** 3
     with pytest.raises(mclbm.MclbmError):
         mclbm.required_bytes(dict(p, rate_field=1, solute="off"))
+    # particle deposition: needs the solute, DP > 0 and a single lattice; adds one FP64 deposit per node
+    nbd = mclbm.required_bytes(dict(p, deposition=1, dep_prob=0.01))
+    assert nbd - nb >= 8 * 64 ** 3
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, deposition=1, dep_prob=0.01, solute="off"))
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, deposition=1, dep_prob=0.0))
+    with pytest.raises(mclbm.MclbmError):
+        mclbm.required_bytes(dict(p, deposition=2, dep_prob=0.01))
+    with pytest.raises(mclbm.MclbmError) as e:
+        mclbm.required_bytes_batch([dict(p, deposition=1, dep_prob=0.01)] * 2)
+    assert "single lattice" in mclbm.last_error()
     # sizes beyond the 32-bit fluid and box indexing are refused before any allocation
     with pytest.raises(mclbm.MclbmError) as e:
         mclbm.required_bytes(dict(p, nx=2048, ny=2048, nz=1024))
