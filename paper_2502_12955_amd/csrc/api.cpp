@@ -886,22 +886,22 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     return MCLBM_OK;
 }
 
+// The nodes whose deposit exceeds 1 turn solid: the geometry is rebuilt on the
+// host (pinch rule, numbering, link words) and the state of every node that is
+// still fluid moves to its new fluid index on the device.
 static int convert_deposits(mclbm_handle* h) {
-    SampleHost& sm = h->smp[0];   // deposition runs on a single lattice
+    SampleHost& sm = h->smp[0];   // deposition runs on a single lattice (kbase 0)
     const long long nf_before = sm.nf;
     std::vector<double> dv((size_t)sm.nf);
-    HIPCHK(h, hipMemcpyAsync(dv.data(), h->dep + sm.kbase, dv.size() * 8, hipMemcpyDeviceToHost, h->stream));
-    size_t pb = 0;
-    int rc = mclbm_population_bytes(h, 1, &pb);
-    if (rc != MCLBM_OK) return rc;
-    std::vector<unsigned char> pops(pb);
-    rc = mclbm_get_populations(h, pops.data(), 1);   // synchronises the stream
-    if (rc != MCLBM_OK) return rc;
+    HIPCHK(h, hipMemcpyAsync(dv.data(), h->dep, dv.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     // new solid mask: the current one plus every node whose deposit exceeds 1;
-    // the deposits of the others, by box node
+    // the old fluid index and the deposit of every node, by box index
     std::vector<uint8_t> mask = sm.mask;
+    std::vector<int> old_k((size_t)sm.N, -1);
     std::vector<double> dbox((size_t)sm.N, 0.0);
     for (long long k = 0; k < sm.nf; ++k) {
+        old_k[sm.pos[k]] = (int)k;
         if (dv[(size_t)k] > 1.0)
             mask[sm.pos[k]] = 1;
         else
@@ -909,23 +909,35 @@ static int convert_deposits(mclbm_handle* h) {
     }
     const int64_t converted = h->dep_converted;
     const std::vector<double> kb = h->k_box;
-    rc = mclbm_set_geometry(h, mask.data(), nullptr);   // pinch rule, numbering, link words; zeroes dep
+    int rc = mclbm_set_geometry(h, mask.data(), nullptr);   // pinch rule, numbering, link words; zeroes dep
     if (rc != MCLBM_OK) return rc;
     if (!kb.empty()) {
         rc = mclbm_set_wall_rate(h, kb.data());
         if (rc != MCLBM_OK) return rc;
     }
-    h->fields_set = true;
-    rc = mclbm_set_populations(h, pops.data(), 1);   // the new solid nodes are left out
-    if (rc != MCLBM_OK) return rc;
+    // the fluid nodes only lose members, so every new fluid node has an old index
+    const size_t M = (size_t)h->nchunks * 64;
+    std::vector<int> from(M, -1);
+    std::vector<double> dn(M, 0.0);
+    for (long long k = 0; k < sm.nf; ++k) {
+        from[(size_t)k] = old_k[sm.pos[k]];
+        dn[(size_t)k] = dbox[sm.pos[k]];
+    }
+    int* d_from = (int*)h->dep_snap;   // free between batches; holds at least M doubles
+    HIPCHK(h, hipMemcpyAsync(d_from, from.data(), M * 4, hipMemcpyHostToDevice, h->stream));
+    const int sb = (int)store_bytes(h->p.storage);
+    HIPCHK(h, k_remap_planes(h->fB, h->fA, h->NC * h->Q, d_from, (long long)M, sb, h->stream));
+    std::swap(h->fA, h->fB);
+    HIPCHK(h, k_remap_planes(h->hB, h->hA, h->HP, d_from, (long long)M, sb, h->stream));
+    std::swap(h->hA, h->hB);
+    HIPCHK(h, hipMemcpyAsync(h->dep, dn.data(), M * 8, hipMemcpyHostToDevice, h->stream));
     // the dense pseudo-potential field is written only at fluid nodes (each step's
     // density pass): the nodes that just turned solid must read 0 there, as every
     // solid node does after init_fields
     HIPCHK(h, hipMemsetAsync(h->psi, 0, (size_t)h->NC * h->Ntot * arith_bytes(h->p.storage), h->stream));
-    std::vector<double> dn((size_t)sm.nf);
-    for (long long k = 0; k < sm.nf; ++k) dn[(size_t)k] = dbox[sm.pos[k]];
-    HIPCHK(h, hipMemcpyAsync(h->dep + sm.kbase, dn.data(), dn.size() * 8, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));   // before the host vectors go
+    h->fields_set = true;
+    h->snap_valid = false;
     h->dep_converted = converted + (nf_before - sm.nf);
     return MCLBM_OK;
 }

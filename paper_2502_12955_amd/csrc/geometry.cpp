@@ -20,11 +20,14 @@ namespace {
 struct Grid {
     int nx, ny, nz, dim;
     bool seam;
+    // periodic wrap of coordinates a few nodes outside the box (no division)
+    static int wrap(int a, int n) {
+        while (a < 0) a += n;
+        while (a >= n) a -= n;
+        return a;
+    }
     long long idx(int x, int y, int z) const {
-        x = (x % nx + nx) % nx;
-        y = (y % ny + ny) % ny;
-        z = (z % nz + nz) % nz;
-        return (long long)x + (long long)nx * ((long long)y + (long long)ny * z);
+        return (long long)wrap(x, nx) + (long long)nx * ((long long)wrap(y, ny) + (long long)ny * wrap(z, nz));
     }
 };
 
@@ -42,31 +45,38 @@ bool pinched(const Grid& g, const std::vector<uint8_t>& m, int x, int y, int z) 
     return false;
 }
 
+// fn(t, z, y) for every row (z, y) of the box, rows dealt round-robin to up to
+// 16 threads (t = thread index)
 template <class F>
-void parallel_z(int nz, F fn) {
+unsigned parallel_rows(int ny, int nz, F fn) {
+    const long long rows = (long long)ny * nz;
     unsigned nt = std::thread::hardware_concurrency();
     if (nt == 0) nt = 1;
     if (nt > 16) nt = 16;
-    if ((int)nt > nz) nt = (unsigned)nz;
+    if ((long long)nt > rows / 64 + 1) nt = (unsigned)(rows / 64 + 1);
     std::vector<std::thread> th;
     for (unsigned t = 0; t < nt; ++t)
         th.emplace_back([&, t]() {
-            for (int z = (int)t; z < nz; z += (int)nt) fn(z);
+            for (long long r = t; r < rows; r += nt) fn(t, (int)(r / ny), (int)(r % ny));
         });
     for (auto& x : th) x.join();
+    return nt;
 }
 
 }  // namespace
 
 int64_t pinch_fill(const GeomSpec& s, std::vector<uint8_t>& mask) {
     Grid g{s.nx, s.ny, s.nz, s.lattice == 1 ? 3 : 2, s.solute == 2};
+    // initial scan in parallel (read-only), then the work list in one thread
+    std::vector<std::vector<long long>> found(16);
+    parallel_rows(g.ny, g.nz, [&](unsigned t, int z, int y) {
+        for (int x = 0; x < g.nx; ++x) {
+            long long n = g.idx(x, y, z);
+            if (!mask[n] && pinched(g, mask, x, y, z)) found[t].push_back(n);
+        }
+    });
     std::vector<long long> work;
-    for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y)
-            for (int x = 0; x < g.nx; ++x) {
-                long long n = g.idx(x, y, z);
-                if (!mask[n] && pinched(g, mask, x, y, z)) work.push_back(n);
-            }
+    for (auto& f : found) work.insert(work.end(), f.begin(), f.end());
     int64_t count = 0;
     static const int ax[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     while (!work.empty()) {
@@ -108,33 +118,32 @@ void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector
     if (flow_bits) flow_bits->assign((size_t)N, 0u);
     if (solute_bits) solute_bits->assign((size_t)N, 0u);
     auto in_x = [&](int x) { return !g.seam || (x >= 0 && x < g.nx); };
-    parallel_z(g.nz, [&](int z) {
-        for (int y = 0; y < g.ny; ++y)
-            for (int x = 0; x < g.nx; ++x) {
-                const long long n = g.idx(x, y, z);
-                if (mask[n]) {
-                    words[n] = 0x80000000u;
-                    continue;
-                }
-                uint32_t w = 0, fb = 0, sb = 0;
-                for (int i = 1; i < Q; ++i)
-                    if (mask[g.idx(x - c[i][0], y - c[i][1], z - c[i][2])]) fb |= 1u << i;
-                for (int k = 1; k < QS; ++k) {
-                    if (!in_x(x - c[k][0])) continue;
-                    if (mask[g.idx(x - c[k][0], y - c[k][1], z - c[k][2])]) sb |= 1u << k;
-                }
-                w = fb | (sb << wet_shift);
-                for (int d = 1; d < QS; ++d) {
-                    // neighbour y = n + e_d, reached without crossing a seam, fluid, whose
-                    // upstream in direction opp(d) (= n + 2 e_d) is solid and in the domain
-                    if (!in_x(x + c[d][0]) || !in_x(x + 2 * c[d][0])) continue;
-                    if (mask[g.idx(x + c[d][0], y + c[d][1], z + c[d][2])]) continue;
-                    if (mask[g.idx(x + 2 * c[d][0], y + 2 * c[d][1], z + 2 * c[d][2])]) w |= 1u << (hop_shift + d);
-                }
-                words[n] = w;
-                if (flow_bits) (*flow_bits)[n] = fb;
-                if (solute_bits) (*solute_bits)[n] = sb;
+    parallel_rows(g.ny, g.nz, [&](unsigned, int z, int y) {
+        for (int x = 0; x < g.nx; ++x) {
+            const long long n = g.idx(x, y, z);
+            if (mask[n]) {
+                words[n] = 0x80000000u;
+                continue;
             }
+            uint32_t w = 0, fb = 0, sb = 0;
+            for (int i = 1; i < Q; ++i)
+                if (mask[g.idx(x - c[i][0], y - c[i][1], z - c[i][2])]) fb |= 1u << i;
+            for (int k = 1; k < QS; ++k) {
+                if (!in_x(x - c[k][0])) continue;
+                if (mask[g.idx(x - c[k][0], y - c[k][1], z - c[k][2])]) sb |= 1u << k;
+            }
+            w = fb | (sb << wet_shift);
+            for (int d = 1; d < QS; ++d) {
+                // neighbour y = n + e_d, reached without crossing a seam, fluid, whose
+                // upstream in direction opp(d) (= n + 2 e_d) is solid and in the domain
+                if (!in_x(x + c[d][0]) || !in_x(x + 2 * c[d][0])) continue;
+                if (mask[g.idx(x + c[d][0], y + c[d][1], z + c[d][2])]) continue;
+                if (mask[g.idx(x + 2 * c[d][0], y + 2 * c[d][1], z + 2 * c[d][2])]) w |= 1u << (hop_shift + d);
+            }
+            words[n] = w;
+            if (flow_bits) (*flow_bits)[n] = fb;
+            if (solute_bits) (*solute_bits)[n] = sb;
+        }
     });
 }
 

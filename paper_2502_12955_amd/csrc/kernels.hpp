@@ -67,5 +67,9 @@ hipError_t k_monitor(const Ctx& c, int have_snapshot);
 // particle deposition after a step: dep[k] += DP * C at fluid nodes with a solid
 // neighbour; *count (zeroed by the caller) receives the nodes whose deposit exceeds 1
 hipError_t k_deposit_step(const Ctx& c, double* dep, double DP, int* count);
+// renumbering after a geometry change: dst(j, k) = src(j, from[k]) over planes of
+// elem_bytes-wide values in the chunked layout, 0 where from[k] < 0 (remap.hip)
+hipError_t k_remap_planes(void* dst, const void* src, int planes, const int* from, long long nnew, int elem_bytes,
+                          hipStream_t stream);
 
 }  // namespace mclbm
