@@ -158,15 +158,19 @@ int mclbm_set_wall_rate(mclbm_handle* h, const double* k_box);
  * non-finite value.  Errors: ESTATE before init_fields, EINVAL (n < 0).
  *
  * With deposition on, every step is followed by the deposit update
- * (eq:surface_deposition) and a synchronisation that reads how many deposits
- * exceed 1.  If any do, those nodes turn solid before the next step: the
- * geometry is rebuilt as by mclbm_set_geometry from the current solid mask
- * plus those nodes (the pinch rule applies again, and the nodes it fills turn
- * solid too), the populations and deposits of the remaining fluid nodes are
- * carried over bit for bit, and those of the new solid nodes are dropped.  A
- * per-node rate field set with mclbm_set_wall_rate is kept.  The residual
- * snapshot starts over.  Graph replay is not used with deposition.  Returns
- * EINVAL (handle unusable) if deposition leaves no fluid node. */
+ * (eq:surface_deposition).  If some deposit exceeds 1 after a step, those
+ * nodes turn solid before the next step: the geometry is rebuilt as by
+ * mclbm_set_geometry from the current solid mask plus those nodes (the pinch
+ * rule applies again, and the nodes it fills turn solid too), the populations
+ * and deposits of the remaining fluid nodes are carried over bit for bit, and
+ * those of the new solid nodes are dropped.  Steps run in batches of up to 64
+ * (never past a monitor step) with one synchronisation per batch; a batch in
+ * which a conversion happened before its last step is rolled back to its
+ * start and re-run up to that step (the result is the same as stepping one at
+ * a time).  A per-node rate field set with mclbm_set_wall_rate is kept.  The
+ * residual snapshot starts over after a conversion.  Graph replay is not used
+ * with deposition.  Returns EINVAL (handle unusable) if deposition leaves no
+ * fluid node. */
 int mclbm_step(mclbm_handle* h, int64_t n);
 
 /* Deposit C_ps of every box node (host FP64 [N], x fastest; 0 on solid nodes
@@ -175,6 +179,15 @@ int mclbm_step(mclbm_handle* h, int64_t n);
  * may be NULL).  Needs deposition = 1.  Errors: ESTATE before init_fields,
  * EINVAL. */
 int mclbm_get_deposit(mclbm_handle* h, double* Cps, int64_t* converted);
+
+/* Restore the deposits (host FP64 [N], box nodes; values at solid nodes are
+ * ignored) and the converted-node count, e.g. from mclbm_get_deposit.  With
+ * mclbm_get_geometry's mask, mclbm_get_populations(raw = 1) and these, a
+ * deposition run resumes bit for bit: set_geometry(mask), init_fields,
+ * set_populations(raw = 1), set_wall_rate if used, set_deposit.  Needs
+ * deposition = 1.  Errors: ESTATE before init_fields, EINVAL (negative or
+ * non-finite deposit on a fluid node). */
+int mclbm_set_deposit(mclbm_handle* h, const double* Cps, int64_t converted);
 
 /* Macroscopic fields of the current (post-streaming) state: rho_s = sum_i f,
  * u = barycentric velocity with half force (eq:1.19, evaluated after

@@ -140,6 +140,7 @@ struct mclbm_handle {
     int* host_nwork = nullptr;      // pinned
     int* host_dep = nullptr;        // pinned [DEP_BATCH], deposition only
     int64_t dep_converted = 0;      // nodes turned solid by deposition since init_fields
+    int dep_batch = 64;             // steps of the next speculative deposition batch
     std::vector<double> k_box;      // the caller's rate field, re-applied after a deposition rebuild
     // state
     bool geom_set = false, fields_set = false;
@@ -959,7 +960,10 @@ int mclbm_get_deposit(mclbm_handle* h, double* Cps, int64_t* converted) {
 }
 
 // Steps with particle deposition (eq:surface_deposition).  Steps run in batches
-// of up to DEP_BATCH, never past the next monitor step; each step is followed by
+// of up to DEP_BATCH, never past the next monitor step; the batch length adapts
+// to the spacing of conversions (twice the steps to the last conversion, doubled
+// after a batch without one), so that dense conversions do not waste most of a
+// long batch.  Each step is followed by
 // the deposit update, which counts the deposits above 1 into a slot of its own,
 // and one synchronisation per batch reads the counts.  The populations and
 // deposits at the start of the batch are kept in a device snapshot: if the j-th
@@ -974,7 +978,7 @@ static int step_deposition(mclbm_handle* h, int64_t n) {
     int64_t left = n;
     while (left > 0) {
         const int64_t to_monitor = K - (h->step % K);
-        const int B = (int)std::min(std::min(left, (int64_t)DEP_BATCH), to_monitor);
+        const int B = (int)std::min(std::min(left, (int64_t)h->dep_batch), to_monitor);
         const size_t M = (size_t)h->nchunks * 64;
         const size_t fbytes = (size_t)h->NC * h->Q * M * sb, hbytes = (size_t)h->HP * M * sb;
         char* snap = (char*)h->dep_snap;
@@ -997,7 +1001,9 @@ static int step_deposition(mclbm_handle* h, int64_t n) {
             if (h->host_dep[j] > 0) first = j;
         if (first < 0) {
             left -= B;
+            h->dep_batch = std::min(DEP_BATCH, 2 * h->dep_batch);
         } else {
+            h->dep_batch = std::min(DEP_BATCH, 2 * (first + 1));
             if (first < B - 1) {   // back to the start of the batch, then up to the crossing step
                 HIPCHK(h, hipMemcpyAsync(h->fA, snap, fbytes, hipMemcpyDeviceToDevice, h->stream));
                 HIPCHK(h, hipMemcpyAsync(h->hA, snap + fbytes, hbytes, hipMemcpyDeviceToDevice, h->stream));
@@ -1021,6 +1027,25 @@ static int step_deposition(mclbm_handle* h, int64_t n) {
         }
     }
     if (monitored) return collect_monitor(h, had);
+    return MCLBM_OK;
+}
+
+int mclbm_set_deposit(mclbm_handle* h, const double* Cps, int64_t converted) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->dep) return fail(h, MCLBM_EINVAL, "the lattice was created without deposition");
+    if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
+    if (!Cps) return fail(h, MCLBM_EINVAL, "Cps is NULL");
+    if (converted < 0) return fail(h, MCLBM_EINVAL, "converted must be >= 0");
+    const SampleHost& sm = h->smp[0];
+    std::vector<double> dv((size_t)sm.nf);
+    for (long long k = 0; k < sm.nf; ++k) {
+        const double v = Cps[sm.pos[k]];
+        if (!(v >= 0) || !isfinite(v)) return fail(h, MCLBM_EINVAL, "deposits must be >= 0 and finite");
+        dv[(size_t)k] = v;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->dep, dv.data(), dv.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->dep_converted = converted;
     return MCLBM_OK;
 }
 

@@ -9,9 +9,10 @@ body force along x (periodic), the particles enter through the plane x = 0 and
 leave through x = nx-1, and the particle lattice is D2Q5 with rest weight 1/3
 (c_s^2 = 1/3, so the paper's diffusivity gives its relaxation time).
 
-Reported: the nodes turned solid over time, the mean velocity (it drops as the
-pores clog), the outlet concentration, and the time per step with deposition
-against the same lattice without it.
+Reported: the nodes turned solid over time and where they are along x (the
+paper finds deposits near the inlet first, then further downstream), the mean
+velocity (it drops as the pores clog), the outlet concentration, and the time
+per step with deposition against the same lattice without it.
 
     python -m paper_2502_12955_amd.deposition [--steps N] [--out report.json]
 """
@@ -47,6 +48,7 @@ def run(steps=100_000, every=10_000, dep_prob=0.002, C_in=0.01, storage="f64", n
         lat = mclbm.Lattice(p)
         nrc = lat.set_geometry(mask)
         lat.init_fields(rho)
+        solid0 = lat.get_geometry()[0].reshape(ny, nx) != 0
         N = nx * ny
         done = 0
         t_total = 0.0
@@ -65,12 +67,17 @@ def run(steps=100_000, every=10_000, dep_prob=0.002, C_in=0.01, storage="f64", n
                 fluid = mg.reshape(ny, nx) == 0
                 ux = u[0].reshape(ny, nx)
                 Cout = C.reshape(ny, nx)[:, nx - 1][fluid[:, nx - 1]]
+                # where the deposits are: x of the nodes that turned solid
+                xs = np.nonzero(~fluid & ~solid0)[1]
                 rec = dict(step=done, converted=int(conv), fluid_nodes=int(fluid.sum()), ms_per_step=1e3 * dt / n,
                            mean_ux=float(ux[fluid].mean()), max_ux=float(ux[fluid].max()),
-                           outlet_C=float(Cout.mean()) if Cout.size else 0.0)
+                           outlet_C=float(Cout.mean()) if Cout.size else 0.0,
+                           x_median=float(np.median(xs)) if xs.size else None,
+                           x_p90=float(np.percentile(xs, 90)) if xs.size else None)
                 out["history"].append(rec)
                 print(f"[deposition] step {done}: {conv} nodes turned solid, mean u_x {rec['mean_ux']:.3e}, "
-                      f"outlet C {rec['outlet_C']:.3e}, {rec['ms_per_step']:.4f} ms/step", flush=True)
+                      f"outlet C {rec['outlet_C']:.3e}, deposits at x median {rec['x_median']} / 90 % "
+                      f"{rec['x_p90']}, {rec['ms_per_step']:.4f} ms/step", flush=True)
         timings["with" if dep else "without"] = dict(ms_per_step=1e3 * t_total / steps,
                                                       mlups=N * steps / t_total / 1e6)
         if not dep:

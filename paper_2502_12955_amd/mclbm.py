@@ -98,7 +98,7 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
-           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_get_deposit", "mclbm_destroy",
+           "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_get_deposit", "mclbm_set_deposit", "mclbm_destroy",
            "mclbm_last_error")
 
 
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_set_geometry.argtypes = [vp, vp, ct.POINTER(i64)]
     lib.mclbm_set_wall_rate.argtypes = [vp, vp]
     lib.mclbm_get_deposit.argtypes = [vp, vp, ct.POINTER(i64)]
+    lib.mclbm_set_deposit.argtypes = [vp, vp, i64]
     lib.mclbm_get_geometry.argtypes = [vp, vp, vp, vp]
     lib.mclbm_init_fields.argtypes = [vp, vp, vp, vp]
     lib.mclbm_step.argtypes = [vp, i64]
@@ -221,6 +222,12 @@ def get_deposit(h, N):
     n = ct.c_int64()
     _check(load().mclbm_get_deposit(h, _ptr(Cps), ct.byref(n)), h)
     return Cps, n.value
+
+
+def set_deposit(h, Cps, converted=0):
+    """Restore the deposits [N] (box nodes) and the converted-node count."""
+    d = np.ascontiguousarray(Cps, np.float64).reshape(-1)
+    _check(load().mclbm_set_deposit(h, _ptr(d), int(converted)), h)
 
 
 def get_moments(h, ncomp, N, nspecies=1):
@@ -390,6 +397,9 @@ class Lattice:
 
     def get_deposit(self):
         return get_deposit(self.h, self.N)
+
+    def set_deposit(self, Cps, converted=0):
+        set_deposit(self.h, np.asarray(Cps).reshape(self.N), converted)
 
     def step(self, n=1, allow_diverged=False):
         return step(self.h, n, allow_diverged)

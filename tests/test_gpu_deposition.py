@@ -113,3 +113,64 @@ def test_deposit_calls_check_their_state():
         lat.get_deposit()
     assert e.value.code == mclbm.EINVAL
     lat.close()
+
+
+def test_a_channel_that_fills_up_is_reported():
+    """Three fluid rows between two walls at rest with a uniform particle fraction:
+    the rows next to the walls turn solid after exactly 271 steps (the oracle's closed
+    form for DP c0 = 0.0037) and the middle row is then pinched, so no fluid is left:
+    the step that does it fails with EINVAL and says why."""
+    nz, ny, nx = 1, 5, 12
+    p = inputs.base_params(lattice="D2Q9", nx=nx, ny=ny, nz=nz, ncomp=1, G=((0, 0), (0, 0)), tau=(0.8, 0.8),
+                           solute="periodic", D=0.15, J0=0.2, k_wall=0.0, storage="f64", deposition=1,
+                           dep_prob=0.01)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[0, 0, :] = 1
+    mask[0, ny - 1, :] = 1
+    rho = np.where(mask == 0, 1.0, 0.0)[None]
+    C = np.where(mask == 0, 0.37, 0.0)
+    m = mask.reshape(-1).copy()                        # the oracle updates its mask in place
+    f, h = oracle.init(p, m, rho, None, C)
+    Cps = np.zeros(m.size)
+    assert oracle.step_deposit(p, m, f, h, Cps, 0.01, 270) == 0
+    Cps270 = Cps.copy()
+    assert oracle.step_deposit(p, m, f, h, Cps, 0.01, 1) == 3 * nx and m.all()
+    lat = mclbm.Lattice(p)
+    lat.set_geometry(mask)
+    lat.init_fields(rho, None, C)
+    lat.step(270)
+    Cg, conv = lat.get_deposit()
+    assert conv == 0 and nrel(Cg, Cps270) < 1e-12
+    with pytest.raises(mclbm.MclbmError) as e:
+        lat.step(5)
+    assert e.value.code == mclbm.EINVAL and "no fluid node" in str(e.value)
+    lat.close()
+
+
+def test_a_deposition_run_resumes_bit_for_bit_from_a_checkpoint():
+    """Checkpoint after conversions (solid mask, raw populations, deposits), restore
+    into a new lattice, and both continue through further conversions identically."""
+    p, mask, rho, C = _case("D2Q9", 2, (1, 36, 40), sample=5)
+    lat = mclbm.Lattice(p)
+    lat.set_geometry(mask)
+    lat.init_fields(rho, None, C)
+    lat.step(90)
+    m90, _, _ = lat.get_geometry()
+    pops = lat.populations(raw=True)
+    Cps, conv = lat.get_deposit()
+    assert conv > 0
+    lat.step(70)
+    lat2 = mclbm.Lattice(p)
+    lat2.set_geometry(m90)
+    lat2.init_fields(rho * (m90.reshape(mask.shape) == 0), None, C)
+    lat2.set_populations(pops, raw=True)
+    lat2.set_deposit(Cps, conv)
+    lat2.step(70)
+    a, b = lat.get_deposit(), lat2.get_deposit()
+    print(conv, a[1], b[1], flush=True)
+    assert a[1] == b[1] and a[1] > conv
+    assert np.array_equal(lat.get_geometry()[0], lat2.get_geometry()[0])
+    assert np.array_equal(lat.populations(raw=True), lat2.populations(raw=True))
+    assert np.array_equal(a[0], b[0])
+    lat.close()
+    lat2.close()
