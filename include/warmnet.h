@@ -3,7 +3,7 @@
  *
  * The learned warm start predicts a steady velocity / phase field from the
  * solid mask and the initial phase field; the lattice Boltzmann solver then
- * starts from that prediction and remains the judge of convergence.  These
+ * starts from that prediction and still decides when it has converged.  These
  * entry points are the layers of that network (a 3-D U-Net), written as HIP
  * kernels: 3-D convolutions on BF16 matrix cores (MFMA, FP32 accumulation)
  * over 256-voxel bricks staged with their halo in LDS, their data and weight
