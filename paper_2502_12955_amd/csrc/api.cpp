@@ -960,17 +960,17 @@ int mclbm_get_deposit(mclbm_handle* h, double* Cps, int64_t* converted) {
 }
 
 // Steps with particle deposition (eq:surface_deposition).  Steps run in batches
-// of up to DEP_BATCH, never past the next monitor step; the batch length adapts
-// to the spacing of conversions (twice the steps to the last conversion, doubled
-// after a batch without one), so that dense conversions do not waste most of a
-// long batch.  Each step is followed by
-// the deposit update, which counts the deposits above 1 into a slot of its own,
-// and one synchronisation per batch reads the counts.  The populations and
+// of up to DEP_BATCH, never past the next monitor step.  Each step is followed
+// by the deposit update, which counts the deposits above 1 into a slot of its
+// own, and one synchronisation per batch reads the counts.  The populations and
 // deposits at the start of the batch are kept in a device snapshot: if the j-th
 // step of the batch made some deposit exceed 1 and later steps ran on, the
-// snapshot is restored and the first j steps are run again (every kernel on this
-// path is deterministic, so they reproduce the same state bit for bit); those
-// nodes then turn solid before the next step.
+// snapshot is restored and the first j steps are run again (every value these
+// kernels write is deterministic; the count is the only atomic), so the state
+// is reproduced bit for bit; those nodes then turn solid before the next step.
+// The batch length adapts to the spacing of conversions (twice the steps to the
+// last one, doubled after a batch without one), so that dense conversions do
+// not waste most of a long batch.
 static int step_deposition(mclbm_handle* h, int64_t n) {
     const int K = h->p.monitor_every;
     const size_t sb = store_bytes(h->p.storage);
