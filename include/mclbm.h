@@ -184,8 +184,11 @@ int mclbm_get_deposit(mclbm_handle* h, double* Cps, int64_t* converted);
  * ignored) and the converted-node count, e.g. from mclbm_get_deposit.  With
  * mclbm_get_geometry's mask, mclbm_get_populations(raw = 1) and these, a
  * deposition run resumes bit for bit: set_geometry(mask), init_fields,
- * set_populations(raw = 1), set_wall_rate if used, set_deposit.  Needs
- * deposition = 1.  Errors: ESTATE before init_fields, EINVAL (negative or
+ * set_populations(raw = 1), set_wall_rate if used, set_deposit.  With 16-bit
+ * storage the raw values are relative to the storage shift that init_fields
+ * fixes (the mean initial density over the fluid nodes), so init_fields must
+ * give the same shift as in the original run (e.g. uniform initial densities).
+ * Needs deposition = 1.  Errors: ESTATE before init_fields, EINVAL (negative or
  * non-finite deposit on a fluid node). */
 int mclbm_set_deposit(mclbm_handle* h, const double* Cps, int64_t converted);
 
