@@ -96,7 +96,8 @@ struct SampleHost {
     long long kbase;  // first fluid index (multiple of 64)
     long long nf;     // fluid nodes
     std::vector<uint8_t> mask;
-    std::vector<unsigned> pos;  // box index of each fluid node, increasing
+    std::vector<unsigned> pos;  // box index of each fluid node, in the fluid numbering (band order)
+    std::vector<uint32_t> words;  // link word of each fluid node (kept for deposition runs)
     bool frozen = false;        // converged or diverged, excluded from the work list
     long long conv_step = -1;
     long long div_step = -1;    // monitor step at which a non-finite value was seen
@@ -753,6 +754,10 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
             pos[(size_t)(kbase + k)] = sm.pos[k];
             links[(size_t)(kbase + k)] = words[sm.pos[k]];
         }
+        if (h->dep) {   // deposition updates the geometry incrementally from these
+            sm.words.resize((size_t)sm.nf);
+            for (long long k = 0; k < sm.nf; ++k) sm.words[(size_t)k] = words[sm.pos[k]];
+        }
         for (long long c = 0; c < padded / 64; ++c) chunk_sample.push_back(s);
         sd[s] = SampleDev{sm.nx, sm.ny, sm.nz, (int)sm.nf, (int)sm.N, (int)sm.dbase, (int)sm.kbase, 0};
         sm.frozen = false;
@@ -887,59 +892,76 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     return MCLBM_OK;
 }
 
-// The nodes whose deposit exceeds 1 turn solid: the geometry is rebuilt on the
-// host (pinch rule, numbering, link words) and the state of every node that is
-// still fluid moves to its new fluid index on the device.
+// The nodes whose deposit exceeds 1 turn solid.  The host updates the geometry
+// incrementally (the pinch rule from the new solid nodes, the fluid list in the
+// same band order without them, the link words within two nodes of them: the
+// same result as mclbm_set_geometry on the new mask) and uploads it; the state
+// of every node that is still fluid moves to its new fluid index on the device.
 static int convert_deposits(mclbm_handle* h) {
     SampleHost& sm = h->smp[0];   // deposition runs on a single lattice (kbase 0)
     const long long nf_before = sm.nf;
     std::vector<double> dv((size_t)sm.nf);
     HIPCHK(h, hipMemcpyAsync(dv.data(), h->dep, dv.size() * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    // new solid mask: the current one plus every node whose deposit exceeds 1;
-    // the old fluid index and the deposit of every node, by box index
-    std::vector<uint8_t> mask = sm.mask;
-    std::vector<int> old_k((size_t)sm.N, -1);
-    std::vector<double> dbox((size_t)sm.N, 0.0);
+    std::vector<long long> add;
+    for (long long k = 0; k < sm.nf; ++k)
+        if (dv[(size_t)k] > 1.0) add.push_back((long long)sm.pos[k]);
+    drop_graphs(h);
+    const GeomSpec gs{h->p.lattice, sm.nx, sm.ny, sm.nz, h->p.solute};
+    std::vector<int> from;
+    convert_nodes(gs, sm.mask, sm.pos, sm.words, add, from);
+    sm.nf = (long long)sm.pos.size();
+    if (sm.nf == 0) {
+        h->geom_set = h->fields_set = false;
+        return fail(h, MCLBM_EINVAL, "deposition left no fluid node (the lattice needs set_geometry again)");
+    }
+    // device geometry in the new numbering (tail lanes as set_geometry makes them)
+    const long long padded = pad64(sm.nf);
+    std::vector<int> map((size_t)h->Ntot, -1);
+    std::vector<unsigned> pos((size_t)padded, 0u);
+    std::vector<uint32_t> links((size_t)padded, tail_link_word(h->p.lattice));
+    std::vector<int> fromp((size_t)padded, -1);
+    std::vector<double> dn((size_t)padded, 0.0);
     for (long long k = 0; k < sm.nf; ++k) {
-        old_k[sm.pos[k]] = (int)k;
-        if (dv[(size_t)k] > 1.0)
-            mask[sm.pos[k]] = 1;
-        else
-            dbox[sm.pos[k]] = dv[(size_t)k];
+        map[sm.pos[k]] = (int)k;
+        pos[(size_t)k] = sm.pos[k];
+        links[(size_t)k] = sm.words[(size_t)k];
+        fromp[(size_t)k] = from[(size_t)k];
+        dn[(size_t)k] = dv[(size_t)from[(size_t)k]];
     }
-    const int64_t converted = h->dep_converted;
-    const std::vector<double> kb = h->k_box;
-    int rc = mclbm_set_geometry(h, mask.data(), nullptr);   // pinch rule, numbering, link words; zeroes dep
-    if (rc != MCLBM_OK) return rc;
-    if (!kb.empty()) {
-        rc = mclbm_set_wall_rate(h, kb.data());
-        if (rc != MCLBM_OK) return rc;
-    }
-    // the fluid nodes only lose members, so every new fluid node has an old index
-    const size_t M = (size_t)h->nchunks * 64;
-    std::vector<int> from(M, -1);
-    std::vector<double> dn(M, 0.0);
-    for (long long k = 0; k < sm.nf; ++k) {
-        from[(size_t)k] = old_k[sm.pos[k]];
-        dn[(size_t)k] = dbox[sm.pos[k]];
-    }
-    int* d_from = (int*)h->dep_snap;   // free between batches; holds at least M doubles
-    HIPCHK(h, hipMemcpyAsync(d_from, from.data(), M * 4, hipMemcpyHostToDevice, h->stream));
+    const std::vector<int> chunk_sample((size_t)(padded / 64), 0);
+    const SampleDev sd{sm.nx, sm.ny, sm.nz, (int)sm.nf, (int)sm.N, (int)sm.dbase, (int)sm.kbase, 0};
+    h->nchunks = padded / 64;
+    HIPCHK(h, hipMemcpyAsync(h->map, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->links, links.data(), links.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->smp_dev, &sd, sizeof(SampleDev), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->chunk_sample, chunk_sample.data(), chunk_sample.size() * 4, hipMemcpyHostToDevice,
+                             h->stream));
+    // the state moves to the new numbering on the device (the batch snapshot area
+    // is free here and holds at least M doubles)
+    int* d_from = (int*)h->dep_snap;
+    HIPCHK(h, hipMemcpyAsync(d_from, fromp.data(), fromp.size() * 4, hipMemcpyHostToDevice, h->stream));
     const int sb = (int)store_bytes(h->p.storage);
-    HIPCHK(h, k_remap_planes(h->fB, h->fA, h->NC * h->Q, d_from, (long long)M, sb, h->stream));
+    HIPCHK(h, k_remap_planes(h->fB, h->fA, h->NC * h->Q, d_from, padded, sb, h->stream));
     std::swap(h->fA, h->fB);
-    HIPCHK(h, k_remap_planes(h->hB, h->hA, h->HP, d_from, (long long)M, sb, h->stream));
+    HIPCHK(h, k_remap_planes(h->hB, h->hA, h->HP, d_from, padded, sb, h->stream));
     std::swap(h->hA, h->hB);
-    HIPCHK(h, hipMemcpyAsync(h->dep, dn.data(), M * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->dep, dn.data(), dn.size() * 8, hipMemcpyHostToDevice, h->stream));
     // the dense pseudo-potential field is written only at fluid nodes (each step's
     // density pass): the nodes that just turned solid must read 0 there, as every
     // solid node does after init_fields
     HIPCHK(h, hipMemsetAsync(h->psi, 0, (size_t)h->NC * h->Ntot * arith_bytes(h->p.storage), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));   // before the host vectors go
-    h->fields_set = true;
+    int rc = upload_work(h);
+    if (rc != MCLBM_OK) return rc;
+    if (h->kfield) {   // the rate planes follow the new numbering
+        const std::vector<double> kb = h->k_box;
+        rc = mclbm_set_wall_rate(h, kb.data());
+        if (rc != MCLBM_OK) return rc;
+    }
     h->snap_valid = false;
-    h->dep_converted = converted + (nf_before - sm.nf);
+    h->dep_converted += nf_before - sm.nf;
     return MCLBM_OK;
 }
 

@@ -8,6 +8,7 @@
 // mask whatever the processing order; a work list reaches it in O(N).
 #include <stdint.h>
 
+#include <algorithm>
 #include <thread>
 #include <vector>
 
@@ -107,17 +108,59 @@ static const int C19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {
 static const int C9[9][3] = {{0, 0, 0}, {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
                              {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
 
+namespace {
+
+struct WordCtx {
+    Grid g;
+    int Q, QS;
+    const int (*c)[3];
+    int wet_shift, hop_shift;
+    bool in_x(int x) const { return !g.seam || (x >= 0 && x < g.nx); }
+};
+
+WordCtx word_ctx(const GeomSpec& s) {
+    WordCtx w{Grid{s.nx, s.ny, s.nz, s.lattice == 1 ? 3 : 2, s.solute == 2}, s.lattice == 1 ? 19 : 9,
+              s.lattice == 1 ? 7 : 5, s.lattice == 1 ? C19 : C9, s.lattice == 1 ? 18 : 8, s.lattice == 1 ? 24 : 12};
+    return w;
+}
+
+// Link word of the fluid node (x, y, z): upstream-solid flow bits, wet solute
+// links, and the bits of the solute directions whose next node is fluid with a
+// wet link in that direction.
+uint32_t word_at(const WordCtx& W, const std::vector<uint8_t>& mask, int x, int y, int z, uint32_t* fb_out,
+                 uint32_t* sb_out) {
+    const Grid& g = W.g;
+    const int(*c)[3] = W.c;
+    uint32_t fb = 0, sb = 0;
+    for (int i = 1; i < W.Q; ++i)
+        if (mask[g.idx(x - c[i][0], y - c[i][1], z - c[i][2])]) fb |= 1u << i;
+    for (int k = 1; k < W.QS; ++k) {
+        if (!W.in_x(x - c[k][0])) continue;
+        if (mask[g.idx(x - c[k][0], y - c[k][1], z - c[k][2])]) sb |= 1u << k;
+    }
+    uint32_t w = fb | (sb << W.wet_shift);
+    for (int d = 1; d < W.QS; ++d) {
+        // neighbour y = n + e_d, reached without crossing a seam, fluid, whose
+        // upstream in direction opp(d) (= n + 2 e_d) is solid and in the domain
+        if (!W.in_x(x + c[d][0]) || !W.in_x(x + 2 * c[d][0])) continue;
+        if (mask[g.idx(x + c[d][0], y + c[d][1], z + c[d][2])]) continue;
+        if (mask[g.idx(x + 2 * c[d][0], y + 2 * c[d][1], z + 2 * c[d][2])]) w |= 1u << (W.hop_shift + d);
+    }
+    if (fb_out) *fb_out = fb;
+    if (sb_out) *sb_out = sb;
+    return w;
+}
+
+}  // namespace
+
 void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector<uint32_t>& words,
                 std::vector<uint32_t>* flow_bits, std::vector<uint32_t>* solute_bits) {
-    Grid g{s.nx, s.ny, s.nz, s.lattice == 1 ? 3 : 2, s.solute == 2};
-    const int Q = s.lattice == 1 ? 19 : 9, QS = s.lattice == 1 ? 7 : 5;
-    const int(*c)[3] = s.lattice == 1 ? C19 : C9;
-    const int wet_shift = s.lattice == 1 ? 18 : 8, hop_shift = s.lattice == 1 ? 24 : 12;
+    const WordCtx W = word_ctx(s);
+    const Grid& g = W.g;
     const long long N = (long long)g.nx * g.ny * g.nz;
     words.assign((size_t)N, 0u);
     if (flow_bits) flow_bits->assign((size_t)N, 0u);
     if (solute_bits) solute_bits->assign((size_t)N, 0u);
-    auto in_x = [&](int x) { return !g.seam || (x >= 0 && x < g.nx); };
     parallel_rows(g.ny, g.nz, [&](unsigned, int z, int y) {
         for (int x = 0; x < g.nx; ++x) {
             const long long n = g.idx(x, y, z);
@@ -125,26 +168,95 @@ void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector
                 words[n] = 0x80000000u;
                 continue;
             }
-            uint32_t w = 0, fb = 0, sb = 0;
-            for (int i = 1; i < Q; ++i)
-                if (mask[g.idx(x - c[i][0], y - c[i][1], z - c[i][2])]) fb |= 1u << i;
-            for (int k = 1; k < QS; ++k) {
-                if (!in_x(x - c[k][0])) continue;
-                if (mask[g.idx(x - c[k][0], y - c[k][1], z - c[k][2])]) sb |= 1u << k;
-            }
-            w = fb | (sb << wet_shift);
-            for (int d = 1; d < QS; ++d) {
-                // neighbour y = n + e_d, reached without crossing a seam, fluid, whose
-                // upstream in direction opp(d) (= n + 2 e_d) is solid and in the domain
-                if (!in_x(x + c[d][0]) || !in_x(x + 2 * c[d][0])) continue;
-                if (mask[g.idx(x + c[d][0], y + c[d][1], z + c[d][2])]) continue;
-                if (mask[g.idx(x + 2 * c[d][0], y + 2 * c[d][1], z + 2 * c[d][2])]) w |= 1u << (hop_shift + d);
-            }
-            words[n] = w;
+            uint32_t fb = 0, sb = 0;
+            words[n] = word_at(W, mask, x, y, z, &fb, &sb);
             if (flow_bits) (*flow_bits)[n] = fb;
             if (solute_bits) (*solute_bits)[n] = sb;
         }
     });
+}
+
+int64_t convert_nodes(const GeomSpec& s, std::vector<uint8_t>& mask, std::vector<unsigned>& pos,
+                      std::vector<uint32_t>& words, const std::vector<long long>& add, std::vector<int>& from) {
+    const WordCtx W = word_ctx(s);
+    const Grid& g = W.g;
+    static const int ax[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    // 1. the new solid nodes, then the pinch rule from their axis neighbours
+    std::vector<long long> newly, work;
+    auto xyz = [&](long long n, int& x, int& y, int& z) {
+        x = (int)(n % g.nx);
+        y = (int)((n / g.nx) % g.ny);
+        z = (int)(n / ((long long)g.nx * g.ny));
+    };
+    auto push_axis_neighbours = [&](long long n) {
+        int x, y, z;
+        xyz(n, x, y, z);
+        for (int a = 0; a < g.dim; ++a)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const int xx = x + sgn * ax[a][0];
+                if (g.seam && (xx < 0 || xx >= g.nx)) continue;
+                work.push_back(g.idx(xx, y + sgn * ax[a][1], z + sgn * ax[a][2]));
+            }
+    };
+    for (long long n : add)
+        if (!mask[n]) {
+            mask[n] = 1;
+            newly.push_back(n);
+            push_axis_neighbours(n);
+        }
+    while (!work.empty()) {
+        const long long n = work.back();
+        work.pop_back();
+        if (mask[n]) continue;
+        int x, y, z;
+        xyz(n, x, y, z);
+        if (!pinched(g, mask, x, y, z)) continue;
+        mask[n] = 1;
+        newly.push_back(n);
+        push_axis_neighbours(n);
+    }
+    // 2. the fluid list without them, in the same (band) order
+    const long long nf_old = (long long)pos.size();
+    std::vector<unsigned> pos_new;
+    std::vector<uint32_t> words_new;
+    pos_new.reserve((size_t)nf_old);
+    words_new.reserve((size_t)nf_old);
+    from.clear();
+    for (long long k = 0; k < nf_old; ++k) {
+        if (mask[pos[k]]) continue;
+        pos_new.push_back(pos[k]);
+        words_new.push_back(words[k]);
+        from.push_back((int)k);
+    }
+    // 3. link words of the fluid nodes within two nodes of a new solid node
+    //    (flow and wet bits look one node upstream, the wet-neighbour bits two)
+    std::vector<long long> touched;
+    for (long long n : newly) {
+        int x, y, z;
+        xyz(n, x, y, z);
+        for (int dz = (g.dim == 3 ? -2 : 0); dz <= (g.dim == 3 ? 2 : 0); ++dz)
+            for (int dy = -2; dy <= 2; ++dy)
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const long long m = g.idx(x + dx, y + dy, z + dz);
+                    if (!mask[m]) touched.push_back(m);
+                }
+    }
+    if (!touched.empty()) {
+        std::sort(touched.begin(), touched.end());
+        touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+        // new fluid index of each touched node: binary search in the band order
+        // is not possible (pos is not sorted by box index), so map them once
+        std::vector<int> knew((size_t)g.nx * g.ny * g.nz, -1);
+        for (size_t k = 0; k < pos_new.size(); ++k) knew[pos_new[k]] = (int)k;
+        for (long long m : touched) {
+            int x, y, z;
+            xyz(m, x, y, z);
+            words_new[(size_t)knew[m]] = word_at(W, mask, x, y, z, nullptr, nullptr);
+        }
+    }
+    pos.swap(pos_new);
+    words.swap(words_new);
+    return (int64_t)newly.size();
 }
 
 }  // namespace mclbm

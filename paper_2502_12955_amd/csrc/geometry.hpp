@@ -21,4 +21,14 @@ int64_t pinch_fill(const GeomSpec& s, std::vector<uint8_t>& mask);
 void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector<uint32_t>& words,
                 std::vector<uint32_t>* flow_bits, std::vector<uint32_t>* solute_bits);
 
+// Turns the fluid nodes listed in `add` (box indices) solid, applies the pinch
+// rule from them, and updates in place: mask, pos (fluid index -> box index, in
+// the same band order without the nodes that turned solid) and words (link
+// word of each fluid node, recomputed where a new solid node is within two
+// nodes).  from[k] receives the old fluid index of new fluid node k.  Returns
+// the number of nodes that turned solid.  The result equals pinch_fill and
+// link_words applied to the new mask.
+int64_t convert_nodes(const GeomSpec& s, std::vector<uint8_t>& mask, std::vector<unsigned>& pos,
+                      std::vector<uint32_t>& words, const std::vector<long long>& add, std::vector<int>& from);
+
 }  // namespace mclbm
