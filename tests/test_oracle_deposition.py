@@ -32,39 +32,42 @@ def _rest_box(lattice, shape, mask):
     return p, np.ascontiguousarray(m.reshape(-1)), f, h
 
 
-def test_deposit_layers_grow_one_node_per_closed_form_period():
-    nz, ny, nx = 1, 12, 10
+@pytest.mark.parametrize("lattice,nz", [("D2Q9", 1), ("D3Q19", 3)])
+def test_deposit_layers_grow_one_node_per_closed_form_period(lattice, nz):
+    ny, nx = 12, 10
     mask = np.zeros((nz, ny, nx), np.uint8)
-    mask[0, 0, :] = 1
-    mask[0, ny - 1, :] = 1
-    p, m, f, h = _rest_box("D2Q9", (nz, ny, nx), mask)
+    mask[:, 0, :] = 1
+    mask[:, ny - 1, :] = 1
+    p, m, f, h = _rest_box(lattice, (nz, ny, nx), mask)
+    QS = 7 if lattice == "D3Q19" else 5
     t_star = math.floor(1.0 / (DP * C0)) + 1
     assert t_star == 271
     Cps = np.zeros(nx * ny * nz)
-    rows = lambda a: a.reshape(ny, nx)
+    rows = lambda a: a.reshape(nz, ny, nx).transpose(1, 0, 2).reshape(ny, nz * nx)   # [y][z, x]
     n = oracle.step_deposit(p, m, f, h, Cps, DP, t_star - 1)
     assert n == 0
     # rows next to a wall hold (t*-1) DP c0; the rows further in hold nothing
     assert np.allclose(rows(Cps)[[1, ny - 2]], (t_star - 1) * DP * C0, rtol=1e-12, atol=0)
     assert np.all(rows(Cps)[2:ny - 2] == 0.0)
     # the particle field is still exactly uniform
-    C = h[:5].sum(axis=0)
+    C = h[:QS].sum(axis=0)
     assert np.allclose(C[m == 0], C0, rtol=1e-13, atol=0)
     fluid_mass = f.sum()
+    layer = nx * nz
     n = oracle.step_deposit(p, m, f, h, Cps, DP, 1)
-    assert n == 2 * nx
+    assert n == 2 * layer
     assert np.all(rows(m)[[0, 1, ny - 2, ny - 1]] == 1) and np.all(rows(m)[2:ny - 2] == 0)
-    assert np.all(rows(Cps)[[1, ny - 2]] == 0.0) and np.all(f[:, rows(m).reshape(-1) == 1] == 0.0)
+    assert np.all(rows(Cps)[[1, ny - 2]] == 0.0) and np.all(f[:, m == 1] == 0.0)
     # the converted nodes took their fluid (rho = 1 each) and particles (c0 each) with them
-    assert abs(f.sum() - (fluid_mass - 2 * nx)) < 1e-10
-    assert abs(h[:5].sum() - C0 * nx * (ny - 4)) < 1e-10
+    assert abs(f.sum() - (fluid_mass - 2 * layer)) < 1e-10
+    assert abs(h[:QS].sum() - C0 * layer * (ny - 4)) < 1e-10
     # the next layer starts from zero and needs the same t* steps
     n = oracle.step_deposit(p, m, f, h, Cps, DP, t_star - 1)
     assert n == 0
     assert np.allclose(rows(Cps)[[2, ny - 3]], (t_star - 1) * DP * C0, rtol=1e-12, atol=0)
     n = oracle.step_deposit(p, m, f, h, Cps, DP, 1)
-    assert n == 2 * nx
-    assert int(m.sum()) == 6 * nx
+    assert n == 2 * layer
+    assert int(m.sum()) == 6 * layer
 
 
 @pytest.mark.parametrize("lattice,shape,nbrs", [("D2Q9", (1, 9, 9), 8), ("D3Q19", (7, 7, 7), 18)])
