@@ -105,7 +105,12 @@ typedef struct {
  * partials).  Returns MCLBM_EINVAL for invalid parameters. */
 int mclbm_required_bytes(const mclbm_params* p, size_t* bytes);
 
-/* Create a lattice.  device_arena: caller-owned device memory of at least
+/* Create a lattice for the problem of the multi-component LBM section: the
+ * components with their own relaxation times (eq:1.16), the interaction
+ * matrix G (eq:1.14), the adhesion strengths (eq:1.15), the pseudo-potential
+ * reference density (eq:1.11), the forcing scheme (eq:1.17-eq:1.21) and the
+ * solute of the reactive LBM (eq:therpop_species, eq:wetnode9).
+ * device_arena: caller-owned device memory of at least
  * mclbm_required_bytes() bytes, 256-byte aligned, kept alive and untouched by
  * the caller until mclbm_destroy(); NULL makes the library allocate (and
  * later free) its own.  hip_stream: a hipStream_t (NULL = the null stream) on
@@ -118,7 +123,10 @@ int mclbm_required_bytes(const mclbm_params* p, size_t* bytes);
 int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_bytes,
                        void* hip_stream, mclbm_handle** out);
 
-/* Set the solid geometry from a host mask of N bytes (1 = solid, 0 = fluid).
+/* Set the solid geometry from a host mask of N bytes (1 = solid, 0 = fluid):
+ * the solid indicator s(x) of the adhesion force (eq:1.15), the halfway
+ * bounce-back links of the flow (eq:5 with the bounce-back rule of the
+ * boundary-condition section) and the wet links of the solute (eq:wetnode9).
  * Fluid voxels that have solids on both sides along one axis (and, with the
  * inlet/outlet solute, voxels pinched against the x = 0 / x = nx-1 planes)
  * are reclassified as solid, to a fixed point; *n_reclassified (may be NULL)
@@ -136,8 +144,8 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
 int mclbm_get_geometry(mclbm_handle* h, uint8_t* mask_out, uint32_t* flow_links,
                        uint32_t* solute_links);
 
-/* Initial state at equilibrium without force term: f_i = f^eq_i(rho_s, u),
- * h_k = h^eq_k(C, u).  rho: host FP64 [ncomp][N] (must be > 0 on fluid
+/* Initial state at equilibrium without force term: f_i = f^eq_i(rho_s, u)
+ * of eq:6, h_k = h^eq_k(C, u) of eq:therpopeq_species.  rho: host FP64 [ncomp][N] (must be > 0 on fluid
  * nodes); u: host FP64 [3][N] or NULL (rest); C: host FP64 [N] or NULL
  * (zero).  The product species (if on) starts at zero concentration.
  * Resets the step counter and the residual snapshot, and fixes the

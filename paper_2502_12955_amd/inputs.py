@@ -209,3 +209,11 @@ def batch_edges(count=64, seed=None, choices=(32, 48, 64, 96, 128)):
     rng = SplitMix64(seed_for(4, 0) if seed is None else seed)
     picks = rng.integers(3 * count, len(choices)).reshape(count, 3)
     return [tuple(int(choices[j]) for j in row) for row in picks]
+
+
+def arrhenius_rate_field(T, A, E_over_R):
+    """Per-node first-order wall reaction rate k = A exp(-E / (R_u T)) (the rate law of
+    the O2 reaction, eq:reactO2) of a prescribed temperature field T [K]; E_over_R =
+    E / R_u in K.  An input generator for the rate-field runs: both sides take the
+    resulting k values as given."""
+    return A * np.exp(-E_over_R / np.asarray(T, np.float64))

@@ -203,12 +203,6 @@ def step(h, n: int, allow_diverged=False):
     return _check(load().mclbm_step(h, int(n)), h, allow)
 
 
-def arrhenius(T, A, E_over_R):
-    """First-order wall reaction rate k = A exp(-E / (R_u T)) (eq:reactO2) of a
-    temperature field T [K]; E_over_R = E / R_u in K."""
-    return A * np.exp(-E_over_R / np.asarray(T, np.float64))
-
-
 def set_wall_rate(h, k_box):
     """Per-node reaction rate [N] (box nodes; needs rate_field=1 and set_geometry first)."""
     k = np.ascontiguousarray(k_box, np.float64).reshape(-1)

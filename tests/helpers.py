@@ -14,6 +14,17 @@ def nrel(a, b):
     return num / den if den else num
 
 
+def maxrel(a, b):
+    """Element-wise difference relative to the field's scale: max|a - b| / max|b|
+    (max|a - b| if b vanishes).  One wrong value anywhere in the field shows up at
+    its own size, unlike a norm over the whole field."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    num = float(np.max(np.abs(a - b), initial=0.0))
+    den = float(np.max(np.abs(b), initial=0.0))
+    return num / den if den else num
+
+
 def gpu_lattice(p, mask, rho, u=None, C=None, block=None):
     from paper_2502_12955_amd import mclbm
 

@@ -4,8 +4,8 @@ the FP64 oracle, through the C ABI.
 The deposits grow at the nodes next to the substrate after every step, nodes
 whose deposit exceeds 1 turn solid (the pinch rule again), and the run goes on
 on the new geometry.  After many conversions the solid mask is bit-identical to
-the oracle's, the populations and deposits agree to 1e-12 (normwise), and the
-count of converted nodes matches.
+the oracle's, the populations and deposits agree element by element to 1e-12
+of each field's scale, and the count of converted nodes matches.
 """
 import numpy as np
 import pytest
@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_2502_12955_amd import inputs, mclbm
 
-from helpers import nrel, split_pops
+from helpers import maxrel, split_pops
 
 pytestmark = pytest.mark.gpu
 
@@ -54,12 +54,12 @@ def test_deposition_matches_oracle(lattice, ncomp, shape):
     mg, _, _ = lat.get_geometry()
     fg, hg = split_pops(p, lat.populations())
     Cg, convg = lat.get_deposit()
-    print(lattice, ncomp, conv, convg, nrel(fg, f), nrel(hg, h), nrel(Cg, Cps), flush=True)
+    print(lattice, ncomp, conv, convg, maxrel(fg, f), maxrel(hg, h), maxrel(Cg, Cps), flush=True)
     assert conv > 10                                  # several conversions happened
     assert np.array_equal(mg, m)
     assert convg == conv
-    assert nrel(fg, f) < 1e-12 and nrel(hg, h) < 1e-12
-    assert nrel(Cg, Cps) < 1e-12
+    assert maxrel(fg, f) < 1e-12 and maxrel(hg, h) < 1e-12
+    assert maxrel(Cg, Cps) < 1e-12
     assert np.all(Cg[m != 0] == 0.0)
     # monitors count the fluid nodes of the new geometry
     lat.monitor_now()
@@ -70,14 +70,14 @@ def test_deposition_matches_oracle(lattice, ncomp, shape):
 def test_deposition_keeps_the_rate_field_across_rebuilds():
     p, mask, rho, C = _case("D2Q9", 1, (1, 32, 40), sample=6, rate_field=1, k_wall=0.0)
     zz, yy, xx = np.meshgrid(*[np.arange(s) for s in mask.shape], indexing="ij")
-    k_node = mclbm.arrhenius(700.0 + 10.0 * xx + 3.0 * yy, 1.0, 2500.0).reshape(-1)
+    k_node = inputs.arrhenius_rate_field(700.0 + 10.0 * xx + 3.0 * yy, 1.0, 2500.0).reshape(-1)
     (m, f, h, Cps, conv), lat = _run_both(p, mask, rho, C, 150, k_node=k_node)
     mg, _, _ = lat.get_geometry()
     fg, hg = split_pops(p, lat.populations())
     Cg, convg = lat.get_deposit()
-    print(conv, convg, nrel(hg, h), flush=True)
+    print(conv, convg, maxrel(hg, h), flush=True)
     assert conv > 10 and convg == conv and np.array_equal(mg, m)
-    assert nrel(fg, f) < 1e-12 and nrel(hg, h) < 1e-12 and nrel(Cg, Cps) < 1e-12
+    assert maxrel(fg, f) < 1e-12 and maxrel(hg, h) < 1e-12 and maxrel(Cg, Cps) < 1e-12
     lat.close()
 
 
@@ -140,7 +140,7 @@ def test_a_channel_that_fills_up_is_reported():
     lat.init_fields(rho, None, C)
     lat.step(270)
     Cg, conv = lat.get_deposit()
-    assert conv == 0 and nrel(Cg, Cps270) < 1e-12
+    assert conv == 0 and maxrel(Cg, Cps270) < 1e-12
     with pytest.raises(mclbm.MclbmError) as e:
         lat.step(5)
     assert e.value.code == mclbm.EINVAL and "no fluid node" in str(e.value)

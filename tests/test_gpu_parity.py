@@ -1,7 +1,8 @@
 """GPU parity: the HIP library against the FP64 oracle, through the C ABI.
 
-FP64 storage: normwise relative difference <= 1e-12 per field (the method is
-deterministic; only summation order differs).  FP32: one step from the same
+FP64 storage: every value within 1e-12 of its field's scale, max|a - b| <=
+1e-12 max|b| per field (the method is deterministic; only summation order
+differs).  FP32: one step from the same
 state, per-value error <= 2e-6 of the population scale.  Geometry and link
 masks: bit-exact.
 """
@@ -11,7 +12,7 @@ import pytest
 import oracle
 from paper_2502_12955_amd import inputs
 
-from helpers import gpu_lattice, nrel, oracle_state, small_porous, split_pops
+from helpers import gpu_lattice, maxrel, oracle_state, small_porous, split_pops
 
 pytestmark = pytest.mark.gpu
 
@@ -24,9 +25,10 @@ def variants():
     return BLOCKS
 
 
-def test_droplet_2d_fp64_matches_oracle_over_2000_steps(variants):
-    """D2Q9 two-component droplet, 128x64, tau = 1, G_c = 5, Guo forcing, 2000 steps."""
-    p, mask, rho, _, _ = inputs.droplet_2d_case()
+@pytest.mark.parametrize("forcing", ["guo", "sc"])
+def test_droplet_2d_fp64_matches_oracle_over_2000_steps(forcing, variants):
+    """D2Q9 two-component droplet, 128x64, tau = 1, G_c = 5, 2000 steps, both forcings."""
+    p, mask, rho, _, _ = inputs.droplet_2d_case(forcing=forcing)
     m, f, h = oracle_state(p, mask, rho)
     ref = []
     for _ in range(4):
@@ -37,9 +39,9 @@ def test_droplet_2d_fp64_matches_oracle_over_2000_steps(variants):
         for k in range(4):
             lat.step(500)
             r, u, _ = lat.moments()
-            print(var, (k + 1) * 500, nrel(r, ref[k][0]), nrel(u, ref[k][1]), flush=True)
-            assert nrel(r, ref[k][0]) < 1e-12
-            assert nrel(u, ref[k][1]) < 1e-12
+            print(var, (k + 1) * 500, maxrel(r, ref[k][0]), maxrel(u, ref[k][1]), flush=True)
+            assert maxrel(r, ref[k][0]) < 1e-12
+            assert maxrel(u, ref[k][1]) < 1e-12
         mon = lat.monitors()
         assert mon[0] == 2000
         rr = ref[-1][0]
@@ -51,19 +53,20 @@ def test_droplet_2d_fp64_matches_oracle_over_2000_steps(variants):
 @pytest.mark.parametrize("forcing", ["guo", "sc"])
 @pytest.mark.parametrize("solute", ["inlet_outlet_x", "periodic"])
 def test_porous_3d_fp64_populations_match_oracle(forcing, solute, variants):
-    """D3Q19 x2 + D3Q7, sphere pack with ragged box sizes, adhesion, drive, wall reaction."""
+    """D3Q19 x2 + D3Q7, sphere pack with ragged box sizes, adhesion, drive, wall
+    reaction; every population after 200 steps."""
     p, mask, rho, u, C = small_porous(forcing=forcing, solute=solute, storage="f64",
                                       tau=(0.9, 1.3) if forcing == "sc" else (1.0, 1.0),
                                       k_wall=0.05, C_in=1.0)
     m, f, h = oracle_state(p, mask, rho, u, C)
-    oracle.step(p, m, f, h, 40)
+    oracle.step(p, m, f, h, 200)
     for var in variants:
         lat = gpu_lattice(p, mask, rho, u, C, block=var)
-        lat.step(40)
+        lat.step(200)
         fg, hg = split_pops(p, lat.populations())
-        print(var, forcing, solute, nrel(fg, f), nrel(hg, h), flush=True)
-        assert nrel(fg, f) < 1e-12
-        assert nrel(hg, h) < 1e-12
+        print(var, forcing, solute, maxrel(fg, f), maxrel(hg, h), flush=True)
+        assert maxrel(fg, f) < 1e-12
+        assert maxrel(hg, h) < 1e-12
         lat.close()
 
 
@@ -84,7 +87,7 @@ def test_single_component_channel_2d_with_solute(variants):
         lat = gpu_lattice(p, mask, rho, block=var)
         lat.step(300)
         fg, hg = split_pops(p, lat.populations())
-        assert nrel(fg, f) < 1e-12 and nrel(hg, h) < 1e-12
+        assert maxrel(fg, f) < 1e-12 and maxrel(hg, h) < 1e-12
         lat.close()
 
 

@@ -1,8 +1,8 @@
 """GPU: the product species (CO2 made at the reacting walls, eq:react /
 eq:reactCO2) against the FP64 oracle, through the C ABI.
 
-Every population of both solute species <= 1e-12 (normwise) after tens of
-steps, in 3-D porous media with inlet/outlet and periodic solute, both forcing
+Every population of both solute species within 1e-12 of the field's scale
+(element by element) after tens of steps, in 3-D porous media with inlet/outlet and periodic solute, both forcing
 schemes; the moments return both concentrations; a batch carries the product
 per sample exactly as single runs do.
 """
@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2502_12955_amd import inputs
 
-from helpers import gpu_lattice, nrel, oracle_state, small_porous, split_pops
+from helpers import gpu_lattice, maxrel, oracle_state, small_porous, split_pops
 
 pytestmark = pytest.mark.gpu
 
@@ -29,17 +29,17 @@ def test_product_populations_match_oracle(forcing, solute):
     lat.step(40)
     fg, hg = split_pops(p, lat.populations())
     QS = 7
-    print(forcing, solute, nrel(fg, f), nrel(hg[:QS], h[:QS]), nrel(hg[QS:], h[QS:]), flush=True)
+    print(forcing, solute, maxrel(fg, f), maxrel(hg[:QS], h[:QS]), maxrel(hg[QS:], h[QS:]), flush=True)
     assert hg.shape == h.shape == (2 * QS, f.shape[1])
     assert np.abs(h[QS:]).max() > 0          # the product exists
-    assert nrel(fg, f) < 1e-12
-    assert nrel(hg[:QS], h[:QS]) < 1e-12
-    assert nrel(hg[QS:], h[QS:]) < 1e-12
+    assert maxrel(fg, f) < 1e-12
+    assert maxrel(hg[:QS], h[:QS]) < 1e-12
+    assert maxrel(hg[QS:], h[QS:]) < 1e-12
     _, _, Cg = lat.moments()
     _, _, Co = oracle.moments(p, m, f, h)
     assert Cg.shape == Co.shape == (2, f.shape[1])
     assert np.all(Cg[:, m.reshape(-1) != 0] == 0.0)      # solid nodes read 0 in both planes
-    assert nrel(Cg, Co) < 1e-12
+    assert maxrel(Cg, Co) < 1e-12
     lat.close()
 
 
@@ -60,7 +60,7 @@ def test_product_in_a_2d_channel_and_fp32():
     lat = gpu_lattice(p, mask, rho)
     lat.step(300)
     fg, hg = split_pops(p, lat.populations())
-    assert nrel(fg, f) < 1e-12 and nrel(hg, h) < 1e-12
+    assert maxrel(fg, f) < 1e-12 and maxrel(hg, h) < 1e-12
     lat.close()
     # FP32: load the FP64 state, one step, compare with the oracle's step from it
     p32 = dict(p, storage="f32")
@@ -114,7 +114,7 @@ def test_rate_field_from_a_temperature_field_matches_oracle(product):
     shape = mask.shape
     zz, yy, xx = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
     T = 700.0 + 15.0 * xx + 5.0 * np.sin(yy + zz)
-    k_node = mclbm.arrhenius(T, 1.0, 2500.0).reshape(-1)
+    k_node = inputs.arrhenius_rate_field(T, 1.0, 2500.0).reshape(-1)
     assert 0.01 < k_node.min() and k_node.max() < 0.1
     po = dict(p, k_node=k_node)
     m, f, h = oracle_state(po, mask, rho, u, C)
@@ -125,6 +125,6 @@ def test_rate_field_from_a_temperature_field_matches_oracle(product):
     lat.init_fields(rho, u, C)
     lat.step(40)
     fg, hg = split_pops(p, lat.populations())
-    print(product, nrel(fg, f), nrel(hg, h), flush=True)
-    assert nrel(fg, f) < 1e-12 and nrel(hg, h) < 1e-12
+    print(product, maxrel(fg, f), maxrel(hg, h), flush=True)
+    assert maxrel(fg, f) < 1e-12 and maxrel(hg, h) < 1e-12
     lat.close()

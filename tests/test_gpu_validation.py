@@ -1,8 +1,8 @@
 """GPU: the multiphase validation cases of the paper on the HIP path.
 
 Single component with a diagonal cohesion (eq:1.12, G = -5): FP64 parity
-with the oracle (normwise <= 1e-12), a phase separation that reaches the
-flat-interface coexistence densities, and the two-component contact angle
+with the oracle (element by element, <= 1e-12 of the field's scale), a phase
+separation that reaches the flat-interface coexistence densities, and the two-component contact angle
 (eq:1.15) on the side of 90 degrees that the adhesion relation predicts.
 """
 import numpy as np
@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2502_12955_amd import inputs, validation
 
-from helpers import gpu_lattice, nrel, oracle_state, split_pops
+from helpers import gpu_lattice, maxrel, oracle_state, split_pops
 
 pytestmark = pytest.mark.gpu
 
@@ -32,8 +32,8 @@ def test_single_component_cohesion_fp64_matches_oracle(lattice, shape, forcing):
     lat = gpu_lattice(p, mask, rho)
     lat.step(300)
     fg, _ = split_pops(p, lat.populations())
-    print(lattice, forcing, nrel(fg, f), flush=True)
-    assert nrel(fg, f) < 1e-12
+    print(lattice, forcing, maxrel(fg, f), flush=True)
+    assert maxrel(fg, f) < 1e-12
     lat.close()
 
 
