@@ -233,6 +233,11 @@ int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw);
 /* Replace the pre-collision state of every sample (same layout as
  * mclbm_get_populations; the storage shift rhobar_s is kept).  Writing back
  * what get_populations(raw=1) returned continues the run bit for bit.
+ * raw == 0: each FP64 value is encoded on the device by the store the step
+ * kernels use: rounded to the arithmetic type (FP32 for F32 and the 16-bit
+ * formats), the shift w_i rhobar_s of its flow plane subtracted in that type
+ * (solute planes unshifted), then rounded to nearest even into FP16 / BF16
+ * (Inf stays Inf, NaN stays NaN, overflow gives Inf).
  * Convergence flags of a batch and the residual snapshot start over.  ESTATE
  * before init_fields. */
 int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw);

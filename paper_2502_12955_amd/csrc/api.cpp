@@ -47,44 +47,11 @@ float half_to_float(uint16_t h) {
     return f;
 }
 
-uint16_t float_to_half_rne(float f) {
-    uint32_t x;
-    memcpy(&x, &f, 4);
-    const uint16_t sign = (uint16_t)((x >> 16) & 0x8000u);
-    const uint32_t ax = x & 0x7fffffffu;
-    if (ax >= 0x7f800000u) return (uint16_t)(sign | 0x7c00u | (ax > 0x7f800000u ? 0x200u : 0u));
-    if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // rounds to >= 65520 -> inf
-    if (ax < 0x38800000u) {                                      // result subnormal or zero
-        if (ax < 0x33000000u) return sign;                       // < 2^-25: rounds to 0
-        const int e = (int)(ax >> 23);
-        const uint32_t man = (ax & 0x7fffffu) | 0x800000u;
-        const int shift = 126 - e;  // 14 - (e - 127) + 13 - 1 ... bits dropped to reach 2^-24 units
-        const uint32_t q = man >> (shift - 0);
-        const uint32_t rem = man & ((1u << shift) - 1u);
-        const uint32_t half = 1u << (shift - 1);
-        uint32_t r = q;
-        if (rem > half || (rem == half && (q & 1u))) ++r;
-        return (uint16_t)(sign | r);
-    }
-    uint32_t r = ax - 0x38000000u;  // rebias exponent (127 - 15 = 112 -> 112 << 23)
-    const uint32_t rem = r & 0x1fffu;
-    r >>= 13;
-    if (rem > 0x1000u || (rem == 0x1000u && (r & 1u))) ++r;
-    return (uint16_t)(sign | r);
-}
-
 float bf16_to_float_h(uint16_t b) {
     uint32_t u = (uint32_t)b << 16;
     float f;
     memcpy(&f, &u, 4);
     return f;
-}
-uint16_t float_to_bf16_rne_h(float f) {
-    uint32_t u;
-    memcpy(&u, &f, 4);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
 }
 
 }  // namespace
@@ -1211,36 +1178,45 @@ int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw) {
     const size_t M = (size_t)h->nchunks * 64;
     const size_t PF = (size_t)h->NC * h->Q, PS = (size_t)h->HP;
     const size_t nplanes = PF + PS, ib = raw ? sb : 8;
-    std::vector<unsigned char> dev((PF + PS) * M * sb, 0);
+    // raw: the stored bytes are copied as they are; otherwise the FP64 values
+    // are laid out in the chunked order and encoded on the device by the same
+    // store the step kernels use
+    const size_t eb = raw ? sb : 8;
+    std::vector<unsigned char> dev((PF + PS) * M * eb, 0);
     const Ctx c = make_ctx(h);
     for (auto& sm : h->smp) {
         const size_t N = (size_t)sm.N;
         const unsigned char* in = (const unsigned char*)src + nplanes * (size_t)sm.dbase * ib;
         for (size_t j = 0; j < nplanes; ++j) {
             const bool flow = j < PF;
-            unsigned char* dstp = flow ? dev.data() : dev.data() + PF * M * sb;
+            unsigned char* dstp = flow ? dev.data() : dev.data() + PF * M * eb;
             const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
-            const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
-            const float shift = flow ? shift_f32(c, s, i) : 0.0f;
             for (size_t k = 0; k < (size_t)sm.nf; ++k) {
                 const size_t q = blk_index(P, jj, (size_t)sm.kbase + k);
                 const size_t o = j * N + sm.pos[k];
-                if (raw) {
-                    memcpy(dstp + q * sb, in + o * sb, sb);
-                    continue;
-                }
-                const double v = ((const double*)in)[o];
-                switch (h->p.storage) {
-                    case MCLBM_F64: ((double*)dstp)[q] = v; break;
-                    case MCLBM_F32: ((float*)dstp)[q] = (float)v; break;
-                    case MCLBM_F16_SHIFT: ((uint16_t*)dstp)[q] = float_to_half_rne((float)v - shift); break;
-                    default: ((uint16_t*)dstp)[q] = float_to_bf16_rne_h((float)v - shift); break;
-                }
+                memcpy(dstp + q * eb, in + o * eb, eb);
             }
         }
     }
-    HIPCHK(h, hipMemcpyAsync(h->fA, dev.data(), PF * M * sb, hipMemcpyHostToDevice, h->stream));
-    if (PS) HIPCHK(h, hipMemcpyAsync(h->hA, dev.data() + PF * M * sb, PS * M * sb, hipMemcpyHostToDevice, h->stream));
+    if (raw) {
+        HIPCHK(h, hipMemcpyAsync(h->fA, dev.data(), PF * M * sb, hipMemcpyHostToDevice, h->stream));
+        if (PS)
+            HIPCHK(h, hipMemcpyAsync(h->hA, dev.data() + PF * M * sb, PS * M * sb, hipMemcpyHostToDevice, h->stream));
+    } else {
+        // pieces of at most the staging capacity, FP64 in, storage format out
+        const long long cap = (long long)((size_t)(h->NC + 4) * (size_t)h->Ntot);
+        const double* hv = (const double*)dev.data();
+        for (int arr = 0; arr < (PS ? 2 : 1); ++arr) {
+            const long long tot = (long long)((arr ? PS : PF) * M);
+            const double* base = hv + (arr ? PF * M : 0);
+            void* dst = arr ? h->hA : h->fA;
+            for (long long q0 = 0; q0 < tot; q0 += cap) {
+                const long long cnt = std::min(cap, tot - q0);
+                HIPCHK(h, hipMemcpyAsync(h->stage, base + q0, (size_t)cnt * 8, hipMemcpyHostToDevice, h->stream));
+                HIPCHK(h, k_encode_planes(c, h->stage, dst, q0, cnt, (int)(arr ? PS : PF), arr ? 0 : 1));
+            }
+        }
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     // a new state for every sample: convergence flags (frozen samples would
     // otherwise keep a stale mirror in B) and the residual snapshot start over

@@ -450,6 +450,33 @@ __global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R>
 }
 
 // ---------------------------------------------------------------------------
+// encoding of caller-supplied FP64 populations into the storage format, with
+// the same store the step kernels use: elements q0 .. q0 + cnt - 1 of a
+// chunked array of P planes; in a flow array (flow = 1) plane j is component
+// j / Q, direction j % Q and carries the storage shift of that pair; solute
+// planes are stored unshifted.  The value is rounded to the arithmetic type
+// first, then shifted and rounded to the stored type.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ void __launch_bounds__(256) k_encode(Phys<typename Store<ST>::R> P, const double* __restrict__ src,
+                                                typename Store<ST>::T* __restrict__ dst, long long q0, long long cnt,
+                                                int planes, int flow) {
+    using S = Store<ST>;
+    using R = typename S::R;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const long long q = q0 + t;
+    const int j = (int)((q >> 6) % planes);
+    const R v = (R)src[t];
+    if (flow) {
+        const int s = j / Lat<LAT>::Q, i = j % Lat<LAT>::Q;
+        S::store(dst + q, v, (ST >= ST_F16S) ? P.sh[s][i] : R(0));
+    } else {
+        S::store_plain(dst + q, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // particle deposition (sec:particle_deposition, eq:surface_deposition): after
 // a step, every fluid node with a solid flow-lattice neighbour adds DP times
 // its particle concentration (the reacting solute species: the sum of its
@@ -751,6 +778,16 @@ static hipError_t deposit_t(const Ctx& c, double* dep, double DP, int* count) {
     return hipGetLastError();
 }
 
+template <int LAT, int ST, int NC>
+static hipError_t encode_t(const Ctx& c, const double* src, void* dst, long long q0, long long cnt, int planes,
+                           int flow) {
+    if (cnt <= 0) return hipSuccess;
+    auto P = make_phys<SR<ST>>(c);
+    hipLaunchKernelGGL((k_encode<LAT, ST>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c.stream, P, src,
+                       (STT<ST>*)dst, q0, cnt, planes, flow);
+    return hipGetLastError();
+}
+
 #define MCLBM_DISPATCH(FN, ...)                                \
     do {                                                       \
         const int key = c.lat * 100 + c.st * 10 + c.nc;        \
@@ -781,6 +818,10 @@ hipError_t k_init(const Ctx& c, const double* rho, const double* u, const double
 hipError_t k_step(const Ctx& c) { MCLBM_DISPATCH(step_t, c); }
 hipError_t k_moments(const Ctx& c, double* rho, double* u, double* C) { MCLBM_DISPATCH(moments_t, c, rho, u, C); }
 hipError_t k_monitor(const Ctx& c, int have_snapshot) { MCLBM_DISPATCH(monitor_t, c, have_snapshot); }
+hipError_t k_encode_planes(const Ctx& c, const double* src, void* dst, long long q0, long long cnt, int planes,
+                          int flow) {
+    MCLBM_DISPATCH(encode_t, c, src, dst, q0, cnt, planes, flow);
+}
 hipError_t k_deposit_step(const Ctx& c, double* dep, double DP, int* count) {
     MCLBM_DISPATCH(deposit_t, c, dep, DP, count);
 }

@@ -64,6 +64,11 @@ hipError_t k_init(const Ctx& c, const double* rho, const double* u, const double
 hipError_t k_step(const Ctx& c);
 hipError_t k_moments(const Ctx& c, double* rho, double* u, double* C);
 hipError_t k_monitor(const Ctx& c, int have_snapshot);
+// FP64 values src[0 .. cnt-1] stored into elements q0 .. q0 + cnt - 1 of the
+// chunked array dst of `planes` planes with the step kernels' encoder (flow = 1:
+// a flow array with per-plane storage shifts; 0: unshifted solute planes)
+hipError_t k_encode_planes(const Ctx& c, const double* src, void* dst, long long q0, long long cnt, int planes,
+                          int flow);
 // particle deposition after a step: dep[k] += DP * C at fluid nodes with a solid
 // neighbour; *count (zeroed by the caller) receives the nodes whose deposit exceeds 1
 hipError_t k_deposit_step(const Ctx& c, double* dep, double DP, int* count);
