@@ -50,6 +50,19 @@ size_t wn_wgrad_workspace_bytes(int n, int d, int h, int w, int ci, int co, int 
 int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w, int ci, int co, int k, float* dW,
                     void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same weight
+ * gradient as wn_conv3d_wgrad, with the chunk partial sums kept in a static
+ * device array of wn_wgrad_noalloc_max_bytes() bytes (40 MiB) that the
+ * library owns, one copy per GPU, held until the process ends.  Calls no
+ * allocating routine.  Returns -1 (and a message) for a shape whose
+ * wn_wgrad_workspace_bytes() exceeds that size, -3 for a HIP error.  All
+ * calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams or host threads) race and must be serialised by the caller. */
+size_t wn_wgrad_noalloc_max_bytes(void);
+int wn_conv3d_wgrad_noalloc(const float* x, const float* dy, int n, int d, int h, int w, int ci, int co, int k,
+                            float* dW, void* stream);
+
 /* Workspace bytes needed by wn_bias_grad for V voxels and co channels. */
 size_t wn_bias_grad_workspace_bytes(long long V, int co);
 

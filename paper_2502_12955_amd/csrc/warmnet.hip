@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "warmnet.h"
@@ -906,6 +907,64 @@ int wn_conv3d_wgrad(const float* x, const float* dy, int n, int d, int h, int w,
     hipLaunchKernelGGL(sum_chunks, dim3((unsigned)((nw + 15) / 16)), dim3(256), 0, (hipStream_t)stream,
                        (const float*)workspace, pl.nchunk, nw, dW);
     return hip_result("conv_wgrad");
+}
+
+// ---------------------------------------------------------------------------
+// no-allocation weight gradient: the chunk partial sums live in a file-scope
+// device array instead of a caller workspace.  Each GPU holds its own copy of
+// the array; its device address is looked up once per device on the first
+// call made with that device current and kept in scratch_ptr[].  Every call on
+// one GPU reuses that GPU's array, so calls that overlap on one GPU (other
+// streams or threads) race on it.  Every partial that sum_chunks reads is
+// written first by the same call, so nothing needs clearing.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+namespace {
+constexpr size_t kScratchBytes = (size_t)40 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+void* scratch_ptr[kMaxDevices];
+std::mutex scratch_mu;
+
+int scratch_for_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return err(-3, (std::string("hipGetDevice: ") + hipGetErrorString(e)).c_str());
+    if (dev < 0 || dev >= kMaxDevices) return err(-1, "wn_conv3d_wgrad_noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return err(-3, (std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)).c_str());
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return 0;
+}
+}  // namespace
+extern "C" {
+
+size_t wn_wgrad_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int wn_conv3d_wgrad_noalloc(const float* x, const float* dy, int n, int d, int h, int w, int ci, int co, int k,
+                            float* dW, void* stream) {
+    if (!x || !dy || !dW || (k != 1 && k != 3) || !shape_ok(n, d, h, w, ci) || !shape_ok(n, d, h, w, co))
+        return err(-1, "wn_conv3d_wgrad_noalloc: bad arguments");
+    const size_t need = wn_wgrad_workspace_bytes(n, d, h, w, ci, co, k);
+    if (need > kScratchBytes)
+        return err(-1, ("wn_conv3d_wgrad_noalloc: this shape needs " + std::to_string(need) +
+                        " bytes of partial sums, more than the " + std::to_string(kScratchBytes) +
+                        "-byte static scratch; use wn_conv3d_wgrad with a workspace")
+                           .c_str());
+    void* ws = nullptr;
+    if (int rc = scratch_for_current_device(&ws)) return rc;
+    const WgradPlan pl = wgrad_plan(n, d, h, w, ci, co, k);
+    launch_wgrad(pl, x, ci, dy, co, Grid3{n, d, h, w}, k, (float*)ws, (hipStream_t)stream);
+    const long long nw = (long long)co * k * k * k * ci;
+    hipLaunchKernelGGL(sum_chunks, dim3((unsigned)((nw + 15) / 16)), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)ws, pl.nchunk, nw, dW);
+    return hip_result("conv_wgrad_noalloc");
 }
 
 size_t wn_bias_grad_workspace_bytes(long long V, int co) {

@@ -33,6 +33,9 @@ def load(path: str = LIB_PATH):
     lib.wn_wgrad_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, i32]
     lib.wn_wgrad_workspace_bytes.restype = sz
     lib.wn_conv3d_wgrad.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    lib.wn_conv3d_wgrad_noalloc.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp]
+    lib.wn_wgrad_noalloc_max_bytes.argtypes = []
+    lib.wn_wgrad_noalloc_max_bytes.restype = sz
     lib.wn_bias_grad.argtypes = [vp, i64, i32, vp, vp, sz, vp]
     lib.wn_bias_grad_workspace_bytes.argtypes = [i64, i32]
     lib.wn_bias_grad_workspace_bytes.restype = sz
@@ -95,6 +98,13 @@ def conv3d_wgrad(x, dy, k, dW, ws):
     n, d, h, w, ci = x.shape
     co = dy.shape[-1]
     _ok(load().wn_conv3d_wgrad(_p(x), _p(dy), n, d, h, w, ci, co, k, _p(dW), _p(ws), ws.numel() * 4, _stream()))
+
+
+def conv3d_wgrad_noalloc(x, dy, k, dW):
+    """Weight gradient without a workspace (the library's static scratch)."""
+    n, d, h, w, ci = x.shape
+    co = dy.shape[-1]
+    _ok(load().wn_conv3d_wgrad_noalloc(_p(x), _p(dy), n, d, h, w, ci, co, k, _p(dW), _stream()))
 
 
 def bias_grad_workspace_bytes(V, co):
