@@ -262,6 +262,15 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
  * with the same arithmetic, so results do not depend on the launch shape. */
 int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks);
 
+/* Addressing of the collide pass.  flat = 0 (default): raw buffer
+ * instructions with 32-bit byte offsets whenever every population array and
+ * each sample's dense fields are below 4 GiB, flat 64-bit addresses
+ * otherwise; flat = 1: flat 64-bit addresses always.  Both forms store the
+ * same values to the same elements (results are bit-identical); the buffer
+ * form issues fewer instructions.  Drops captured graphs.  EINVAL for other
+ * values. */
+int mclbm_set_addressing(mclbm_handle* h, int32_t flat);
+
 /* Time the step kernels over a set of launch shapes and keep the fastest.
  * Candidates: block_threads 64, 128, 256 crossed with grid_blocks 0 (one
  * pass) and persistent grids of 8, 16 and 32 wavefronts per compute unit.
@@ -313,6 +322,19 @@ int mclbm_get_step(mclbm_handle* h, int64_t* step);
 int mclbm_synchronize(mclbm_handle* h);
 
 /* Free library-owned objects (never the caller's arena).  NULL is a no-op. */
+/* Practical HBM bandwidth of this device, measured with streaming kernels
+ * (not part of the method: the ceiling the step kernels are compared with).
+ * kind 0: read `bytes` of `a` (non-temporal 16-byte loads; `b` >= 4 KiB of
+ * device memory receives nothing in practice); 1: write `bytes` to `a`;
+ * 2: copy `bytes` from `a` to `b` (counted as read + write).  Grid:
+ * blocks_per_cu x the device's CU count, 256 threads.  Runs iters + 1
+ * passes on `stream` (the first untimed), synchronises, and returns the best
+ * pass in *best_gbps (1e9 bytes/s).  `bytes` >= 4096 and a multiple of 16;
+ * buffers are device memory owned by the caller.  EINVAL for bad arguments,
+ * EHIP for a runtime error. */
+int mclbm_hbm_probe(int32_t kind, void* a, void* b, size_t bytes, int32_t blocks_per_cu, int32_t iters,
+                    void* stream, double* best_gbps);
+
 void mclbm_destroy(mclbm_handle* h);
 
 /* Message of the last failed call on h ("" if none); h == NULL gives the

@@ -117,6 +117,7 @@ struct mclbm_handle {
     double mon[16];
     double rhobar[2] = {0, 0};
     int block = 256, grid = 0;
+    int flat = 0;                   // 1: flat 64-bit addressing in the collide pass
     // graph replay of monitor_every steps (one per A/B parity)
     bool use_graph = false;
     hipStream_t gstream = nullptr;
@@ -359,6 +360,9 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     Ctx c = base_ctx(h->p);
     c.nsamples = h->S;
     c.Ntot = h->Ntot;
+    c.flat = h->flat;
+    c.max_sample_nodes = 0;
+    for (const auto& sm : h->smp) c.max_sample_nodes = std::max(c.max_sample_nodes, sm.N);
     c.nchunks = h->nchunks;
     c.rhobar[0] = h->rhobar[0];
     c.rhobar[1] = h->rhobar[1];
@@ -1299,6 +1303,14 @@ int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks
     drop_graphs(h);
     h->block = block_threads;
     h->grid = grid_blocks;
+    return MCLBM_OK;
+}
+
+int mclbm_set_addressing(mclbm_handle* h, int32_t flat) {
+    if (!h) return MCLBM_EINVAL;
+    if (flat != 0 && flat != 1) return fail(h, MCLBM_EINVAL, "flat must be 0 or 1");
+    drop_graphs(h);
+    h->flat = flat;
     return MCLBM_OK;
 }
 

@@ -56,6 +56,107 @@ __device__ __forceinline__ T* blk(T* base, int P, int j, unsigned k) {
     return base + ((size_t)(k >> 6) * (size_t)P + (size_t)j) * 64u + (k & 63u);
 }
 
+// ---------------------------------------------------------------------------
+// Population access of the collide pass, in two addressing forms with the
+// same element layout (blk above):
+//   GlobalIO: 64-bit flat addresses per element.
+//   BufIO:    raw buffer instructions: a 32-bit byte offset per node and
+//             the plane offset as a wave-uniform scalar, so a store costs
+//             no 64-bit address arithmetic per lane.  Usable while every
+//             array is below 4 GiB (the host checks this).
+// Both store exactly the same values to the same elements.
+// ---------------------------------------------------------------------------
+template <int ST, int PF, int HP>
+struct GlobalIO {
+    using S = Store<ST>;
+    using R = typename S::R;
+    using T = typename S::T;
+    T* __restrict__ fB;
+    const T* __restrict__ hA;
+    T* __restrict__ hB;
+    __device__ __forceinline__ void fstore(int j, unsigned kd, R v, R shift) const { S::store(blk(fB, PF, j, kd), v, shift); }
+    __device__ __forceinline__ R hload(int q, unsigned k) const { return S::load_plain(blk(hA, HP, q, k)); }
+    __device__ __forceinline__ void hstore(int q, unsigned kd, R v) const { S::store_plain(blk(hB, HP, q, kd), v); }
+};
+
+// raw buffer resource: base, no stride, num_records = bytes, gfx9 data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int ST>
+struct BufBits;
+template <>
+struct BufBits<ST_F64> {
+    template <int AUX>
+    __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        auto b = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, AUX);
+        uint64_t u = ((uint64_t)b[1] << 32) | b[0];
+        return __builtin_bit_cast(double, u);
+    }
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, double v, uint32_t vo, uint32_t so) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        typedef unsigned v2u __attribute__((ext_vector_type(2)));
+        v2u b;
+        b[0] = (unsigned)u;
+        b[1] = (unsigned)(u >> 32);
+        __builtin_amdgcn_raw_buffer_store_b64(b, r, vo, so, 0);
+    }
+};
+template <>
+struct BufBits<ST_F32> {
+    template <int AUX>
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, AUX));
+    }
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, uint32_t vo, uint32_t so) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, so, 0);
+    }
+};
+template <>
+struct BufBits<ST_F16S> {
+    template <int AUX>
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, AUX)));
+    }
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, uint32_t vo, uint32_t so) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, vo, so, 0);
+    }
+};
+template <>
+struct BufBits<ST_BF16S> {
+    template <int AUX>
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return bf16_to_float(__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, AUX));
+    }
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, uint32_t vo, uint32_t so) {
+        __builtin_amdgcn_raw_buffer_store_b16(float_to_bf16_rne(v), r, vo, so, 0);
+    }
+};
+
+template <int ST, int PF, int HP>
+struct BufIO {
+    using S = Store<ST>;
+    using R = typename S::R;
+    static constexpr uint32_t E = sizeof(typename S::T), PS = 64 * E;   // element and plane bytes
+    __amdgpu_buffer_rsrc_t fB, hA, hB;
+    // byte offset of (plane 0, node k) in an array of P planes
+    template <int P>
+    __device__ __forceinline__ static uint32_t node_off(unsigned k) {
+        // chunk numbers stay below 2^24 (fluid indices below 2^30), so a 24-bit multiply suffices
+        return (__umul24(k >> 6, (uint32_t)(P * 64)) + (k & 63u)) * E;
+    }
+    __device__ __forceinline__ void fstore(int j, unsigned kd, R v, R shift) const {
+        BufBits<ST>::st(fB, v - shift, node_off<PF>(kd) + (uint32_t)j * PS, 0);
+    }
+    __device__ __forceinline__ R hload(int q, unsigned k) const {
+        return BufBits<ST>::template ld<2>(hA, node_off<HP>(k), (uint32_t)q * PS);
+    }
+    __device__ __forceinline__ void hstore(int q, unsigned kd, R v) const {
+        BufBits<ST>::st(hB, v, node_off<HP>(kd), (uint32_t)q * PS);
+    }
+};
+
 struct Geo {
     const SampleDev* smp;
     const int* chunk_sample;
@@ -184,13 +285,11 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
 //   dest(i): fluid index of x + c_i (called only where that node is fluid)
 //   x, nx: x coordinate of the node and the box edge (solute seams)
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC, int FC, int PR, int KF, class PsiNb, class Dest>
+template <int LAT, int ST, int NC, int FC, int PR, int KF, class PsiNb, class Dest, class IO>
 __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& P,
                                              const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q], unsigned k,
                                              uint32_t lw, int x, int nx, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q],
-                                             PsiNb psi_nb, Dest dest, typename Store<ST>::T* __restrict__ fB,
-                                             const typename Store<ST>::T* __restrict__ hA,
-                                             typename Store<ST>::T* __restrict__ hB) {
+                                             PsiNb psi_nb, Dest dest, const IO& io) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
@@ -204,16 +303,16 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
         if (i != 0 && !bb) kd = dest(i);
         const int dir = bb ? L::opp[i] : i;
 #pragma unroll
-        for (int s = 0; s < NC; ++s) S::store(blk(fB, PF, s * Q + dir, kd), f[s][i], sh[s][i]);  // w_i = w_opp(i)
+        for (int s = 0; s < NC; ++s) io.fstore(s * Q + dir, kd, f[s][i], sh[s][i]);  // w_i = w_opp(i)
     }
     if (P.solute) {
         // loaded only now: fewer registers live through the flow part
         constexpr int HP = QS * (1 + PR);   // solute planes per node (= P.hplanes)
         R h[QS];
 #pragma unroll
-        for (int q = 0; q < QS; ++q) h[q] = S::load_plain(blk(hA, HP, q, k));
+        for (int q = 0; q < QS; ++q) h[q] = io.hload(q, k);
         solute_collide<LAT, R>(P, h, u, P.inv_tau_d);
-        S::store_plain(blk(hB, HP, 0, k), h[0]);
+        io.hstore(0, k, h[0]);
         const bool seam_mode = (P.solute == 2);
 #pragma unroll
         for (int d = 1; d < QS; ++d) {
@@ -221,15 +320,15 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
             if (!seam && !(lw & (1u << L::opp[d]))) {
                 const unsigned kd = dest(d);
-                S::store_plain(blk(hB, HP, d, kd), h[d]);
+                io.hstore(d, kd, h[d]);
                 if (lw & (1u << (L::HOP_SHIFT + d))) {
                     const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
-                    S::store_plain(blk(hB, HP, L::opp[d], kd), R(2) * P.Ws * Cb - h[d]);
+                    io.hstore(L::opp[d], kd, R(2) * P.Ws * Cb - h[d]);
                 }
                 if (seam_mode && d == L::SXM && x == 1)
-                    S::store_plain(blk(hB, HP, L::SXP, kd), R(2) * P.Ws * P.C_in - h[d]);
+                    io.hstore(L::SXP, kd, R(2) * P.Ws * P.C_in - h[d]);
             }
-            if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, HP, d, k), h[d]);
+            if (seam_mode && d == L::SXM && x == nx - 1) io.hstore(d, k, h[d]);
         }
         if (PR) {
             // the product (planes QS..2QS-1): same collision with its own tau, same
@@ -238,25 +337,25 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             // convention: h2_out = h2_in + k tau2 / (tau2 - 1/2) C_b
             R h2[QS];
 #pragma unroll
-            for (int q = 0; q < QS; ++q) h2[q] = S::load_plain(blk(hA, HP, QS + q, k));
+            for (int q = 0; q < QS; ++q) h2[q] = io.hload(QS + q, k);
             solute_collide<LAT, R>(P, h2, u, P.inv_tau_d2);
-            S::store_plain(blk(hB, HP, QS, k), h2[0]);
+            io.hstore(QS, k, h2[0]);
 #pragma unroll
             for (int d = 1; d < QS; ++d) {
                 const int dx = L::cx[d];
                 const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
                 if (!seam && !(lw & (1u << L::opp[d]))) {
                     const unsigned kd = dest(d);
-                    S::store_plain(blk(hB, HP, QS + d, kd), h2[d]);
+                    io.hstore(QS + d, kd, h2[d]);
                     if (lw & (1u << (L::HOP_SHIFT + d))) {
                         const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
                         const R gain = KF ? P.kfield[P.kstride + kd] : P.prod_gain;
-                        S::store_plain(blk(hB, HP, QS + L::opp[d], kd), h2[d] + gain * Cb);
+                        io.hstore(QS + L::opp[d], kd, h2[d] + gain * Cb);
                     }
                     if (seam_mode && d == L::SXM && x == 1)
-                        S::store_plain(blk(hB, HP, QS + L::SXP, kd), R(2) * P.Ws * P.C_in2 - h2[d]);
+                        io.hstore(QS + L::SXP, kd, R(2) * P.Ws * P.C_in2 - h2[d]);
                 }
-                if (seam_mode && d == L::SXM && x == nx - 1) S::store_plain(blk(hB, HP, QS + d, k), h2[d]);
+                if (seam_mode && d == L::SXM && x == nx - 1) io.hstore(QS + d, k, h2[d]);
             }
         }
     }
@@ -267,18 +366,20 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
 // ---------------------------------------------------------------------------
 // FC: forcing scheme (0 Guo, 1 Shan-Chen); SV: solute variant, bit 0 the
 // product species, bit 1 the per-node rate field (each compiled in or out, so
-// the plain path keeps its registers and schedule)
-template <int LAT, int ST, int NC, int FC, int SV>
+// the plain path keeps its registers and schedule); BUF: buffer addressing
+// (BufIO, every array below 4 GiB) or flat addresses (GlobalIO)
+template <int LAT, int ST, int NC, int FC, int SV, int BUF>
 __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, Geo g,
                                                  const typename Store<ST>::T* __restrict__ fA,
                                                  typename Store<ST>::T* __restrict__ fB,
                                                  const typename Store<ST>::T* __restrict__ hA,
                                                  typename Store<ST>::T* __restrict__ hB,
-                                                 const typename Store<ST>::R* __restrict__ psi) {
+                                                 const typename Store<ST>::R* __restrict__ psi,
+                                                 uint32_t fbytes, uint32_t hbytes) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    constexpr int Q = L::Q, PF = NC * Q;
+    constexpr int Q = L::Q, PF = NC * Q, QS = L::QS, HP = QS * (1 + (SV & 1));
     R sh[NC][Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
@@ -290,20 +391,50 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
         const unsigned n = g.pos[k];
         const uint32_t lw = g.links[k];
         R f[NC][Q];
+        if constexpr (BUF) {
+            const __amdgpu_buffer_rsrc_t fr = make_rsrc(fA, fbytes);
+            const uint32_t vo = BufIO<ST, PF, HP>::template node_off<PF>(k);
 #pragma unroll
-        for (int s = 0; s < NC; ++s)
+            for (int s = 0; s < NC; ++s)
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
+                for (int i = 0; i < Q; ++i) {
+                    const R v = BufBits<ST>::template ld<2>(fr, vo, (uint32_t)(s * Q + i) * BufIO<ST, PF, HP>::PS);
+                    f[s][i] = (ST >= ST_F16S) ? v + sh[s][i] : v;
+                }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
+        }
         const SampleDev sd = sample_of(g, ch);
         int x, y, z;
         coords(n, sd.nx, sd.ny, x, y, z);
         const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
         const int* mp = g.map + sd.dbase;
         const R* ps = psi + (size_t)NC * sd.dbase;
-
-        auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
-        auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
-        collide_push<LAT, ST, NC, FC, (SV & 1), (SV >> 1)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, fB, hA, hB);
+        if constexpr (BUF) {
+            const __amdgpu_buffer_rsrc_t mr = make_rsrc(mp, (uint32_t)sd.N * 4u);
+            const __amdgpu_buffer_rsrc_t pr = make_rsrc(ps, (uint32_t)sd.N * (uint32_t)(NC * sizeof(R)));
+            auto psi_nb = [&](int t, int i) -> R {
+                const uint32_t o = nb.at(L::cx[i], L::cy[i], L::cz[i]) * (uint32_t)(NC * sizeof(R)) + t * sizeof(R);
+                if constexpr (sizeof(R) == 8) return BufBits<ST_F64>::template ld<0>(pr, o, 0);
+                else return BufBits<ST_F32>::template ld<0>(pr, o, 0);
+            };
+            auto dest = [&](int i) -> unsigned {
+                return __builtin_amdgcn_raw_buffer_load_b32(mr, nb.at(L::cx[i], L::cy[i], L::cz[i]) * 4u, 0, 0);
+            };
+            BufIO<ST, PF, HP> io;
+            io.fB = make_rsrc(fB, fbytes);
+            io.hA = make_rsrc(hA, hbytes);
+            io.hB = make_rsrc(hB, hbytes);
+            collide_push<LAT, ST, NC, FC, (SV & 1), (SV >> 1)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, io);
+        } else {
+            auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
+            auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
+            const GlobalIO<ST, PF, HP> io{fB, hA, hB};
+            collide_push<LAT, ST, NC, FC, (SV & 1), (SV >> 1)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, io);
+        }
     });
 }
 
@@ -706,8 +837,22 @@ static hipError_t step_t(const Ctx& c) {
     const STT<ST>* hA = (const STT<ST>*)c.hA;
     STT<ST>* hB = (STT<ST>*)c.hB;
     const SR<ST>* psi = (const SR<ST>*)c.psi;
-#define MCLBM_COLLIDE(FC, SV)                                                                              \
-    hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, hA, hB, psi)
+    // buffer addressing needs every population array, and each sample's map
+    // and pseudo-potential field, below 4 GiB (32-bit byte offsets)
+    const size_t fbytes = (size_t)c.nchunks * 64 * NC * Lat<LAT>::Q * sizeof(STT<ST>);
+    const size_t hbytes = (size_t)c.nchunks * 64 * (size_t)(c.hplanes > 0 ? c.hplanes : 1) * sizeof(STT<ST>);
+    const bool buf = !c.flat && fbytes < (1ull << 32) && hbytes < (1ull << 32) &&
+                     (size_t)c.max_sample_nodes * NC * sizeof(SR<ST>) < (1ull << 32);
+    const uint32_t fb32 = (uint32_t)(buf ? fbytes : 0), hb32 = (uint32_t)(buf ? hbytes : 0);
+#define MCLBM_COLLIDE(FC, SV)                                                                                    \
+    do {                                                                                                         \
+        if (buf)                                                                                                 \
+            hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV, 1>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, \
+                               hA, hB, psi, fb32, hb32);                                                         \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV, 0>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, \
+                               hA, hB, psi, fb32, hb32);                                                         \
+    } while (0)
     const int sv = (c.product ? 1 : 0) + (c.kfield ? 2 : 0);
     switch (c.forcing * 4 + sv) {
         case 0: MCLBM_COLLIDE(0, 0); break;

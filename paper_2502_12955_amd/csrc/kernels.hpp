@@ -23,6 +23,7 @@ struct Ctx {
     int lat, st, nc;            // lattice (0 D2Q9, 1 D3Q19), storage, components
     int nsamples;
     long long Ntot;             // box nodes of all samples
+    long long max_sample_nodes; // box nodes of the largest sample
     long long nchunks;          // 64-node chunks of the fluid numbering (with per-sample padding)
     int forcing, solute;
     double tau[2], G[2][2], Gads[2], rho0, accel[3];
@@ -48,6 +49,7 @@ struct Ctx {
     double* result;             // [nsamples][16] per-sample monitor sums
     int block;                  // threads per block of the step kernels (64, 128, 256)
     int grid;                   // persistent grid (blocks, multiple of 8); 0 = one pass over the chunks
+    int flat;                   // 1: flat 64-bit addresses in the collide pass even where buffer offsets fit
 };
 
 constexpr int MON_NV = 11;      // values reduced per monitor

@@ -99,7 +99,7 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
            "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_get_deposit", "mclbm_set_deposit", "mclbm_destroy",
-           "mclbm_last_error")
+           "mclbm_last_error", "mclbm_hbm_probe", "mclbm_set_addressing")
 
 
 def load(path: str = LIB_PATH):
@@ -130,6 +130,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_run_to_residual.argtypes = [vp, dbl, i64, ct.POINTER(i64)]
     lib.mclbm_set_launch.argtypes = [vp, i32, i32]
     lib.mclbm_set_graph.argtypes = [vp, i32]
+    lib.mclbm_set_addressing.argtypes = [vp, i32]
     lib.mclbm_required_bytes_batch.argtypes = [P, i32, ct.POINTER(sz)]
     lib.mclbm_init_batch.argtypes = [P, i32, vp, sz, vp, ct.POINTER(vp)]
     lib.mclbm_get_sample_monitors.argtypes = [vp, i32, vp]
@@ -137,6 +138,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_synchronize.argtypes = [vp]
     lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp, i32,
                                    ct.POINTER(i32)]
+    lib.mclbm_hbm_probe.argtypes = [i32, vp, vp, sz, i32, i32, vp, ct.POINTER(dbl)]
     lib.mclbm_destroy.argtypes = [vp]
     lib.mclbm_destroy.restype = None
     lib.mclbm_last_error.argtypes = [vp]
@@ -146,6 +148,22 @@ def load(path: str = LIB_PATH):
             getattr(lib, name).restype = ct.c_int
     _lib = lib
     return lib
+
+
+def hbm_probe(kind: str, nbytes: int = 2 << 30, blocks_per_cu: int = 8, iters: int = 5) -> float:
+    """Best GB/s of the library's streaming read / write / copy kernel over
+    ``nbytes`` (device buffers allocated here with torch)."""
+    import torch
+
+    k = {"read": 0, "write": 1, "copy": 2}[kind]
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty(nbytes // 4 if k == 2 else 4096, dtype=torch.float32, device="cuda")
+    out = ct.c_double()
+    stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(load().mclbm_hbm_probe(k, ct.c_void_p(a.data_ptr()), ct.c_void_p(b.data_ptr()), nbytes, blocks_per_cu,
+                                  iters, stream, ct.byref(out)))
+    del a, b
+    return out.value
 
 
 def last_error(handle=None) -> str:
@@ -285,6 +303,10 @@ def set_launch(h, block_threads=256, grid_blocks=0):
     _check(load().mclbm_set_launch(h, int(block_threads), int(grid_blocks)), h)
 
 
+def set_addressing(h, flat: bool):
+    _check(load().mclbm_set_addressing(h, int(bool(flat))), h)
+
+
 def autotune(h, trial_steps=20):
     """Native launch-shape tuner; returns (block, grid, ms_per_step, table rows (block, grid, ms))."""
     b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32()
@@ -421,6 +443,9 @@ class Lattice:
 
     def set_graph(self, enable=True):
         set_graph(self.h, enable)
+
+    def set_addressing(self, flat=False):
+        set_addressing(self.h, flat)
 
 
 

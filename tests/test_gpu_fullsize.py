@@ -87,4 +87,10 @@ def test_full_size_every_autotune_shape_is_bit_identical(workload):
             ref = pops
         else:
             assert np.array_equal(pops, ref), (blk, grid)
+    # flat 64-bit addressing instead of buffer offsets: same values
+    lat.set_addressing(flat=True)
+    lat.set_launch(256, 0)
+    lat.init_fields(rho, None, C)
+    lat.step(2)
+    assert np.array_equal(lat.populations(raw=True), ref)
     lat.close()
