@@ -327,3 +327,84 @@ def residual(a_now, a_prev, fluid):
     if den == 0.0:
         return 0.0 if num == 0.0 else float("inf")
     return (num / den) ** 0.5
+
+
+# ----------------------------------------------------------------------------- conjugate heat transfer
+class _Thermal(ct.Structure):
+    _fields_ = [("tau_ef", ct.c_double), ("tau_es", ct.c_double), ("rhocp_f", ct.c_double),
+                ("rhocp_s", ct.c_double), ("h_r", ct.c_double), ("A", ct.c_double), ("E_over_R", ct.c_double),
+                ("T_tol", ct.c_double), ("T_maxit", ct.c_int32), ("pad_", ct.c_int32)]
+
+
+THERMAL_KEYS = ("tau_ef", "tau_es", "rhocp_f", "rhocp_s", "h_r", "arr_A", "arr_E_over_R", "T_tol", "T_maxit")
+
+
+def _thermal(p: dict) -> _Thermal:
+    t = _Thermal()
+    t.tau_ef = float(p.get("tau_ef", 1.0))
+    t.tau_es = float(p.get("tau_es", 1.0))
+    t.rhocp_f = float(p.get("rhocp_f", 1.0))
+    t.rhocp_s = float(p.get("rhocp_s", 1.0))
+    t.h_r = float(p.get("h_r", 0.0))
+    t.A = float(p.get("arr_A", 0.0))
+    t.E_over_R = float(p.get("arr_E_over_R", 0.0))
+    t.T_tol = float(p.get("T_tol", 1e-14))
+    t.T_maxit = int(p.get("T_maxit", 100))
+    return t
+
+
+def thermal_nodes(p, mask):
+    """(holds_solid, interface) node classes of the conjugate heat transfer:
+    solid and interface nodes carry solid energy populations; an interface node is
+    a fluid node with a solid flow-lattice neighbour (Reactive LBM subsection)."""
+    m = np.ascontiguousarray(mask, np.uint8).reshape(-1)
+    N = n_nodes(p)
+    hs = np.zeros(N, np.uint8)
+    it = np.zeros(N, np.uint8)
+    s = _struct(p)
+    _load().orc_thermal_nodes(ct.byref(s), _ptr(m, ct.c_uint8), _ptr(hs, ct.c_uint8), _ptr(it, ct.c_uint8))
+    return hs, it
+
+
+def thermal_init(p, mask, T, u=None):
+    """Energy populations at temperature T [N]: fluid g^eq(rho_f c_p,f T, u)
+    (eq:therpopeq), solid w_i rho_s c_p,s T (eq:therpopeq_solid); returns (g, gs, Ti)."""
+    N = n_nodes(p)
+    Q = _q(p)
+    m = np.ascontiguousarray(mask, np.uint8).reshape(-1)
+    T = np.ascontiguousarray(T, np.float64).reshape(N)
+    up = None if u is None else np.ascontiguousarray(u, np.float64).reshape(3, N)
+    g = np.zeros((Q, N))
+    gs = np.zeros((Q, N))
+    Ti = np.zeros(N)
+    s, t = _struct(p), _thermal(p)
+    _load().orc_thermal_init(ct.byref(s), ct.byref(t), _ptr(m, ct.c_uint8), _ptr(T, ct.c_double),
+                             None if up is None else _ptr(up, ct.c_double), _ptr(g, ct.c_double),
+                             _ptr(gs, ct.c_double), _ptr(Ti, ct.c_double))
+    return g, gs, Ti
+
+
+def step_thermal(p, mask, f, h, g, gs, Ti, nsteps=1):
+    """Advance (f, h, g, gs, Ti) in place by nsteps steps with conjugate heat
+    transfer; returns (iterations, unsettled interface solves, degenerate
+    interface nodes)."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    for a in (f, h, g, gs, Ti):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    stats = np.zeros(3, np.int64)
+    s, t = _struct(p), _thermal(p)
+    _load().orc_step_thermal(ct.byref(s), ct.byref(t), _ptr(m, ct.c_uint8), _ptr(f, ct.c_double),
+                             _ptr(h, ct.c_double), _ptr(g, ct.c_double), _ptr(gs, ct.c_double),
+                             _ptr(Ti, ct.c_double), ct.c_int64(int(nsteps)), _ptr(stats, ct.c_int64))
+    return tuple(int(v) for v in stats)
+
+
+def temperature(p, mask, g, gs):
+    """T [N]: fluid (and interface) nodes E_f / (rho c_p)_f, solid nodes E_s / (rho c_p)_s."""
+    N = n_nodes(p)
+    m = np.ascontiguousarray(mask, np.uint8).reshape(-1)
+    T = np.zeros(N)
+    s, t = _struct(p), _thermal(p)
+    _load().orc_temperature(ct.byref(s), ct.byref(t), _ptr(m, ct.c_uint8), _ptr(g, ct.c_double),
+                            _ptr(gs, ct.c_double), _ptr(T, ct.c_double))
+    return T

@@ -38,6 +38,10 @@
  *   - fluid voxels pinched between two solids along one axis are made solid
  *     before anything else (in inlet/outlet mode the planes beyond x = 0 and
  *     x = nx-1 count as solid for this test).
+ *   - conjugate heat transfer: interface nodes are fluid nodes with a solid
+ *     flow-lattice neighbour and carry both energy distributions; the
+ *     counter-slip conditions are posed per node over its unknown links
+ *     (details with orc_step_thermal below).
  *   - particle deposition: "near the substrate" means a solid neighbour along
  *     any flow-lattice link; the deposit does not remove particles from the
  *     fluid (the paper's update has no sink term); nodes that turn solid lose
@@ -703,4 +707,301 @@ void orc_moments(const orc_params* p, const uint8_t* mask, const double* f, cons
     }
     free(rho);
     free(psi);
+}
+
+/* ===========================================================================
+ * Conjugate heat transfer (Reactive LBM subsection): internal-energy
+ * distributions in the fluid (eq:therpop, eq:therpopeq) and in the solid
+ * (eq:therpop_solid, eq:therpopeq_solid) on the flow lattice, coupled at the
+ * interface by the thermal counter-slip conditions (eq:countSlipFluxCon,
+ * eq:countSlipTempCon) with the reaction heat (eq:reacRate), iterated with
+ * the wet-node reaction (eq:wetnode9) until the interface temperature settles
+ * (the flowchart's C_b - T loop).
+ *
+ * Which nodes carry what:
+ *   - every fluid node carries fluid energy populations g_i;
+ *   - every solid node carries solid energy populations gs_i;
+ *   - an interface node is a fluid node with a solid neighbour along some
+ *     flow-lattice link; it carries both (the paper's double node on the
+ *     interface, the same node the solute's wet-node rule acts on).
+ * Streaming pulls g_i from x - c_i if that node is fluid, gs_i if it carries
+ * solid populations; the remaining populations of an interface node are the
+ * unknowns of the counter-slip conditions:
+ *   M_f = { i : x - c_i solid }            fluid unknowns  g_i  = w_i X_f
+ *   M_s = { i : x - c_i pure fluid }       solid unknowns  gs_i = w_i X_s
+ * (the counter-slip form: unknowns proportional to their weights).  Reading
+ * (ours) of the flat-wall conditions for any voxel interface:
+ *   temperature   (Kn_f + W_f X_f) / (rho c_p)_f = (Kn_s + W_s X_s) / (rho c_p)_s
+ *   heat flux     k_f (W_f' X_f - B_f) = k_s (A_s - W_s' X_s) + Hdot
+ * with Kn the sums of the known populations, W = sum of w_i over the
+ * unknowns, W' and B (A) over the unknowns whose opposite population is
+ * known (B = sum of g_opp(i), A = sum of gs_opp(i)), k = 1 - 1/(2 tau_e),
+ * Hdot = h_r sum over the node's wet solute links of k(T) C_b (eq:reacRate,
+ * eq:wetnode9), k(T) = A exp(-E / (R_u T)).  For a flat wall with normal +y
+ * in D2Q9 (M_f = {2, 5, 6}, M_s = {4, 7, 8}) eliminating X_f gives exactly
+ * the printed eq:unknownpopTempS, and the temperature condition then gives
+ * eq:unknownpopTempF.  Where the flux condition cannot be posed (no unknown
+ * solid population, or every unknown paired with an unknown opposite on both
+ * sides) the temperature condition alone is used, the solid unknowns taking
+ * the local solid equilibrium; such nodes release no reaction heat and are
+ * counted.
+ * ========================================================================= */
+typedef struct {
+    double tau_ef, tau_es;   /* 3 alpha + 1/2 of fluid and solid */
+    double rhocp_f, rhocp_s; /* rho c_p of fluid and solid */
+    double h_r;              /* heat released per unit of O2 consumed */
+    double A, E_over_R;      /* k(T) = A exp(-E_over_R / T) at the interface */
+    double T_tol;            /* relative tolerance of the interface iteration */
+    int32_t T_maxit;         /* its iteration cap */
+    int32_t pad_;
+} orc_thermal;
+
+/* Node classes: holds_solid[n] = 1 for solid and interface nodes,
+ * iface[n] = 1 for interface nodes. */
+void orc_thermal_nodes(const orc_params* p, const uint8_t* mask, uint8_t* holds_solid, uint8_t* iface) {
+    flow_lat L = make_flow(p->lattice);
+    int64_t N = nnodes(p);
+    for (int64_t n = 0; n < N; ++n) {
+        int any = 0;
+        if (!mask[n])
+            for (int i = 1; i < L.Q; ++i)
+                if (mask[nbr_back(p, n, L.c[i])]) any = 1;
+        iface[n] = (uint8_t)any;
+        holds_solid[n] = (uint8_t)(mask[n] || any);
+    }
+}
+
+/* Energy equilibrium of the fluid, eq:therpopeq, with E = rho_f eps_f = sum g:
+ * w_i E [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)]. */
+static double geq_i(const flow_lat* L, int i, double E, const double u[3]) {
+    double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return L->w[i] * E * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+}
+
+/* Initial energy populations at temperature T [N]: fluid g = g^eq(rho_f c_p,f T, u),
+ * solid (and interface) gs = w_i rho_s c_p,s T; Ti = T at every node. */
+void orc_thermal_init(const orc_params* p, const orc_thermal* th, const uint8_t* mask, const double* T,
+                      const double* u, double* g, double* gs, double* Ti) {
+    flow_lat L = make_flow(p->lattice);
+    int64_t N = nnodes(p);
+    uint8_t* hs = (uint8_t*)malloc((size_t)N);
+    uint8_t* itf = (uint8_t*)malloc((size_t)N);
+    orc_thermal_nodes(p, mask, hs, itf);
+    for (int64_t n = 0; n < N; ++n) {
+        double v[3] = {0, 0, 0};
+        if (u) { v[0] = u[n]; v[1] = u[N + n]; v[2] = u[2 * N + n]; }
+        for (int i = 0; i < L.Q; ++i) {
+            g[(int64_t)i * N + n] = mask[n] ? 0.0 : geq_i(&L, i, th->rhocp_f * T[n], v);
+            gs[(int64_t)i * N + n] = hs[n] ? L.w[i] * th->rhocp_s * T[n] : 0.0;
+        }
+        Ti[n] = T[n];
+    }
+    free(hs);
+    free(itf);
+}
+
+/* Counter-slip solve at interface node y (see the block comment above).  g, gs
+ * hold the streamed known populations and receive the unknowns; h (solute,
+ * after streaming) receives the wet-link populations of both species with the
+ * rate at the settled temperature.  Ti[y]: start value in, settled value out.
+ * Returns the iterations used; *degenerate = 1 if the flux condition could not
+ * be posed; *settled = 1 if the tolerance was met. */
+static int interface_solve(const orc_params* p, const orc_thermal* th, const flow_lat* L, const sol_lat* S,
+                           const uint8_t* mask, const uint8_t* hs, const uint32_t* wet, double* g, double* gs,
+                           double* h, double* Ti, int64_t y, int* degenerate, int* settled) {
+    int64_t N = nnodes(p);
+    int Q = L->Q;
+    int mf[19], ms[19];
+    for (int i = 0; i < Q; ++i) {
+        int64_t src = nbr_back(p, y, L->c[i]);
+        mf[i] = (i > 0) && mask[src];
+        ms[i] = (i > 0) && !hs[src];
+    }
+    double Knf = 0, Kns = 0, Wf = 0, Ws = 0, Wfp = 0, Wsp = 0, Bf = 0, As = 0;
+    for (int i = 0; i < Q; ++i) {
+        int o = L->opp[i];
+        if (mf[i]) {
+            Wf += L->w[i];
+            if (!mf[o]) { Wfp += L->w[i]; Bf += g[(int64_t)o * N + y]; }
+        } else {
+            Knf += g[(int64_t)i * N + y];
+        }
+        if (ms[i]) {
+            Ws += L->w[i];
+            if (!ms[o]) { Wsp += L->w[i]; As += gs[(int64_t)o * N + y]; }
+        } else {
+            Kns += gs[(int64_t)i * N + y];
+        }
+    }
+    double kf = 1.0 - 0.5 / th->tau_ef, ks = 1.0 - 0.5 / th->tau_es;
+    double cfs = th->rhocp_f / th->rhocp_s;
+    double det = Wf * ks * Wsp + cfs * Ws * kf * Wfp;
+    *degenerate = !(det > 0.0);
+
+    /* solute wet links of this node: h_in = h_opp(k) after streaming */
+    int nwet = 0, kw[7];
+    double hin[7];
+    double tau_d = p->D / S->cs2 + 0.5;
+    if (p->solute)
+        for (int k = 1; k < S->Q; ++k)
+            if (wet[y] & (1u << k)) { kw[nwet] = k; hin[nwet] = h[(int64_t)S->opp[k] * N + y]; ++nwet; }
+
+    double T = Ti[y], Xf = 0, Xs = 0, kr = 0, Cb[7];
+    int it = 0;
+    *settled = 0;
+    while (it < th->T_maxit) {
+        ++it;
+        kr = th->A * exp(-th->E_over_R / T);
+        double Hdot = 0.0;
+        for (int q = 0; q < nwet; ++q) {
+            int k = kw[q];
+            Cb[q] = 2.0 * hin[q] / (2.0 * S->w[k] + kr * tau_d / (tau_d - 0.5));
+            Hdot += th->h_r * kr * Cb[q];
+        }
+        if (!*degenerate) {
+            Xs = (Wf * (ks * As + kf * Bf + Hdot) - kf * Wfp * (cfs * Kns - Knf)) / det;
+        } else {
+            Xs = Ws > 0.0 ? Kns / (1.0 - Ws) : 0.0;
+        }
+        Xf = (cfs * (Kns + Ws * Xs) - Knf) / Wf;
+        double Tn = (Knf + Wf * Xf) / th->rhocp_f;
+        int done = fabs(Tn - T) <= th->T_tol * fabs(Tn);
+        T = Tn;
+        if (done) { *settled = 1; break; }
+    }
+    for (int i = 0; i < Q; ++i) {
+        if (mf[i]) g[(int64_t)i * N + y] = L->w[i] * Xf;
+        if (ms[i]) gs[(int64_t)i * N + y] = L->w[i] * Xs;
+    }
+    Ti[y] = T;
+    /* wet-link populations with the rate of the last iteration: O2 (eq:wetnode9)
+     * and the product (eq:reactCO2, same convention as without heat) */
+    for (int q = 0; q < nwet; ++q) {
+        int k = kw[q];
+        h[(int64_t)k * N + y] = 2.0 * S->w[k] * Cb[q] - hin[q];
+        if (p->product) {
+            double tau2 = p->D2 / S->cs2 + 0.5;
+            double hin2 = h[(int64_t)(S->Q + S->opp[k]) * N + y];
+            h[(int64_t)(S->Q + k) * N + y] = hin2 + kr * tau2 / (tau2 - 0.5) * Cb[q];
+        }
+    }
+    return it;
+}
+
+/* Full time steps with conjugate heat transfer.  Flow and solute as orc_step,
+ * except that the wet-link populations of the solute come from the interface
+ * solve (their rate follows the interface temperature); then the energy
+ * populations:
+ *   1. fluid g: BGK towards g^eq(sum g, u) with tau_ef, u the barycentric
+ *      velocity with half force of this step (the solute's);
+ *      solid gs: BGK towards w_i sum gs with tau_es (eq:therpop_solid);
+ *   2. streaming (pull) of the known populations;
+ *   3. interface solve at every interface node (counter-slip + reaction).
+ * g, gs: [Q][N]; Ti: [N] interface temperatures (start values of the
+ * iteration, carried from step to step).  stats (may be NULL): [0] total
+ * iterations, [1] interface solves that did not settle, [2] degenerate
+ * interface nodes (of the last step). */
+void orc_step_thermal(const orc_params* p, const orc_thermal* th, const uint8_t* mask, double* f, double* h,
+                      double* g, double* gs, double* Ti, int64_t nsteps, int64_t* stats) {
+    flow_lat L = make_flow(p->lattice);
+    sol_lat S = make_sol(p->lattice, p->J0);
+    int64_t N = nnodes(p);
+    int NC = p->ncomp, Q = L.Q;
+    int NS = p->solute ? (p->product ? 2 : 1) : 0;
+    double* rho = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* psi = (double*)calloc((size_t)(NC * N), sizeof(double));
+    double* fstar = (double*)calloc((size_t)(NC * Q * N), sizeof(double));
+    double* hstar = NS ? (double*)calloc((size_t)(NS * S.Q * N), sizeof(double)) : NULL;
+    double* gstar = (double*)calloc((size_t)(Q * N), sizeof(double));
+    double* gsstar = (double*)calloc((size_t)(Q * N), sizeof(double));
+    uint8_t* hs = (uint8_t*)malloc((size_t)N);
+    uint8_t* itf = (uint8_t*)malloc((size_t)N);
+    uint32_t* fb = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t* wet = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    orc_thermal_nodes(p, mask, hs, itf);
+    orc_link_masks(p, mask, fb, wet);
+    int64_t iters = 0, unsettled = 0, degen = 0;
+
+    for (int64_t t = 0; t < nsteps; ++t) {
+        densities(p, &L, mask, f, rho, psi);
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            if (!mask[n]) {
+                double fs[2][19], hsn[14], F[2][3], u[3];
+                collide_at(p, &L, &S, mask, f, h, rho, psi, n, fs, hsn);
+                for (int s = 0; s < NC; ++s)
+                    for (int i = 0; i < Q; ++i) fstar[((int64_t)s * Q + i) * N + n] = fs[s][i];
+                for (int k = 0; k < NS * S.Q; ++k) hstar[(int64_t)k * N + n] = hsn[k];
+                force_at(p, &L, mask, rho, psi, n, F);
+                bary_u(p, &L, f, n, rho, F, u);
+                double E = 0.0;
+                for (int i = 0; i < Q; ++i) E += g[(int64_t)i * N + n];
+                for (int i = 0; i < Q; ++i) {
+                    double gi = g[(int64_t)i * N + n];
+                    gstar[(int64_t)i * N + n] = gi - (gi - geq_i(&L, i, E, u)) / th->tau_ef;
+                }
+            }
+            if (hs[n]) {
+                double Es = 0.0;
+                for (int i = 0; i < Q; ++i) Es += gs[(int64_t)i * N + n];
+                for (int i = 0; i < Q; ++i) {
+                    double gi = gs[(int64_t)i * N + n];
+                    gsstar[(int64_t)i * N + n] = gi - (gi - L.w[i] * Es) / th->tau_es;
+                }
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            if (!mask[n]) {
+                for (int s = 0; s < NC; ++s)
+                    for (int i = 0; i < Q; ++i)
+                        f[((int64_t)s * Q + i) * N + n] = flow_stream_value(p, &L, mask, fstar, s, i, n);
+                for (int sp = 0; sp < NS; ++sp)
+                    for (int k = 0; k < S.Q; ++k) {
+                        /* wet links are left to the interface solve (their rate needs T) */
+                        int64_t src = nbr_back(p, n, S.c[k]);
+                        int x, yy, z;
+                        coords(p, n, &x, &yy, &z);
+                        int seam = p->solute == 2 && ((x == 0 && S.c[k][0] == 1) || (x == p->nx - 1 && S.c[k][0] == -1));
+                        if (!seam && mask[src]) continue;
+                        h[(int64_t)(sp * S.Q + k) * N + n] = solute_stream_value(p, &S, mask, hstar, sp, k, n);
+                    }
+                for (int i = 0; i < Q; ++i) {
+                    int64_t src = nbr_back(p, n, L.c[i]);
+                    if (!mask[src]) g[(int64_t)i * N + n] = gstar[(int64_t)i * N + src];
+                }
+            }
+            if (hs[n])
+                for (int i = 0; i < Q; ++i) {
+                    int64_t src = nbr_back(p, n, L.c[i]);
+                    if (hs[src]) gs[(int64_t)i * N + n] = gsstar[(int64_t)i * N + src];
+                }
+        }
+        degen = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : iters, unsettled, degen)
+        for (int64_t n = 0; n < N; ++n) {
+            if (!itf[n]) continue;
+            int dg = 0, ok = 0;
+            iters += interface_solve(p, th, &L, &S, mask, hs, wet, g, gs, h, Ti, n, &dg, &ok);
+            unsettled += !ok;
+            degen += dg;
+        }
+    }
+    if (stats) { stats[0] = iters; stats[1] = unsettled; stats[2] = degen; }
+    free(rho); free(psi); free(fstar); free(hstar); free(gstar); free(gsstar);
+    free(hs); free(itf); free(fb); free(wet);
+}
+
+/* Temperature field: fluid nodes (interface included) E_f / (rho c_p)_f,
+ * solid nodes E_s / (rho c_p)_s.  T: [N]. */
+void orc_temperature(const orc_params* p, const orc_thermal* th, const uint8_t* mask, const double* g,
+                     const double* gs, double* T) {
+    flow_lat L = make_flow(p->lattice);
+    int64_t N = nnodes(p);
+    for (int64_t n = 0; n < N; ++n) {
+        double E = 0.0;
+        for (int i = 0; i < L.Q; ++i) E += mask[n] ? gs[(int64_t)i * N + n] : g[(int64_t)i * N + n];
+        T[n] = E / (mask[n] ? th->rhocp_s : th->rhocp_f);
+    }
 }
