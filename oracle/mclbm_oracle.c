@@ -728,7 +728,10 @@ void orc_moments(const orc_params* p, const uint8_t* mask, const double* f, cons
  * solid populations; the remaining populations of an interface node are the
  * unknowns of the counter-slip conditions:
  *   M_f = { i : x - c_i solid }            fluid unknowns  g_i  = w_i X_f
- *   M_s = { i : x - c_i pure fluid }       solid unknowns  gs_i = w_i X_s
+ *   M_s = { i : x - c_i fluid, and either not an interface node (nothing
+ *           streams gs_i) or x + c_i solid (gs_i would come in from across
+ *           the fluid: the solid field does not pass through it) }
+ *                                           solid unknowns  gs_i = w_i X_s
  * (the counter-slip form: unknowns proportional to their weights).  Reading
  * (ours) of the flat-wall conditions for any voxel interface:
  *   temperature   (Kn_f + W_f X_f) / (rho c_p)_f = (Kn_s + W_s X_s) / (rho c_p)_s
@@ -740,11 +743,11 @@ void orc_moments(const orc_params* p, const uint8_t* mask, const double* f, cons
  * eq:wetnode9), k(T) = A exp(-E / (R_u T)).  For a flat wall with normal +y
  * in D2Q9 (M_f = {2, 5, 6}, M_s = {4, 7, 8}) eliminating X_f gives exactly
  * the printed eq:unknownpopTempS, and the temperature condition then gives
- * eq:unknownpopTempF.  Where the flux condition cannot be posed (no unknown
- * solid population, or every unknown paired with an unknown opposite on both
- * sides) the temperature condition alone is used, the solid unknowns taking
- * the local solid equilibrium; such nodes release no reaction heat and are
- * counted.
+ * eq:unknownpopTempF.  The flux condition can always be posed except at a
+ * node whose every missing fluid link has a solid on both sides (only
+ * diagonal pairs: axis pinches are removed by the geometry rule); there the
+ * temperature condition alone is used, the solid unknowns taking the local
+ * solid equilibrium, no reaction heat is released, and the node is counted.
  * ========================================================================= */
 typedef struct {
     double tau_ef, tau_es;   /* 3 alpha + 1/2 of fluid and solid */
@@ -815,8 +818,12 @@ static int interface_solve(const orc_params* p, const orc_thermal* th, const flo
     int mf[19], ms[19];
     for (int i = 0; i < Q; ++i) {
         int64_t src = nbr_back(p, y, L->c[i]);
+        int64_t dst = nbr(p, y, L->c[i]);
         mf[i] = (i > 0) && mask[src];
-        ms[i] = (i > 0) && !hs[src];
+        /* solid unknown: nothing streams it (the upstream node is pure fluid),
+         * or it streams in from a fluid node across the node from a solid one
+         * (the solid field does not pass through the fluid) */
+        ms[i] = (i > 0) && !mask[src] && (!hs[src] || mask[dst]);
     }
     double Knf = 0, Kns = 0, Wf = 0, Ws = 0, Wfp = 0, Wsp = 0, Bf = 0, As = 0;
     for (int i = 0; i < Q; ++i) {

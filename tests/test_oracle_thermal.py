@@ -285,3 +285,25 @@ def test_reaction_heat_warms_the_wall():
         T[key] = oracle.temperature(p, mask, g, gs).reshape(mask.shape)[0, 8, :].mean()
     assert abs(T["none"] - 1.0) < 1e-13
     assert 1.0 < T["slow"] < T["fast"]
+
+
+def test_two_node_channel_interfaces_are_posed():
+    """A fluid gap two nodes wide between solid slabs: every fluid node is an
+    interface node; the solid populations that would stream across the gap
+    from the other wall are unknowns of the counter-slip conditions, so the
+    flux condition is posed at every node (no degenerate node) and the
+    temperatures on both sides agree at every interface node."""
+    p = _thermal_params("D2Q9", nx=5, ny=12, solute="periodic", D=0.1, h_r=0.6, arr_A=4.0, arr_E_over_R=1.0)
+    mask = np.ones((1, 12, 5), np.uint8)
+    mask[0, 5:7, :] = 0
+    N = mask.size
+    f, h = oracle.init(p, mask, np.ones((1, N)), None, np.ones(N))
+    g, gs, Ti = oracle.thermal_init(p, mask, np.full(N, 1.0))
+    stats = oracle.step_thermal(p, mask, f, h, g, gs, Ti, 20)
+    assert stats[2] == 0 and stats[1] == 0
+    _, it = oracle.thermal_nodes(p, mask)
+    assert it.sum() == 10
+    for n in np.nonzero(it)[0]:
+        assert abs(g[:, n].sum() / p["rhocp_f"] - gs[:, n].sum() / p["rhocp_s"]) < 1e-14
+    T = oracle.temperature(p, mask, g, gs).reshape(12, 5)
+    assert T[5:7].min() > 1.0          # the reaction heat stays in the gap's walls and fluid
