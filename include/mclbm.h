@@ -322,6 +322,76 @@ int mclbm_get_step(mclbm_handle* h, int64_t* step);
 int mclbm_synchronize(mclbm_handle* h);
 
 /* Free library-owned objects (never the caller's arena).  NULL is a no-op. */
+/* ---------------------------------------------------------------------------
+ * Conjugate heat transfer (Reactive LBM subsection).  Internal-energy
+ * distributions on the flow lattice in the fluid (eq:therpop with the
+ * equilibrium eq:therpopeq, advected by the barycentric velocity with half
+ * force) and in the solid (eq:therpop_solid, eq:therpopeq_solid), coupled at
+ * interface nodes -- fluid nodes with a solid flow-lattice neighbour, which
+ * carry both distributions -- by the thermal counter-slip conditions
+ * (eq:countSlipFluxCon, eq:countSlipTempCon: equal temperatures, heat-flux
+ * balance with the reaction heat h_r k(T) C_b of eq:reacRate).  The unknown
+ * populations of an interface node -- fluid ones whose upstream node is
+ * solid; solid ones whose upstream node is a fluid node that is not an
+ * interface node, or a fluid node while the downstream node is solid (the
+ * solid field does not pass through the fluid) -- are w_i X_f and w_i X_s;
+ * the two conditions give X_f and X_s (for a flat wall exactly
+ * eq:unknownpopTempS and eq:unknownpopTempF).  The wet-link
+ * reaction of the solute (eq:wetnode9, and the product's, eq:reactCO2) at an
+ * interface node uses k(T) = A exp(-E_over_R / T) of the interface
+ * temperature, and C_b and T are iterated per node until
+ * |T_new - T| <= tol |T_new| (tol = max(T_tol, 4 x the arithmetic type's
+ * epsilon)) or T_maxit iterations, before the step ends (the C_b - T loop of
+ * the paper's flowchart).  Where the flux condition cannot be posed (every
+ * missing fluid link of the node has a solid on both sides, possible only
+ * along diagonals) the temperature condition alone is used and the solid
+ * unknowns take the node's solid equilibrium; such nodes release no reaction
+ * heat and are counted.  The thermal field is periodic in every direction. */
+typedef struct {
+    double tau_ef;    /* fluid energy relaxation time, 3 alpha_f + 1/2, > 1/2 */
+    double tau_es;    /* solid energy relaxation time, 3 alpha_s + 1/2, > 1/2 */
+    double rhocp_f;   /* rho c_p of the fluid, > 0 */
+    double rhocp_s;   /* rho c_p of the solid, > 0 */
+    double h_r;       /* heat released per unit of reacting species consumed, >= 0 */
+    double A;         /* pre-exponential factor of k(T), >= 0 */
+    double E_over_R;  /* activation temperature E / R_u of k(T), >= 0 */
+    double T_tol;     /* relative tolerance of the interface iteration, > 0 */
+    int32_t T_maxit;  /* iteration cap, >= 1 */
+    int32_t reserved; /* must be 0 */
+} mclbm_thermal;
+
+/* Turn conjugate heat transfer on for a single lattice (not a batch) with F64
+ * or F32 storage, without deposition or rate_field.  Call after init_lattice
+ * and before set_geometry (the thermal node lists are built there; a call
+ * after set_geometry resets the geometry: ESTATE until set_geometry again).
+ * The thermal arrays are device memory the library allocates in
+ * set_geometry and frees in destroy.  EINVAL for invalid values or an
+ * unsupported combination. */
+int mclbm_set_thermal(mclbm_handle* h, const mclbm_thermal* t);
+
+/* Initial energy populations from a temperature field T [N] (host FP64, box
+ * layout): fluid nodes the equilibrium eq:therpopeq at E = rho_c_p,f T and
+ * velocity u ([3][N] host FP64, or NULL for rest), solid and interface nodes
+ * w_i rho_c_p,s T; the interface iteration starts from T.  Call after
+ * init_fields (which invalidates the thermal state: ESTATE from mclbm_step
+ * until this call).  Resets the statistics of mclbm_get_thermal_stats. */
+int mclbm_init_temperature(mclbm_handle* h, const double* T, const double* u);
+
+/* Temperature [N] (host FP64): fluid and interface nodes E_f / rho_c_p,f,
+ * solid nodes E_s / rho_c_p,s (E = sum of the node's energy populations). */
+int mclbm_get_temperature(mclbm_handle* h, double* T);
+
+/* Energy populations of the current state, FP64 host [Q][N] each, box layout:
+ * g at fluid nodes (0 elsewhere), gs at solid and interface nodes (0
+ * elsewhere).  Either pointer may be NULL. */
+int mclbm_get_thermal_populations(mclbm_handle* h, double* g, double* gs);
+
+/* Statistics since init_temperature: out[0] interface iterations in total,
+ * out[1] interface solves that stopped at T_maxit without meeting the
+ * tolerance, out[2] interface nodes where the flux condition cannot be posed
+ * (a property of the geometry, counted once). */
+int mclbm_get_thermal_stats(mclbm_handle* h, int64_t out[3]);
+
 /* Practical HBM bandwidth of this device, measured with streaming kernels
  * (not part of the method: the ceiling the step kernels are compared with).
  * kind 0: read `bytes` of `a` (non-temporal 16-byte loads; `b` >= 4 KiB of

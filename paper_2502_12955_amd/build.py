@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBS = {
-    "libmclbm.so": ["api.cpp", "geometry.cpp", "kernels.hip", "remap.hip", "probe.hip"],
+    "libmclbm.so": ["api.cpp", "geometry.cpp", "kernels.hip", "remap.hip", "probe.hip", "thermal.hip"],
     "libwarmnet.so": ["warmnet.hip"],
 }
 

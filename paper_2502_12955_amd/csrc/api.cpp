@@ -118,6 +118,15 @@ struct mclbm_handle {
     double rhobar[2] = {0, 0};
     int block = 256, grid = 0;
     int flat = 0;                   // 1: flat 64-bit addressing in the collide pass
+    // conjugate heat transfer (library-owned device memory, allocated in set_geometry)
+    bool thermal = false, temp_set = false;
+    mclbm_thermal th{};
+    void *gA = nullptr, *gB = nullptr, *gsA = nullptr, *gsB = nullptr, *Ti = nullptr;
+    int* smap = nullptr;
+    unsigned* spos = nullptr;
+    int* iface = nullptr;
+    unsigned long long* th_stats = nullptr;
+    long long nsolid = 0, niface = 0, ndegenerate = 0;
     // graph replay of monitor_every steps (one per A/B parity)
     bool use_graph = false;
     hipStream_t gstream = nullptr;
@@ -361,6 +370,33 @@ Ctx make_ctx(mclbm_handle* h, hipStream_t stream) {
     c.nsamples = h->S;
     c.Ntot = h->Ntot;
     c.flat = h->flat;
+    c.thermal = h->thermal && h->gA ? 1 : 0;
+    if (c.thermal) {
+        c.th_tau_ef = h->th.tau_ef;
+        c.th_tau_es = h->th.tau_es;
+        c.th_rhocp_f = h->th.rhocp_f;
+        c.th_rhocp_s = h->th.rhocp_s;
+        c.th_h_r = h->th.h_r;
+        c.th_A = h->th.A;
+        c.th_EoR = h->th.E_over_R;
+        c.th_tol = h->th.T_tol;
+        c.th_maxit = h->th.T_maxit;
+        c.gA = h->gA;
+        c.gB = h->gB;
+        c.gsA = h->gsA;
+        c.gsB = h->gsB;
+        c.Ti = h->Ti;
+        c.smap = h->smap;
+        c.spos = h->spos;
+        c.nsolid = h->nsolid;
+        c.iface = h->iface;
+        c.niface = h->niface;
+        c.th_stats = h->th_stats;
+        c.thermal_nx = h->smp[0].nx;
+        c.thermal_ny = h->smp[0].ny;
+        c.thermal_nz = h->smp[0].nz;
+        c.thermal_nfluid = h->smp[0].nf;
+    }
     c.max_sample_nodes = 0;
     for (const auto& sm : h->smp) c.max_sample_nodes = std::max(c.max_sample_nodes, sm.N);
     c.nchunks = h->nchunks;
@@ -499,6 +535,8 @@ int launch_step(mclbm_handle* h, hipStream_t stream) {
     HIPCHK(h, k_step(c));
     std::swap(h->fA, h->fB);
     std::swap(h->hA, h->hB);
+    std::swap(h->gA, h->gB);
+    std::swap(h->gsA, h->gsB);
     ++h->step;
     return MCLBM_OK;
 }
@@ -518,6 +556,7 @@ int graph_for_parity(mclbm_handle* h, int parity, hipGraphExec_t* out) {
     const int K = h->p.monitor_every;
     const int64_t step0 = h->step;
     void *fA = h->fA, *fB = h->fB, *hA = h->hA, *hB = h->hB;
+    void *gA = h->gA, *gB = h->gB, *gsA = h->gsA, *gsB = h->gsB;
     HIPCHK(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int s = 0; s < K && e == hipSuccess; ++s) {
@@ -525,11 +564,14 @@ int graph_for_parity(mclbm_handle* h, int parity, hipGraphExec_t* out) {
         e = k_step(c);
         std::swap(h->fA, h->fB);
         std::swap(h->hA, h->hB);
+        std::swap(h->gA, h->gB);
+        std::swap(h->gsA, h->gsB);
     }
     if (e == hipSuccess) e = k_monitor(make_ctx(h, h->gstream), 1);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(h->gstream, &graph);
     h->fA = fA, h->fB = fB, h->hA = hA, h->hB = hB;
+    h->gA = gA, h->gB = gB, h->gsA = gsA, h->gsB = gsB;
     h->step = step0;
     if (e != hipSuccess) return hip_fail(h, e, "capture");
     if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
@@ -663,6 +705,92 @@ int mclbm_init_lattice(const mclbm_params* p, void* device_arena, size_t arena_b
     return mclbm_init_batch(p, 1, device_arena, arena_bytes, hip_stream, out);
 }
 
+// ---------------------------------------------------------------- conjugate heat transfer
+static void free_thermal(mclbm_handle* h) {
+    for (void** p : {&h->gA, &h->gB, &h->gsA, &h->gsB, &h->Ti, (void**)&h->smap, (void**)&h->spos,
+                     (void**)&h->iface, (void**)&h->th_stats})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    h->nsolid = h->niface = h->ndegenerate = 0;
+    h->temp_set = false;
+}
+
+static int band_rows(int ny);
+
+// Build the solid list, the interface list and the thermal arrays for the
+// current geometry (single lattice).  `map` is the box -> fluid index map.
+static int build_thermal(mclbm_handle* h, const std::vector<int>& map) {
+    free_thermal(h);
+    SampleHost& sm = h->smp[0];
+    const GeomSpec gs{h->p.lattice, sm.nx, sm.ny, sm.nz, h->p.solute};
+    std::vector<unsigned> spos, ibox;
+    std::vector<int> smap;
+    std::vector<uint32_t> msb;
+    thermal_lists(gs, sm.mask, band_rows(sm.ny), spos, smap, ibox, msb);
+    const int Q = h->Q;
+    const size_t sb = store_bytes(h->p.storage), ab = arith_bytes(h->p.storage);
+    const long long nsol = (long long)spos.size(), ni = (long long)ibox.size();
+    const long long schunks = std::max(1LL, pad64(nsol) / 64);
+    std::vector<int> iface((size_t)std::max(1LL, ni) * 4, 0);
+    for (long long q = 0; q < ni; ++q) {
+        const unsigned n = ibox[(size_t)q];
+        iface[(size_t)(4 * q)] = map[n];
+        iface[(size_t)(4 * q + 1)] = smap[n];
+        iface[(size_t)(4 * q + 2)] = (int)msb[(size_t)q];
+    }
+    const size_t gbytes = (size_t)h->nchunks * 64 * Q * sb, gsbytes = (size_t)schunks * 64 * Q * sb;
+    auto dalloc = [&](void** p, size_t bytes) -> hipError_t { return hipMalloc(p, std::max(bytes, (size_t)256)); };
+    hipError_t e = dalloc(&h->gA, gbytes);
+    if (e == hipSuccess) e = dalloc(&h->gB, gbytes);
+    if (e == hipSuccess) e = dalloc(&h->gsA, gsbytes);
+    if (e == hipSuccess) e = dalloc(&h->gsB, gsbytes);
+    if (e == hipSuccess) e = dalloc(&h->Ti, (size_t)std::max(1LL, ni) * ab);
+    if (e == hipSuccess) e = dalloc((void**)&h->smap, smap.size() * 4);
+    if (e == hipSuccess) e = dalloc((void**)&h->spos, (size_t)schunks * 64 * 4);
+    if (e == hipSuccess) e = dalloc((void**)&h->iface, iface.size() * 4);
+    if (e == hipSuccess) e = dalloc((void**)&h->th_stats, 64);
+    if (e != hipSuccess) {
+        free_thermal(h);
+        return fail(h, MCLBM_ENOMEM, std::string("thermal arrays: ") + hipGetErrorString(e));
+    }
+    spos.resize((size_t)schunks * 64, 0u);
+    HIPCHK(h, hipMemcpyAsync(h->smap, smap.data(), smap.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->spos, spos.data(), spos.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->iface, iface.data(), iface.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->th_stats, 0, 64, h->stream));
+    // the energy arrays hold no stale values in slots the kernels never write
+    HIPCHK(h, hipMemsetAsync(h->gA, 0, gbytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->gB, 0, gbytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->gsA, 0, gsbytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->gsB, 0, gsbytes, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    // degenerate interface nodes, where the flux condition cannot be posed (the
+    // kernel's det = W_f k_s W_s' + c_fs W_s k_f W_f' vanishes): no unknown solid
+    // population with a known opposite, and not both an unknown solid population
+    // and an unknown fluid population with a known opposite
+    long long degen = 0;
+    std::vector<uint32_t> words, fb;
+    link_words(gs, sm.mask, words, &fb, nullptr);
+    static const int O19[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static const int O9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const int* O = h->p.lattice == MCLBM_D3Q19 ? O19 : O9;
+    for (long long q = 0; q < ni; ++q) {
+        const uint32_t mf = fb[ibox[(size_t)q]], ms = msb[(size_t)q];
+        bool wsp = false, ws = ms != 0, wfp = false;
+        for (int i = 1; i < Q; ++i) {
+            if (((ms >> i) & 1u) && !((ms >> O[i]) & 1u)) wsp = true;
+            if (((mf >> i) & 1u) && !((mf >> O[i]) & 1u)) wfp = true;
+        }
+        if (!(wsp || (ws && wfp))) ++degen;
+    }
+    h->nsolid = nsol;
+    h->niface = ni;
+    h->ndegenerate = degen;
+    return MCLBM_OK;
+}
+
 // rows per y-band of the fluid numbering: eight bands (one per XCD of a
 // single large lattice), at least 4 rows
 static int band_rows(int ny) { return std::max(4, (ny + 7) / 8); }
@@ -758,6 +886,13 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
         std::vector<double> kb((size_t)h->Ntot, h->p.k_wall);
         rc = mclbm_set_wall_rate(h, kb.data());
         if (rc != MCLBM_OK) return rc;
+    }
+    if (h->thermal) {
+        rc = build_thermal(h, map);
+        if (rc != MCLBM_OK) {
+            h->geom_set = false;
+            return rc;
+        }
     }
     return MCLBM_OK;
 }
@@ -860,6 +995,7 @@ int mclbm_init_fields(mclbm_handle* h, const double* rho, const double* u, const
     for (int k = 0; k < 16; ++k) h->mon[k] = 0.0;
     h->mon[0] = -1.0;
     h->fields_set = true;
+    h->temp_set = false;
     return MCLBM_OK;
 }
 
@@ -1046,6 +1182,7 @@ int mclbm_step(mclbm_handle* h, int64_t n) {
     if (!h) return MCLBM_EINVAL;
     if (n < 0) return fail(h, MCLBM_EINVAL, "n must be >= 0");
     if (!h->fields_set) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
+    if (h->thermal && !h->temp_set) return fail(h, MCLBM_ESTATE, "init_temperature has not been called");
     if (h->dep) return step_deposition(h, n);
     const int K = h->p.monitor_every;
     bool monitored = false, had = false;
@@ -1410,6 +1547,93 @@ int mclbm_synchronize(mclbm_handle* h) {
     return MCLBM_OK;
 }
 
+int mclbm_set_thermal(mclbm_handle* h, const mclbm_thermal* t) {
+    if (!h) return MCLBM_EINVAL;
+    if (!t) return fail(h, MCLBM_EINVAL, "thermal parameters are NULL");
+    if (h->S != 1) return fail(h, MCLBM_EINVAL, "conjugate heat transfer needs a single lattice");
+    if (h->p.storage != MCLBM_F64 && h->p.storage != MCLBM_F32)
+        return fail(h, MCLBM_EINVAL, "conjugate heat transfer needs F64 or F32 storage");
+    if (h->p.deposition || h->p.rate_field)
+        return fail(h, MCLBM_EINVAL, "conjugate heat transfer excludes deposition and rate_field");
+    auto pos = [](double v) { return v > 0 && isfinite(v); };
+    auto nonneg = [](double v) { return v >= 0 && isfinite(v); };
+    if (!(t->tau_ef > 0.5) || !isfinite(t->tau_ef) || !(t->tau_es > 0.5) || !isfinite(t->tau_es))
+        return fail(h, MCLBM_EINVAL, "tau_ef and tau_es must be > 1/2");
+    if (!pos(t->rhocp_f) || !pos(t->rhocp_s)) return fail(h, MCLBM_EINVAL, "rhocp_f and rhocp_s must be > 0");
+    if (!nonneg(t->h_r) || !nonneg(t->A) || !nonneg(t->E_over_R))
+        return fail(h, MCLBM_EINVAL, "h_r, A and E_over_R must be >= 0 and finite");
+    if (!pos(t->T_tol) || t->T_maxit < 1 || t->reserved != 0)
+        return fail(h, MCLBM_EINVAL, "T_tol must be > 0, T_maxit >= 1, reserved 0");
+    drop_graphs(h);
+    free_thermal(h);
+    h->th = *t;
+    h->thermal = true;
+    h->geom_set = h->fields_set = false;
+    return MCLBM_OK;
+}
+
+int mclbm_init_temperature(mclbm_handle* h, const double* T, const double* u) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->thermal) return fail(h, MCLBM_ESTATE, "set_thermal has not been called");
+    if (!h->fields_set || !h->gA) return fail(h, MCLBM_ESTATE, "init_fields has not been called");
+    if (!T) return fail(h, MCLBM_EINVAL, "T is NULL");
+    const long long N = h->Ntot;
+    for (long long n = 0; n < N; ++n)
+        if (!(T[n] > 0) || !isfinite(T[n])) return fail(h, MCLBM_EINVAL, "T must be > 0 and finite");
+    drop_graphs(h);
+    double* st_T = h->stage;
+    double* st_u = h->stage + N;   // the staging area holds at least (ncomp + 4) N doubles
+    HIPCHK(h, hipMemcpyAsync(st_T, T, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
+    if (u) HIPCHK(h, hipMemcpyAsync(st_u, u, (size_t)3 * N * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, k_thermal_init(make_ctx(h), st_T, u ? st_u : nullptr));
+    HIPCHK(h, hipMemsetAsync(h->th_stats, 0, 64, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->temp_set = true;
+    return MCLBM_OK;
+}
+
+int mclbm_get_temperature(mclbm_handle* h, double* T) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->thermal || !h->temp_set) return fail(h, MCLBM_ESTATE, "init_temperature has not been called");
+    if (!T) return fail(h, MCLBM_EINVAL, "T is NULL");
+    const long long N = h->Ntot;
+    HIPCHK(h, hipMemsetAsync(h->stage, 0, (size_t)N * 8, h->stream));
+    HIPCHK(h, k_thermal_out(make_ctx(h), 0, 0, h->stage));
+    HIPCHK(h, hipMemcpyAsync(T, h->stage, (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MCLBM_OK;
+}
+
+int mclbm_get_thermal_populations(mclbm_handle* h, double* g, double* gs) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->thermal || !h->temp_set) return fail(h, MCLBM_ESTATE, "init_temperature has not been called");
+    const long long N = h->Ntot;
+    for (int which = 1; which <= 2; ++which) {
+        double* dst = which == 1 ? g : gs;
+        if (!dst) continue;
+        for (int i = 0; i < h->Q; ++i) {
+            HIPCHK(h, hipMemsetAsync(h->stage, 0, (size_t)N * 8, h->stream));
+            HIPCHK(h, k_thermal_out(make_ctx(h), which, i, h->stage));
+            HIPCHK(h, hipMemcpyAsync(dst + (size_t)i * N, h->stage, (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MCLBM_OK;
+}
+
+int mclbm_get_thermal_stats(mclbm_handle* h, int64_t out[3]) {
+    if (!h) return MCLBM_EINVAL;
+    if (!h->thermal || !h->temp_set) return fail(h, MCLBM_ESTATE, "init_temperature has not been called");
+    if (!out) return fail(h, MCLBM_EINVAL, "out is NULL");
+    unsigned long long st[2] = {0, 0};
+    HIPCHK(h, hipMemcpyAsync(st, h->th_stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    out[0] = (int64_t)st[0];
+    out[1] = (int64_t)st[1];
+    out[2] = (int64_t)h->ndegenerate;
+    return MCLBM_OK;
+}
+
 void mclbm_destroy(mclbm_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
@@ -1422,6 +1646,7 @@ void mclbm_destroy(mclbm_handle* h) {
     if (h->host_nwork) (void)hipHostFree(h->host_nwork);
     if (h->host_dep) (void)hipHostFree(h->host_dep);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
+    free_thermal(h);
     delete h;
 }
 

@@ -156,6 +156,47 @@ struct Phys {
     // of kstride values: 1 / (2 W + k tau_d / (tau_d - 1/2)) and k tau_d2 / (tau_d2 - 1/2)
     const R* kfield;
     unsigned kstride;
+    R th_inv_tau_ef;      // 1 / tau of the fluid energy populations (conjugate heat transfer)
 };
+
+// ---------------------------------------------------------------------------
+// Indexing shared by the kernel files
+// ---------------------------------------------------------------------------
+// element (plane j, fluid node k) of a chunked array with P planes
+template <typename T>
+__device__ __forceinline__ T* blk(T* base, int P, int j, unsigned k) {
+    return base + ((size_t)(k >> 6) * (size_t)P + (size_t)j) * 64u + (k & 63u);
+}
+
+__device__ __forceinline__ void coords(const unsigned n, int nx, int ny, int& x, int& y, int& z) {
+    const unsigned nxy = (unsigned)nx * (unsigned)ny;
+    z = (int)(n / nxy);
+    const unsigned r = n - (unsigned)z * nxy;
+    y = (int)(r / (unsigned)nx);
+    x = (int)(r - (unsigned)y * (unsigned)nx);
+}
+
+// box indices of the neighbourhood positions by (cx, cy, cz) in {-1,0,1}
+struct NbIdx {
+    unsigned xo[3];   // x - 1, x, x + 1 (wrapped)
+    unsigned yo[3];   // nx * (y - 1, y, y + 1)
+    unsigned zo[3];   // nx*ny * (z - 1, z, z + 1)
+    __device__ __forceinline__ unsigned at(int cx, int cy, int cz) const { return xo[cx + 1] + yo[cy + 1] + zo[cz + 1]; }
+};
+
+__device__ __forceinline__ NbIdx make_nb(int x, int y, int z, int nx, int ny, int nz) {
+    NbIdx b;
+    b.xo[0] = x == 0 ? nx - 1 : x - 1;
+    b.xo[1] = x;
+    b.xo[2] = x + 1 == nx ? 0 : x + 1;
+    const unsigned unx = nx, unxy = (unsigned)nx * ny;
+    b.yo[0] = unx * (y == 0 ? ny - 1 : y - 1);
+    b.yo[1] = unx * y;
+    b.yo[2] = unx * (y + 1 == ny ? 0 : y + 1);
+    b.zo[0] = unxy * (z == 0 ? nz - 1 : z - 1);
+    b.zo[1] = unxy * z;
+    b.zo[2] = unxy * (z + 1 == nz ? 0 : z + 1);
+    return b;
+}
 
 }  // namespace mclbm

@@ -260,3 +260,66 @@ int64_t convert_nodes(const GeomSpec& s, std::vector<uint8_t>& mask, std::vector
 }
 
 }  // namespace mclbm
+
+namespace mclbm {
+
+// Conjugate heat transfer node lists (periodic wrap in every direction):
+//   solid list: solid nodes and interface nodes (fluid nodes with a solid
+//   flow-lattice neighbour), in the band order of the fluid numbering;
+//   interface list: box index of every interface node (same order) and the
+//   bits i of its unknown solid populations: those whose upstream node
+//   n - c_i is a fluid node that is not an interface node (nothing streams
+//   them), or a fluid node while n + c_i is solid (the solid field does not
+//   pass through the fluid).
+void thermal_lists(const GeomSpec& s, const std::vector<uint8_t>& mask, int band_rows, std::vector<unsigned>& spos,
+                   std::vector<int>& smap, std::vector<unsigned>& iface_box, std::vector<uint32_t>& ms_bits) {
+    const int Q = s.lattice == 1 ? 19 : 9;
+    const int (*c)[3] = s.lattice == 1 ? C19 : C9;
+    const long long N = (long long)s.nx * s.ny * s.nz;
+    auto wrap = [](int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    auto at = [&](int x, int y, int z) { return (long long)x + (long long)s.nx * (y + (long long)s.ny * z); };
+    std::vector<uint8_t> itf((size_t)N, 0);
+    for (int z = 0; z < s.nz; ++z)
+        for (int y = 0; y < s.ny; ++y)
+            for (int x = 0; x < s.nx; ++x) {
+                const long long n = at(x, y, z);
+                if (mask[(size_t)n]) continue;
+                for (int i = 1; i < Q; ++i)
+                    if (mask[(size_t)at(wrap(x - c[i][0], s.nx), wrap(y - c[i][1], s.ny), wrap(z - c[i][2], s.nz))]) {
+                        itf[(size_t)n] = 1;
+                        break;
+                    }
+            }
+    smap.assign((size_t)N, -1);
+    spos.clear();
+    iface_box.clear();
+    ms_bits.clear();
+    for (int y0 = 0; y0 < s.ny; y0 += band_rows)
+        for (int z = 0; z < s.nz; ++z)
+            for (int y = y0; y < std::min(s.ny, y0 + band_rows); ++y)
+                for (int x = 0; x < s.nx; ++x) {
+                    const long long n = at(x, y, z);
+                    if (!mask[(size_t)n] && !itf[(size_t)n]) continue;
+                    smap[(size_t)n] = (int)spos.size();
+                    spos.push_back((unsigned)n);
+                }
+    for (int y0 = 0; y0 < s.ny; y0 += band_rows)
+        for (int z = 0; z < s.nz; ++z)
+            for (int y = y0; y < std::min(s.ny, y0 + band_rows); ++y)
+                for (int x = 0; x < s.nx; ++x) {
+                    const long long n = at(x, y, z);
+                    if (!itf[(size_t)n]) continue;
+                    uint32_t b = 0;
+                    for (int i = 1; i < Q; ++i) {
+                        const long long m = at(wrap(x - c[i][0], s.nx), wrap(y - c[i][1], s.ny), wrap(z - c[i][2], s.nz));
+                        const long long d = at(wrap(x + c[i][0], s.nx), wrap(y + c[i][1], s.ny), wrap(z + c[i][2], s.nz));
+                        // nothing streams it (upstream pure fluid), or it would stream in from
+                        // a fluid node across this node from a solid one
+                        if (!mask[(size_t)m] && (!itf[(size_t)m] || mask[(size_t)d])) b |= 1u << i;
+                    }
+                    iface_box.push_back((unsigned)n);
+                    ms_bits.push_back(b);
+                }
+}
+
+}  // namespace mclbm

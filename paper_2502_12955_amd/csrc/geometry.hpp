@@ -31,4 +31,12 @@ void link_words(const GeomSpec& s, const std::vector<uint8_t>& mask, std::vector
 int64_t convert_nodes(const GeomSpec& s, std::vector<uint8_t>& mask, std::vector<unsigned>& pos,
                       std::vector<uint32_t>& words, const std::vector<long long>& add, std::vector<int>& from);
 
+// Conjugate heat transfer: solid list (solid and interface nodes, band order
+// with band_rows rows per band; spos = box index, smap = box -> list index or
+// -1), interface nodes (box indices, same order) and, per interface node, the
+// bits i of its unknown solid populations (upstream n - c_i a fluid node that
+// is not an interface node, or a fluid node while n + c_i is solid).
+void thermal_lists(const GeomSpec& s, const std::vector<uint8_t>& mask, int band_rows, std::vector<unsigned>& spos,
+                   std::vector<int>& smap, std::vector<unsigned>& iface_box, std::vector<uint32_t>& ms_bits);
+
 }  // namespace mclbm

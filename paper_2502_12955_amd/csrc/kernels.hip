@@ -50,12 +50,6 @@
 
 namespace mclbm {
 
-// element (plane j, fluid node k) of a chunked array with P planes
-template <typename T>
-__device__ __forceinline__ T* blk(T* base, int P, int j, unsigned k) {
-    return base + ((size_t)(k >> 6) * (size_t)P + (size_t)j) * 64u + (k & 63u);
-}
-
 // ---------------------------------------------------------------------------
 // Population access of the collide pass, in two addressing forms with the
 // same element layout (blk above):
@@ -74,9 +68,15 @@ struct GlobalIO {
     T* __restrict__ fB;
     const T* __restrict__ hA;
     T* __restrict__ hB;
+    const T* __restrict__ gA;   // fluid energy populations (GQ planes), conjugate heat transfer only
+    T* __restrict__ gB;
     __device__ __forceinline__ void fstore(int j, unsigned kd, R v, R shift) const { S::store(blk(fB, PF, j, kd), v, shift); }
     __device__ __forceinline__ R hload(int q, unsigned k) const { return S::load_plain(blk(hA, HP, q, k)); }
     __device__ __forceinline__ void hstore(int q, unsigned kd, R v) const { S::store_plain(blk(hB, HP, q, kd), v); }
+    template <int GQ>
+    __device__ __forceinline__ R gload(int i, unsigned k) const { return S::load_plain(blk(gA, GQ, i, k)); }
+    template <int GQ>
+    __device__ __forceinline__ void gstore(int i, unsigned kd, R v) const { S::store_plain(blk(gB, GQ, i, kd), v); }
 };
 
 // raw buffer resource: base, no stride, num_records = bytes, gfx9 data format
@@ -139,7 +139,7 @@ struct BufIO {
     using S = Store<ST>;
     using R = typename S::R;
     static constexpr uint32_t E = sizeof(typename S::T), PS = 64 * E;   // element and plane bytes
-    __amdgpu_buffer_rsrc_t fB, hA, hB;
+    __amdgpu_buffer_rsrc_t fB, hA, hB, gA, gB;
     // byte offset of (plane 0, node k) in an array of P planes
     template <int P>
     __device__ __forceinline__ static uint32_t node_off(unsigned k) {
@@ -154,6 +154,14 @@ struct BufIO {
     }
     __device__ __forceinline__ void hstore(int q, unsigned kd, R v) const {
         BufBits<ST>::st(hB, v, node_off<HP>(kd), (uint32_t)q * PS);
+    }
+    template <int GQ>
+    __device__ __forceinline__ R gload(int i, unsigned k) const {
+        return BufBits<ST>::template ld<2>(gA, node_off<GQ>(k), (uint32_t)i * PS);
+    }
+    template <int GQ>
+    __device__ __forceinline__ void gstore(int i, unsigned kd, R v) const {
+        BufBits<ST>::st(gB, v, node_off<GQ>(kd), (uint32_t)i * PS);
     }
 };
 
@@ -211,37 +219,6 @@ __device__ __forceinline__ SampleDev sample_of(const Geo& g, int ch) {
     return d;
 }
 
-__device__ __forceinline__ void coords(const unsigned n, int nx, int ny, int& x, int& y, int& z) {
-    const unsigned nxy = (unsigned)nx * (unsigned)ny;
-    z = (int)(n / nxy);
-    const unsigned r = n - (unsigned)z * nxy;
-    y = (int)(r / (unsigned)nx);
-    x = (int)(r - (unsigned)y * (unsigned)nx);
-}
-
-// box indices of the neighbourhood positions by (cx, cy, cz) in {-1,0,1}
-struct NbIdx {
-    unsigned xo[3];   // x - 1, x, x + 1 (wrapped)
-    unsigned yo[3];   // nx * (y - 1, y, y + 1)
-    unsigned zo[3];   // nx*ny * (z - 1, z, z + 1)
-    __device__ __forceinline__ unsigned at(int cx, int cy, int cz) const { return xo[cx + 1] + yo[cy + 1] + zo[cz + 1]; }
-};
-
-__device__ __forceinline__ NbIdx make_nb(int x, int y, int z, int nx, int ny, int nz) {
-    NbIdx b;
-    b.xo[0] = x == 0 ? nx - 1 : x - 1;
-    b.xo[1] = x;
-    b.xo[2] = x + 1 == nx ? 0 : x + 1;
-    const unsigned unx = nx, unxy = (unsigned)nx * ny;
-    b.yo[0] = unx * (y == 0 ? ny - 1 : y - 1);
-    b.yo[1] = unx * y;
-    b.yo[2] = unx * (y + 1 == ny ? 0 : y + 1);
-    b.zo[0] = unxy * (z == 0 ? nz - 1 : z - 1);
-    b.zo[1] = unxy * z;
-    b.zo[2] = unxy * (z + 1 == nz ? 0 : z + 1);
-    return b;
-}
-
 // ---------------------------------------------------------------------------
 // density / pseudo-potential
 // ---------------------------------------------------------------------------
@@ -285,7 +262,7 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
 //   dest(i): fluid index of x + c_i (called only where that node is fluid)
 //   x, nx: x coordinate of the node and the box edge (solute seams)
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC, int FC, int PR, int KF, class PsiNb, class Dest, class IO>
+template <int LAT, int ST, int NC, int FC, int PR, int KF, int TH, class PsiNb, class Dest, class IO>
 __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& P,
                                              const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q], unsigned k,
                                              uint32_t lw, int x, int nx, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q],
@@ -321,7 +298,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             if (!seam && !(lw & (1u << L::opp[d]))) {
                 const unsigned kd = dest(d);
                 io.hstore(d, kd, h[d]);
-                if (lw & (1u << (L::HOP_SHIFT + d))) {
+                if (!TH && (lw & (1u << (L::HOP_SHIFT + d)))) {   // with heat: the interface solve
                     const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
                     io.hstore(L::opp[d], kd, R(2) * P.Ws * Cb - h[d]);
                 }
@@ -347,7 +324,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
                 if (!seam && !(lw & (1u << L::opp[d]))) {
                     const unsigned kd = dest(d);
                     io.hstore(QS + d, kd, h2[d]);
-                    if (lw & (1u << (L::HOP_SHIFT + d))) {
+                    if (!TH && (lw & (1u << (L::HOP_SHIFT + d)))) {
                         const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
                         const R gain = KF ? P.kfield[P.kstride + kd] : P.prod_gain;
                         io.hstore(QS + L::opp[d], kd, h2[d] + gain * Cb);
@@ -357,6 +334,31 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
                 }
                 if (seam_mode && d == L::SXM && x == nx - 1) io.hstore(QS + d, k, h2[d]);
             }
+        }
+    }
+    if (TH) {
+        // fluid energy populations (eq:therpop, eq:therpopeq): BGK towards
+        // w_i E [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u], E = sum g, with the
+        // barycentric velocity; pushed to fluid neighbours only (a population
+        // heading into a solid leaves the fluid; the interface solve supplies
+        // the ones arriving from solids)
+        R g[Q];
+        R E = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            g[i] = io.template gload<Q>(i, k);
+            E += g[i];
+        }
+        const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const R cu = cdot<LAT, R>(i, u[0], u[1], u[2]);
+            const R geq = wgt<LAT, R>(i) * E * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+            const R post = g[i] - (g[i] - geq) * P.th_inv_tau_ef;
+            if (i == 0)
+                io.template gstore<Q>(0, k, post);
+            else if (!(lw & (1u << L::opp[i])))
+                io.template gstore<Q>(i, dest(i), post);
         }
     }
 }
@@ -375,7 +377,9 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
                                                  const typename Store<ST>::T* __restrict__ hA,
                                                  typename Store<ST>::T* __restrict__ hB,
                                                  const typename Store<ST>::R* __restrict__ psi,
-                                                 uint32_t fbytes, uint32_t hbytes) {
+                                                 uint32_t fbytes, uint32_t hbytes,
+                                                 const typename Store<ST>::T* __restrict__ gA,
+                                                 typename Store<ST>::T* __restrict__ gB, uint32_t gbytes) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
@@ -428,12 +432,16 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
             io.fB = make_rsrc(fB, fbytes);
             io.hA = make_rsrc(hA, hbytes);
             io.hB = make_rsrc(hB, hbytes);
-            collide_push<LAT, ST, NC, FC, (SV & 1), (SV >> 1)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, io);
+            io.gA = make_rsrc(gA, gbytes);
+            io.gB = make_rsrc(gB, gbytes);
+            collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb,
+                                                                                  dest, io);
         } else {
             auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
             auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
-            const GlobalIO<ST, PF, HP> io{fB, hA, hB};
-            collide_push<LAT, ST, NC, FC, (SV & 1), (SV >> 1)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest, io);
+            const GlobalIO<ST, PF, HP> io{fB, hA, hB, gA, gB};
+            collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb,
+                                                                                  dest, io);
         }
     });
 }
@@ -784,6 +792,7 @@ Phys<R> make_phys(const Ctx& c) {
     P.C_in2 = (R)c.C_in2;
     P.kfield = (const R*)c.kfield;
     P.kstride = (unsigned)(c.nchunks * 64);
+    P.th_inv_tau_ef = (R)(c.thermal ? 1.0 / c.th_tau_ef : 1.0);
     return P;
 }
 template Phys<float> make_phys<float>(const Ctx&);
@@ -841,18 +850,39 @@ static hipError_t step_t(const Ctx& c) {
     // and pseudo-potential field, below 4 GiB (32-bit byte offsets)
     const size_t fbytes = (size_t)c.nchunks * 64 * NC * Lat<LAT>::Q * sizeof(STT<ST>);
     const size_t hbytes = (size_t)c.nchunks * 64 * (size_t)(c.hplanes > 0 ? c.hplanes : 1) * sizeof(STT<ST>);
-    const bool buf = !c.flat && fbytes < (1ull << 32) && hbytes < (1ull << 32) &&
+    const size_t gbytes = c.thermal ? (size_t)c.nchunks * 64 * Lat<LAT>::Q * sizeof(STT<ST>) : 0;
+    const bool buf = !c.flat && fbytes < (1ull << 32) && hbytes < (1ull << 32) && gbytes < (1ull << 32) &&
                      (size_t)c.max_sample_nodes * NC * sizeof(SR<ST>) < (1ull << 32);
-    const uint32_t fb32 = (uint32_t)(buf ? fbytes : 0), hb32 = (uint32_t)(buf ? hbytes : 0);
+    const uint32_t fb32 = (uint32_t)(buf ? fbytes : 0), hb32 = (uint32_t)(buf ? hbytes : 0),
+                   gb32 = (uint32_t)(buf ? gbytes : 0);
+    const STT<ST>* gA = (const STT<ST>*)c.gA;
+    STT<ST>* gB = (STT<ST>*)c.gB;
 #define MCLBM_COLLIDE(FC, SV)                                                                                    \
     do {                                                                                                         \
         if (buf)                                                                                                 \
             hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV, 1>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, \
-                               hA, hB, psi, fb32, hb32);                                                         \
+                               hA, hB, psi, fb32, hb32, gA, gB, gb32);                                           \
         else                                                                                                     \
             hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV, 0>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, \
-                               hA, hB, psi, fb32, hb32);                                                         \
+                               hA, hB, psi, fb32, hb32, gA, gB, gb32);                                           \
     } while (0)
+    if (c.thermal) {
+        // conjugate heat transfer (F64 / F32 storage, uniform rate law of T):
+        // SV bit 2 on, then the solid energy pass and the interface solve
+        if constexpr (ST <= ST_F32) {
+            switch (c.forcing * 2 + (c.product ? 1 : 0)) {
+                case 0: MCLBM_COLLIDE(0, 4); break;
+                case 1: MCLBM_COLLIDE(0, 5); break;
+                case 2: MCLBM_COLLIDE(1, 4); break;
+                default: MCLBM_COLLIDE(1, 5); break;
+            }
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return k_thermal_step(c);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     const int sv = (c.product ? 1 : 0) + (c.kfield ? 2 : 0);
     switch (c.forcing * 4 + sv) {
         case 0: MCLBM_COLLIDE(0, 0); break;

@@ -50,6 +50,21 @@ struct Ctx {
     int block;                  // threads per block of the step kernels (64, 128, 256)
     int grid;                   // persistent grid (blocks, multiple of 8); 0 = one pass over the chunks
     int flat;                   // 1: flat 64-bit addresses in the collide pass even where buffer offsets fit
+    // conjugate heat transfer (single lattice; 0 = off)
+    int thermal;
+    double th_tau_ef, th_tau_es, th_rhocp_f, th_rhocp_s, th_h_r, th_A, th_EoR, th_tol;
+    int th_maxit;
+    void *gA, *gB;              // fluid energy populations, fluid chunks, Q planes
+    void *gsA, *gsB;            // solid energy populations, solid-list chunks, Q planes
+    void* Ti;                   // [niface] interface temperatures (arith type)
+    const int* smap;            // [N] solid-list index of a box node, -1 for a pure fluid node
+    const unsigned* spos;       // [nsolid] box index of each solid-list node
+    long long nsolid;           // solid and interface nodes
+    const int* iface;           // [niface][4]: fluid index, solid-list index, unknown-solid bits, 0
+    long long niface;
+    int thermal_nx, thermal_ny, thermal_nz;   // the lattice (thermal runs are single lattices)
+    long long thermal_nfluid;               // fluid nodes
+    unsigned long long* th_stats;   // [2] device counters: iterations, unsettled solves
 };
 
 constexpr int MON_NV = 11;      // values reduced per monitor
@@ -64,6 +79,14 @@ Phys<R> make_phys(const Ctx& c);
 
 hipError_t k_init(const Ctx& c, const double* rho, const double* u, const double* C);
 hipError_t k_step(const Ctx& c);
+// conjugate heat transfer: the solid energy pass and the interface solve of a
+// step (after the collide pass, before the A/B swap); initial energy populations
+// from FP64 box fields T [N] and u [3][N] (u may be NULL); one output plane in
+// FP64 box layout (what 0: temperature, 1: fluid energy plane i, 2: solid energy
+// plane i; nodes without that field get 0)
+hipError_t k_thermal_step(const Ctx& c);
+hipError_t k_thermal_init(const Ctx& c, const double* T, const double* u);
+hipError_t k_thermal_out(const Ctx& c, int what, int plane, double* dst);
 hipError_t k_moments(const Ctx& c, double* rho, double* u, double* C);
 hipError_t k_monitor(const Ctx& c, int have_snapshot);
 // FP64 values src[0 .. cnt-1] stored into elements q0 .. q0 + cnt - 1 of the

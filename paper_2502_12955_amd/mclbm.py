@@ -44,6 +44,29 @@ class Params(ct.Structure):
                 ("deposition", ct.c_int32), ("reserved2", ct.c_int32), ("dep_prob", ct.c_double)]
 
 
+class ThermalParams(ct.Structure):
+    """mclbm_thermal: conjugate heat transfer parameters."""
+    _fields_ = [("tau_ef", ct.c_double), ("tau_es", ct.c_double), ("rhocp_f", ct.c_double),
+                ("rhocp_s", ct.c_double), ("h_r", ct.c_double), ("A", ct.c_double), ("E_over_R", ct.c_double),
+                ("T_tol", ct.c_double), ("T_maxit", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+def thermal_from_dict(p: dict) -> ThermalParams:
+    """Keys as the oracle's: tau_ef, tau_es, rhocp_f, rhocp_s, h_r, arr_A, arr_E_over_R, T_tol, T_maxit."""
+    t = ThermalParams()
+    t.tau_ef = float(p.get("tau_ef", 1.0))
+    t.tau_es = float(p.get("tau_es", 1.0))
+    t.rhocp_f = float(p.get("rhocp_f", 1.0))
+    t.rhocp_s = float(p.get("rhocp_s", 1.0))
+    t.h_r = float(p.get("h_r", 0.0))
+    t.A = float(p.get("arr_A", 0.0))
+    t.E_over_R = float(p.get("arr_E_over_R", 0.0))
+    t.T_tol = float(p.get("T_tol", 1e-14))
+    t.T_maxit = int(p.get("T_maxit", 100))
+    t.reserved = 0
+    return t
+
+
 def _enum(v, table):
     return table[v] if isinstance(v, str) else int(v)
 
@@ -99,7 +122,9 @@ EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "
            "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
            "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_get_deposit", "mclbm_set_deposit", "mclbm_destroy",
-           "mclbm_last_error", "mclbm_hbm_probe", "mclbm_set_addressing")
+           "mclbm_last_error", "mclbm_hbm_probe", "mclbm_set_addressing", "mclbm_set_thermal",
+           "mclbm_init_temperature", "mclbm_get_temperature", "mclbm_get_thermal_populations",
+           "mclbm_get_thermal_stats")
 
 
 def load(path: str = LIB_PATH):
@@ -131,6 +156,11 @@ def load(path: str = LIB_PATH):
     lib.mclbm_set_launch.argtypes = [vp, i32, i32]
     lib.mclbm_set_graph.argtypes = [vp, i32]
     lib.mclbm_set_addressing.argtypes = [vp, i32]
+    lib.mclbm_set_thermal.argtypes = [vp, ct.POINTER(ThermalParams)]
+    lib.mclbm_init_temperature.argtypes = [vp, vp, vp]
+    lib.mclbm_get_temperature.argtypes = [vp, vp]
+    lib.mclbm_get_thermal_populations.argtypes = [vp, vp, vp]
+    lib.mclbm_get_thermal_stats.argtypes = [vp, vp]
     lib.mclbm_required_bytes_batch.argtypes = [P, i32, ct.POINTER(sz)]
     lib.mclbm_init_batch.argtypes = [P, i32, vp, sz, vp, ct.POINTER(vp)]
     lib.mclbm_get_sample_monitors.argtypes = [vp, i32, vp]
@@ -446,6 +476,33 @@ class Lattice:
 
     def set_addressing(self, flat=False):
         set_addressing(self.h, flat)
+
+    # conjugate heat transfer
+    def set_thermal(self, p: dict):
+        t = thermal_from_dict(p)
+        _check(load().mclbm_set_thermal(self.h, ct.byref(t)), self.h)
+
+    def init_temperature(self, T, u=None):
+        T = np.ascontiguousarray(np.asarray(T, np.float64).reshape(self.N))
+        up = None if u is None else np.ascontiguousarray(np.asarray(u, np.float64).reshape(3, self.N))
+        _check(load().mclbm_init_temperature(self.h, _ptr(T), _ptr(up)), self.h)
+
+    def temperature(self):
+        T = np.zeros(self.N)
+        _check(load().mclbm_get_temperature(self.h, _ptr(T)), self.h)
+        return T
+
+    def thermal_populations(self):
+        q = 19 if _enum(self.params["lattice"], LATTICE) == 1 else 9
+        g = np.zeros((q, self.N))
+        gs = np.zeros((q, self.N))
+        _check(load().mclbm_get_thermal_populations(self.h, _ptr(g), _ptr(gs)), self.h)
+        return g, gs
+
+    def thermal_stats(self):
+        out = np.zeros(3, np.int64)
+        _check(load().mclbm_get_thermal_stats(self.h, _ptr(out)), self.h)
+        return tuple(int(v) for v in out)
 
 
 
