@@ -51,21 +51,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(p, mask, rho, C, steps):
+def cpu_baseline(p, mask, rho, C, steps, steps_single):
+    """The FP64 C oracle on this host: `steps` steps of the benchmark state with
+    every host core, then `steps_single` steps with one thread (bounded samples
+    of the same workload)."""
     import numpy as np
 
     import oracle
 
     m, _ = oracle.pinch_fill(p, mask)
     f, h = oracle.init(p, m, rho, None, C)
+    N = int(np.prod(mask.shape))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    all_cores = oracle.set_threads(cores)
     t0 = time.perf_counter()
     oracle.step(p, m, f, h, steps)
     dt = time.perf_counter() - t0
-    N = int(np.prod(mask.shape))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} steps of the same {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]} state "
-                      f"(plain C FP64 oracle, OpenMP over nodes), {dt:.1f} s"}
+    one = oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.step(p, m, f, h, steps_single)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(all_cores)
+    shape = f"{mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]}"
+    return {"value": round(N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": all_cores, "kind": "oracle",
+            "sample": f"{steps} steps of the same {shape} state (plain C FP64 oracle, OpenMP over nodes, "
+                      f"{all_cores} threads), {dt:.1f} s",
+            "single_thread": {"value": round(N * steps_single / dt1 / 1e6, 4), "unit": "MLUPS", "cores": one,
+                              "sample": f"{steps_single} step(s) of the same state, 1 thread, {dt1:.1f} s"}}
 
 
 def main():
@@ -78,7 +90,9 @@ def main():
     ap.add_argument("--block", type=int, default=0,
                     help="threads per workgroup of the step kernels (0: the native tuner picks the launch shape)")
     ap.add_argument("--grid", type=int, default=0, help="persistent grid blocks with --block (0: one pass)")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps timed on all host cores")
+    ap.add_argument("--cpu-steps-single", type=int, default=1, help="oracle steps timed on one thread")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the HBM probe kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -146,10 +160,20 @@ def main():
                 "kernel": "mcmp step (k_density + k_collide)", "alg_bytes_per_launch": alg_bytes,
                 "launch_ms": round(launch_ms, 4)}
 
+    if not args.no_ceiling:
+        # measured HBM ceiling of this device (streaming kernels of the library)
+        lat.close()
+        torch.cuda.synchronize()
+        ceiling = {k: round(max(mclbm.hbm_probe(k, nbytes=2 << 30, blocks_per_cu=b, iters=3)
+                                for b in (2, 4, 8, 16)), 1)
+                   for k in ("read", "write", "copy")}
+        roofline["measured_ceiling_gbs"] = ceiling
+        roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["copy"], 4)
+
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
-        cpu = cpu_baseline(p, mask, rho, C, args.cpu_steps)
+        cpu = cpu_baseline(p, mask, rho, C, args.cpu_steps, args.cpu_steps_single)
 
     out = {
         "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,

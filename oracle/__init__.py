@@ -181,6 +181,13 @@ def guo(lattice, F, u):
     return out[:_q({"lattice": lattice})].copy()
 
 
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (n <= 0: leave as is); returns the count in effect."""
+    lib = _load()
+    lib.orc_set_threads.restype = ct.c_int
+    return int(lib.orc_set_threads(ct.c_int(int(n))))
+
+
 def psi(rho, rho0=1.0):
     """Pseudo-potential of eq:1.11."""
     return _load().orc_psi(float(rho), float(rho0))

@@ -141,6 +141,21 @@ static sol_lat make_sol(int lattice, double J0) {
     return S;
 }
 
+/* Threads of the OpenMP loops (the CPU-baseline leg times one thread and all
+ * host cores); returns the count now in effect. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Table export for the tests (velocities as int[Q][3], weights, opposites). */
 int orc_flow_lattice(int lattice, int* c, double* w, int* opp) {
     flow_lat L = make_flow(lattice);
