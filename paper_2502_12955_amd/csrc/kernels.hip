@@ -222,35 +222,43 @@ __device__ __forceinline__ SampleDev sample_of(const Geo& g, int ch) {
 // ---------------------------------------------------------------------------
 // density / pseudo-potential
 // ---------------------------------------------------------------------------
+// densities and pseudo-potentials of one 64-node chunk
+template <int LAT, int ST, int NC>
+__device__ __forceinline__ void density_chunk(const Phys<typename Store<ST>::R>& P, const Geo& g,
+                                              const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q],
+                                              const typename Store<ST>::T* __restrict__ fA,
+                                              typename Store<ST>::R* __restrict__ psi, int ch) {
+    using L = Lat<LAT>;
+    using S = Store<ST>;
+    using R = typename S::R;
+    // populations and pos first: every lane of a chunk is inside the
+    // (chunk-padded) arrays, so these loads need not wait for the sample
+    // record; tail lanes are discarded below
+    const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+    R rho[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        R r = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
+        rho[s] = r;
+    }
+    const unsigned n = g.pos[k];
+    const SampleDev sd = sample_of(g, ch);
+    if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
+    R* ps = psi + (size_t)NC * sd.dbase;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) ps[(size_t)n * NC + s] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
+}
+
 template <int LAT, int ST, int NC>
 __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, Geo g,
                                                  const typename Store<ST>::T* __restrict__ fA,
                                                  typename Store<ST>::R* __restrict__ psi) {
-    using L = Lat<LAT>;
-    using S = Store<ST>;
-    using R = typename S::R;
-    R sh[NC][L::Q];
+    using R = typename Store<ST>::R;
+    R sh[NC][Lat<LAT>::Q];
     load_shifts<LAT, ST, NC>(P, sh);
-    for_each_chunk(g, [&](int ch) {
-        // populations and pos first: every lane of a chunk is inside the
-        // (chunk-padded) arrays, so these loads need not wait for the sample
-        // record; tail lanes are discarded below
-        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
-        R rho[NC];
-#pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            R r = 0;
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
-            rho[s] = r;
-        }
-        const unsigned n = g.pos[k];
-        const SampleDev sd = sample_of(g, ch);
-        if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
-        R* ps = psi + (size_t)NC * sd.dbase;
-#pragma unroll
-        for (int s = 0; s < NC; ++s) ps[(size_t)n * NC + s] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
-    });
+    for_each_chunk(g, [&](int ch) { density_chunk<LAT, ST, NC>(P, g, sh, fA, psi, ch); });
 }
 
 // ---------------------------------------------------------------------------
@@ -283,8 +291,9 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
         for (int s = 0; s < NC; ++s) io.fstore(s * Q + dir, kd, f[s][i], sh[s][i]);  // w_i = w_opp(i)
     }
     if (P.solute) {
-        // loaded only now: fewer registers live through the flow part
-        constexpr int HP = QS * (1 + PR);   // solute planes per node (= P.hplanes)
+        // loaded only now: fewer registers live through the flow part (loading
+        // them with the flow populations was measured 0.5 % slower in FP32 and
+        // 4 % slower with 16-bit storage)
         R h[QS];
 #pragma unroll
         for (int q = 0; q < QS; ++q) h[q] = io.hload(q, k);
@@ -366,10 +375,84 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
+// collision and push of one 64-node chunk
+template <int LAT, int ST, int NC, int FC, int SV, int BUF>
+__device__ __forceinline__ void collide_chunk(const Phys<typename Store<ST>::R>& P, const Geo& g,
+                                              const typename Store<ST>::R (&sh)[NC][Lat<LAT>::Q],
+                                              const typename Store<ST>::T* __restrict__ fA,
+                                              typename Store<ST>::T* __restrict__ fB,
+                                              const typename Store<ST>::T* __restrict__ hA,
+                                              typename Store<ST>::T* __restrict__ hB,
+                                              const typename Store<ST>::R* __restrict__ psi, uint32_t fbytes,
+                                              uint32_t hbytes, const typename Store<ST>::T* __restrict__ gA,
+                                              typename Store<ST>::T* __restrict__ gB, uint32_t gbytes, int ch) {
+    using L = Lat<LAT>;
+    using S = Store<ST>;
+    using R = typename S::R;
+    constexpr int Q = L::Q, PF = NC * Q, QS = L::QS, HP = QS * (1 + (SV & 1));
+    // No tail check: the lanes past a sample's last fluid node (up to the
+    // 64-node chunk boundary) carry pos 0 and a link word with every flow
+    // link blocked, so they read inside the sample and store only into
+    // their own (unused) slots.  Node-local loads are issued first.
+    const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
+    const unsigned n = g.pos[k];
+    const uint32_t lw = g.links[k];
+    R f[NC][Q];
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t fr = make_rsrc(fA, fbytes);
+        const uint32_t vo = BufIO<ST, PF, HP>::template node_off<PF>(k);
+#pragma unroll
+        for (int s = 0; s < NC; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const R v = BufBits<ST>::template ld<2>(fr, vo, (uint32_t)(s * Q + i) * BufIO<ST, PF, HP>::PS);
+                f[s][i] = (ST >= ST_F16S) ? v + sh[s][i] : v;
+            }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NC; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
+    }
+    const SampleDev sd = sample_of(g, ch);
+    int x, y, z;
+    coords(n, sd.nx, sd.ny, x, y, z);
+    const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
+    const int* mp = g.map + sd.dbase;
+    const R* ps = psi + (size_t)NC * sd.dbase;
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t mr = make_rsrc(mp, (uint32_t)sd.N * 4u);
+        const __amdgpu_buffer_rsrc_t pr = make_rsrc(ps, (uint32_t)sd.N * (uint32_t)(NC * sizeof(R)));
+        auto psi_nb = [&](int t, int i) -> R {
+            const uint32_t o = nb.at(L::cx[i], L::cy[i], L::cz[i]) * (uint32_t)(NC * sizeof(R)) + t * sizeof(R);
+            if constexpr (sizeof(R) == 8) return BufBits<ST_F64>::template ld<0>(pr, o, 0);
+            else return BufBits<ST_F32>::template ld<0>(pr, o, 0);
+        };
+        auto dest = [&](int i) -> unsigned {
+            return __builtin_amdgcn_raw_buffer_load_b32(mr, nb.at(L::cx[i], L::cy[i], L::cz[i]) * 4u, 0, 0);
+        };
+        BufIO<ST, PF, HP> io;
+        io.fB = make_rsrc(fB, fbytes);
+        io.hA = make_rsrc(hA, hbytes);
+        io.hB = make_rsrc(hB, hbytes);
+        io.gA = make_rsrc(gA, gbytes);
+        io.gB = make_rsrc(gB, gbytes);
+        collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest,
+                                                                              io);
+    } else {
+        auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
+        auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
+        const GlobalIO<ST, PF, HP> io{fB, hA, hB, gA, gB};
+        collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest,
+                                                                              io);
+    }
+}
+
 // FC: forcing scheme (0 Guo, 1 Shan-Chen); SV: solute variant, bit 0 the
-// product species, bit 1 the per-node rate field (each compiled in or out, so
-// the plain path keeps its registers and schedule); BUF: buffer addressing
-// (BufIO, every array below 4 GiB) or flat addresses (GlobalIO)
+// product species, bit 1 the per-node rate field, bit 2 conjugate heat transfer
+// (each compiled in or out, so the plain path keeps its registers and
+// schedule); BUF: buffer addressing (BufIO, every array below 4 GiB) or flat
+// addresses (GlobalIO)
 template <int LAT, int ST, int NC, int FC, int SV, int BUF>
 __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, Geo g,
                                                  const typename Store<ST>::T* __restrict__ fA,
@@ -380,72 +463,13 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
                                                  uint32_t fbytes, uint32_t hbytes,
                                                  const typename Store<ST>::T* __restrict__ gA,
                                                  typename Store<ST>::T* __restrict__ gB, uint32_t gbytes) {
-    using L = Lat<LAT>;
-    using S = Store<ST>;
-    using R = typename S::R;
-    constexpr int Q = L::Q, PF = NC * Q, QS = L::QS, HP = QS * (1 + (SV & 1));
-    R sh[NC][Q];
+    using R = typename Store<ST>::R;
+    R sh[NC][Lat<LAT>::Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
-        // No tail check: the lanes past a sample's last fluid node (up to the
-        // 64-node chunk boundary) carry pos 0 and a link word with every flow
-        // link blocked, so they read inside the sample and store only into
-        // their own (unused) slots.  Node-local loads are issued first.
-        const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
-        const unsigned n = g.pos[k];
-        const uint32_t lw = g.links[k];
-        R f[NC][Q];
-        if constexpr (BUF) {
-            const __amdgpu_buffer_rsrc_t fr = make_rsrc(fA, fbytes);
-            const uint32_t vo = BufIO<ST, PF, HP>::template node_off<PF>(k);
-#pragma unroll
-            for (int s = 0; s < NC; ++s)
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const R v = BufBits<ST>::template ld<2>(fr, vo, (uint32_t)(s * Q + i) * BufIO<ST, PF, HP>::PS);
-                    f[s][i] = (ST >= ST_F16S) ? v + sh[s][i] : v;
-                }
-        } else {
-#pragma unroll
-            for (int s = 0; s < NC; ++s)
-#pragma unroll
-                for (int i = 0; i < Q; ++i) f[s][i] = S::load(blk(fA, PF, s * Q + i, k), sh[s][i]);
-        }
-        const SampleDev sd = sample_of(g, ch);
-        int x, y, z;
-        coords(n, sd.nx, sd.ny, x, y, z);
-        const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
-        const int* mp = g.map + sd.dbase;
-        const R* ps = psi + (size_t)NC * sd.dbase;
-        if constexpr (BUF) {
-            const __amdgpu_buffer_rsrc_t mr = make_rsrc(mp, (uint32_t)sd.N * 4u);
-            const __amdgpu_buffer_rsrc_t pr = make_rsrc(ps, (uint32_t)sd.N * (uint32_t)(NC * sizeof(R)));
-            auto psi_nb = [&](int t, int i) -> R {
-                const uint32_t o = nb.at(L::cx[i], L::cy[i], L::cz[i]) * (uint32_t)(NC * sizeof(R)) + t * sizeof(R);
-                if constexpr (sizeof(R) == 8) return BufBits<ST_F64>::template ld<0>(pr, o, 0);
-                else return BufBits<ST_F32>::template ld<0>(pr, o, 0);
-            };
-            auto dest = [&](int i) -> unsigned {
-                return __builtin_amdgcn_raw_buffer_load_b32(mr, nb.at(L::cx[i], L::cy[i], L::cz[i]) * 4u, 0, 0);
-            };
-            BufIO<ST, PF, HP> io;
-            io.fB = make_rsrc(fB, fbytes);
-            io.hA = make_rsrc(hA, hbytes);
-            io.hB = make_rsrc(hB, hbytes);
-            io.gA = make_rsrc(gA, gbytes);
-            io.gB = make_rsrc(gB, gbytes);
-            collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb,
-                                                                                  dest, io);
-        } else {
-            auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
-            auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
-            const GlobalIO<ST, PF, HP> io{fB, hA, hB, gA, gB};
-            collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb,
-                                                                                  dest, io);
-        }
+        collide_chunk<LAT, ST, NC, FC, SV, BUF>(P, g, sh, fA, fB, hA, hB, psi, fbytes, hbytes, gA, gB, gbytes, ch);
     });
 }
-
 
 // ---------------------------------------------------------------------------
 // initialisation at equilibrium (no force term) from dense staging fields
@@ -835,8 +859,7 @@ static hipError_t step_t(const Ctx& c) {
     const Geo g = make_geo(c, true);
     const int bs = c.block > 0 ? c.block : 256;
     const dim3 grid = grid_for(c, bs, true);
-    hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
-                       (SR<ST>*)c.psi);
+
     // the collide pass walks the chunks in the opposite order of the density
     // pass, so it starts on the chunks the density pass read last
     Geo gr = g;
@@ -857,6 +880,8 @@ static hipError_t step_t(const Ctx& c) {
                    gb32 = (uint32_t)(buf ? gbytes : 0);
     const STT<ST>* gA = (const STT<ST>*)c.gA;
     STT<ST>* gB = (STT<ST>*)c.gB;
+    hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
+                       (SR<ST>*)c.psi);
 #define MCLBM_COLLIDE(FC, SV)                                                                                    \
     do {                                                                                                         \
         if (buf)                                                                                                 \
