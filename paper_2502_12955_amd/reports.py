@@ -1,6 +1,6 @@
 """Measurement studies beyond the single-lattice benchmark.
 
-    python -m paper_2502_12955_amd.reports precision [--n 384 --steps 10000]
+    python -m paper_2502_12955_amd.reports precision [--n 384 --steps 20000]
         Reduced-precision storage (FP16 / BF16 shifted, FP32) against an FP64
         run on the GPU from the same state: per-field max-abs and RMS error
         over fluid nodes after ``steps``, throughput of each storage, and the
@@ -200,10 +200,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="what", required=True)
     a = sub.add_parser("precision")
     a.add_argument("--n", type=int, default=384)
-    # the 384^3 two-phase case goes non-finite near step 13,000 in FP64 as well
-    # as FP32 (a physical instability of this parameter set), so the
-    # comparison is taken at 10,000 steps
-    a.add_argument("--steps", type=int, default=10000)
+    a.add_argument("--steps", type=int, default=20000)
     a.add_argument("--storages", nargs="+", default=["f32", "f16s", "bf16s"])
     a.add_argument("--res-n", type=int, default=128)
     a.add_argument("--tol", type=float, default=1e-6)

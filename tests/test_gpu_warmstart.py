@@ -21,7 +21,9 @@ TOL = 1e-3
 
 
 def test_restart_from_converged_fields_needs_few_steps():
-    samples = warmstart.make_samples(N, 3, first=500)
+    # 64^3: at 32^3 the flows settle within ~4,000 steps from rest, which leaves
+    # the restart transient (~2,000 steps) no room below half of that
+    samples = warmstart.make_samples(64, 3, first=500)
     cold = warmstart.solve(samples, TOL, 60000)
     assert all(s > 0 for s in cold["steps"]), cold["steps"]
     init = []
@@ -31,7 +33,7 @@ def test_restart_from_converged_fields_needs_few_steps():
     print("cold", cold["steps"], "restart", warm["steps"], flush=True)
     # equilibrium populations at the converged (rho, u) are not the converged
     # populations (no non-equilibrium part), so even this perfect macroscopic
-    # prediction needs a relaxation transient: ~0.25-0.4 of the cold steps here
+    # prediction needs a relaxation transient: ~0.3-0.4 of the cold steps here
     assert all(0 < w <= 0.5 * c for w, c in zip(warm["steps"], cold["steps"]))
 
 
