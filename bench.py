@@ -117,10 +117,10 @@ def main():
     lat = mclbm.Lattice(p)
     nrc = lat.set_geometry(mask)
     if args.block == 0:
-        blk, grd, ms = lat.autotune(trial_steps=10)
-        log(f"[bench] autotuned launch shape: block {blk}, grid {grd} ({ms:.3f} ms/step)")
+        nb, blk, grd, ms = lat.autotune(trial_steps=10)
+        log(f"[bench] tuned: {nb or 8} bands, block {blk}, grid {grd} ({ms:.3f} ms/step)")
     else:
-        blk, grd = args.block, args.grid
+        nb, blk, grd = 0, args.block, args.grid
         lat.set_launch(blk, grd)
     gmask, _, _ = lat.get_geometry()
     nfluid = int((gmask == 0).sum())
@@ -186,7 +186,7 @@ def main():
                                f"Boolean sphere pack porosity 0.4 R=8, Guo forcing, body force x 1e-5, "
                                f"wall reaction k=1e-3, inlet/outlet solute",
                    "nodes": N, "fluid_nodes": nfluid, "storage": args.storage,
-                   "launch": {"block": blk, "grid": grd},
+                   "launch": {"block": blk, "grid": grd, "bands": nb or 8},
                    "mflups": round(nfluid / (ms_per_step * 1e-3) / 1e6, 1),
                    "monitor_every": p["monitor_every"], "final_residual": float(mon[9])},
         "roofline": roofline,

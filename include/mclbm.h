@@ -271,20 +271,34 @@ int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks
  * values. */
 int mclbm_set_addressing(mclbm_handle* h, int32_t flat);
 
-/* Time the step kernels over a set of launch shapes and keep the fastest.
- * Candidates: block_threads 64, 128, 256 crossed with grid_blocks 0 (one
- * pass) and persistent grids of 8, 16 and 32 wavefronts per compute unit.
- * Each candidate runs 2 untimed steps, then
- * trial_steps (>= 1) steps timed with HIP events on the handle's stream.
- * Needs set_geometry; it overwrites the populations (uniform rest state,
- * density 1), so init_fields must be called afterwards (ESTATE until then).
- * The chosen shape is applied as by mclbm_set_launch and returned in
+/* Number of y-bands of the fluid numbering (the fluid nodes of a sample are
+ * numbered band by band, each band plane by plane, row by row, x fastest;
+ * a band has at least 4 rows).  bands = 0 (default): eight, one per XCD;
+ * else 1 .. 64.  With the geometry already set the fluid nodes are numbered
+ * again at once, as by mclbm_set_geometry on the current masks: the fields
+ * must be initialised again (ESTATE until init_fields), a per-node rate field
+ * returns to k_wall and deposits to 0.  Results do not depend on the
+ * numbering (every node takes the same arithmetic; only the order of the
+ * monitors' reductions changes).  EINVAL outside 0 .. 64. */
+int mclbm_set_bands(mclbm_handle* h, int32_t bands);
+
+/* Time the step kernels over a set of numberings and launch shapes and keep
+ * the fastest.  Launch shapes: block_threads 64, 128, 256 crossed with
+ * grid_blocks 0 (one pass) and persistent grids of 8, 16 and 32 wavefronts
+ * per compute unit.  Numberings: the current band count, and eight, four and
+ * sixteen bands unless a per-node rate field, deposition or conjugate heat
+ * transfer is on (numbering again would discard their state).  Each
+ * candidate runs 2 untimed steps, then trial_steps (>= 1) steps timed with
+ * HIP events on the handle's stream.  Needs set_geometry; it overwrites the
+ * populations (uniform rest state, density 1), so init_fields must be called
+ * afterwards (ESTATE until then).  The chosen numbering and shape are applied
+ * as by mclbm_set_bands and mclbm_set_launch and returned in *bands,
  * *block_threads, *grid_blocks and *ms_per_step (any may be NULL).  The
- * candidates' timings are written to table[3 * i + 0..2] = (block, grid, ms
- * per step) for i < table_rows (table may be NULL); *n_rows (may be NULL)
- * receives the number of candidates. */
-int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
-                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
+ * candidates' timings are written to table[4 * i + 0..3] = (bands, block,
+ * grid, ms per step) for i < table_rows (table may be NULL); *n_rows (may be
+ * NULL) receives the number of candidates. */
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* bands, int32_t* block_threads,
+                   int32_t* grid_blocks, double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows);
 
 /* enable != 0: run each aligned interval of monitor_every steps (which must
  * be even) as one replay of a captured HIP graph (the step kernels plus the

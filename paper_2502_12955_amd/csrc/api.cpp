@@ -117,6 +117,7 @@ struct mclbm_handle {
     double mon[16];
     double rhobar[2] = {0, 0};
     int block = 256, grid = 0;
+    int bands = 0;                  // y-bands of the fluid numbering (0: eight, one per XCD)
     int flat = 0;                   // 1: flat 64-bit addressing in the collide pass
     // conjugate heat transfer (library-owned device memory, allocated in set_geometry)
     bool thermal = false, temp_set = false;
@@ -717,7 +718,7 @@ static void free_thermal(mclbm_handle* h) {
     h->temp_set = false;
 }
 
-static int band_rows(int ny);
+static int band_rows(int ny, int bands);
 
 // Build the solid list, the interface list and the thermal arrays for the
 // current geometry (single lattice).  `map` is the box -> fluid index map.
@@ -728,7 +729,7 @@ static int build_thermal(mclbm_handle* h, const std::vector<int>& map) {
     std::vector<unsigned> spos, ibox;
     std::vector<int> smap;
     std::vector<uint32_t> msb;
-    thermal_lists(gs, sm.mask, band_rows(sm.ny), spos, smap, ibox, msb);
+    thermal_lists(gs, sm.mask, band_rows(sm.ny, h->bands), spos, smap, ibox, msb);
     const int Q = h->Q;
     const size_t sb = store_bytes(h->p.storage), ab = arith_bytes(h->p.storage);
     const long long nsol = (long long)spos.size(), ni = (long long)ibox.size();
@@ -791,9 +792,12 @@ static int build_thermal(mclbm_handle* h, const std::vector<int>& map) {
     return MCLBM_OK;
 }
 
-// rows per y-band of the fluid numbering: eight bands (one per XCD of a
-// single large lattice), at least 4 rows
-static int band_rows(int ny) { return std::max(4, (ny + 7) / 8); }
+// rows per y-band of the fluid numbering: `bands` bands (0: eight, one per
+// XCD of a single large lattice), at least 4 rows
+static int band_rows(int ny, int bands) {
+    const int nb = bands > 0 ? bands : 8;
+    return std::max(4, (ny + nb - 1) / nb);
+}
 
 static uint32_t tail_link_word(int lattice) {
     const int Q = flow_q(lattice);
@@ -827,7 +831,7 @@ int mclbm_set_geometry(mclbm_handle* h, const uint8_t* solid_mask, int64_t* n_re
         // indices) and its pushes across planes stay in the L2 cache of the
         // XCD that sweeps the band.
         sm.pos.clear();
-        const int rows = band_rows(sm.ny);
+        const int rows = band_rows(sm.ny, h->bands);
         for (int y0 = 0; y0 < sm.ny; y0 += rows)
             for (int z = 0; z < sm.nz; ++z)
                 for (int y = y0; y < std::min(sm.ny, y0 + rows); ++y)
@@ -1451,25 +1455,43 @@ int mclbm_set_addressing(mclbm_handle* h, int32_t flat) {
     return MCLBM_OK;
 }
 
-int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads, int32_t* grid_blocks,
-                   double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
+// Numbers the fluid nodes again with the current band count: set_geometry on
+// the current (reclassified) masks of every sample.
+static int renumber(mclbm_handle* h) {
+    std::vector<uint8_t> mask((size_t)h->Ntot, 0);
+    for (auto& sm : h->smp) std::copy(sm.mask.begin(), sm.mask.end(), mask.begin() + sm.dbase);
+    return mclbm_set_geometry(h, mask.data(), nullptr);
+}
+
+int mclbm_set_bands(mclbm_handle* h, int32_t bands) {
+    if (!h) return MCLBM_EINVAL;
+    if (bands < 0 || bands > 64) return fail(h, MCLBM_EINVAL, "bands must be 0 (eight) or 1 .. 64");
+    if (bands == h->bands) return MCLBM_OK;
+    h->bands = bands;
+    return h->geom_set ? renumber(h) : MCLBM_OK;
+}
+
+int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* bands, int32_t* block_threads,
+                   int32_t* grid_blocks, double* ms_per_step, double* table, int32_t table_rows, int32_t* n_rows) {
     if (!h) return MCLBM_EINVAL;
     if (!h->geom_set) return fail(h, MCLBM_ESTATE, "set_geometry has not been called");
     if (trial_steps < 1) return fail(h, MCLBM_EINVAL, "trial_steps must be >= 1");
-    {
-        std::vector<double> rho((size_t)h->NC * h->Ntot, 1.0);
-        int rc = mclbm_init_fields(h, rho.data(), nullptr, nullptr);
-        if (rc != MCLBM_OK) return rc;
-    }
     int dev = 0, cus = 0;
     HIPCHK(h, hipGetDevice(&dev));
     HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    std::vector<std::pair<int, int>> cand;
+    // band counts: the current one first; the others only where numbering the
+    // fluid nodes again loses no caller state (rate field, deposits, heat)
+    const int old_bands = h->bands;
+    std::vector<int> band_cand{old_bands};
+    if (!h->kfield && !h->dep && !h->thermal)
+        for (int nb : {0, 4, 16})
+            if (nb != old_bands) band_cand.push_back(nb);
+    std::vector<std::pair<int, int>> shapes;
     for (int b : {64, 128, 256}) {
-        cand.push_back({b, 0});
+        shapes.push_back({b, 0});
         for (int w : {8, 16, 32}) {
             const int g = (cus * w / (b / 64) + 7) / 8 * 8;
-            if (g > 0) cand.push_back({b, g});
+            if (g > 0) shapes.push_back({b, g});
         }
     }
     hipEvent_t e0, e1;
@@ -1480,34 +1502,53 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads,
     }
     const int old_block = h->block, old_grid = h->grid;
     double best = INFINITY;
-    int bb = old_block, bg = old_grid, rc = MCLBM_OK;
-    for (size_t i = 0; i < cand.size() && rc == MCLBM_OK; ++i) {
-        h->block = cand[i].first;
-        h->grid = cand[i].second;
-        for (int s = 0; s < 2 && rc == MCLBM_OK; ++s) rc = launch_step(h, h->stream);
-        if (rc != MCLBM_OK) break;
-        hipError_t e = hipEventRecord(e0, h->stream);
-        for (int s = 0; s < trial_steps && rc == MCLBM_OK && e == hipSuccess; ++s) rc = launch_step(h, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess && rc == MCLBM_OK) rc = hip_fail(h, e, "autotune timing");
-        if (rc != MCLBM_OK) break;
-        const double per = (double)ms / trial_steps;
-        if (table && (int)i < table_rows) {
-            table[3 * i + 0] = cand[i].first;
-            table[3 * i + 1] = cand[i].second;
-            table[3 * i + 2] = per;
+    int bn = old_bands, bb = old_block, bg = old_grid, rc = MCLBM_OK;
+    size_t row = 0;
+    for (size_t bi = 0; bi < band_cand.size() && rc == MCLBM_OK; ++bi) {
+        if (band_cand[bi] != h->bands) {
+            h->bands = band_cand[bi];
+            rc = renumber(h);
+            if (rc != MCLBM_OK) break;
         }
-        if (per < best) {
-            best = per;
-            bb = cand[i].first;
-            bg = cand[i].second;
+        {
+            std::vector<double> rho((size_t)h->NC * h->Ntot, 1.0);
+            rc = mclbm_init_fields(h, rho.data(), nullptr, nullptr);
+            if (rc != MCLBM_OK) break;
+        }
+        for (size_t i = 0; i < shapes.size() && rc == MCLBM_OK; ++i, ++row) {
+            h->block = shapes[i].first;
+            h->grid = shapes[i].second;
+            for (int s = 0; s < 2 && rc == MCLBM_OK; ++s) rc = launch_step(h, h->stream);
+            if (rc != MCLBM_OK) break;
+            hipError_t e = hipEventRecord(e0, h->stream);
+            for (int s = 0; s < trial_steps && rc == MCLBM_OK && e == hipSuccess; ++s) rc = launch_step(h, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess && rc == MCLBM_OK) rc = hip_fail(h, e, "autotune timing");
+            if (rc != MCLBM_OK) break;
+            const double per = (double)ms / trial_steps;
+            if (table && (int)row < table_rows) {
+                table[4 * row + 0] = band_cand[bi];
+                table[4 * row + 1] = shapes[i].first;
+                table[4 * row + 2] = shapes[i].second;
+                table[4 * row + 3] = per;
+            }
+            if (per < best) {
+                best = per;
+                bn = band_cand[bi];
+                bb = shapes[i].first;
+                bg = shapes[i].second;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc == MCLBM_OK && h->bands != bn) {
+        h->bands = bn;
+        rc = renumber(h);
+    }
     h->fields_set = false;
     h->step = 0;
     h->snap_valid = false;
@@ -1519,10 +1560,11 @@ int mclbm_autotune(mclbm_handle* h, int32_t trial_steps, int32_t* block_threads,
     }
     h->block = bb;
     h->grid = bg;
+    if (bands) *bands = bn;
     if (block_threads) *block_threads = bb;
     if (grid_blocks) *grid_blocks = bg;
     if (ms_per_step) *ms_per_step = best;
-    if (n_rows) *n_rows = (int32_t)cand.size();
+    if (n_rows) *n_rows = (int32_t)row;
     return MCLBM_OK;
 }
 

@@ -119,7 +119,7 @@ _lib = None
 EXPORTS = ("mclbm_required_bytes", "mclbm_init_lattice", "mclbm_set_geometry", "mclbm_get_geometry",
            "mclbm_init_fields", "mclbm_step", "mclbm_get_moments", "mclbm_get_monitors",
            "mclbm_monitor_now", "mclbm_get_populations", "mclbm_set_populations",
-           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_graph",
+           "mclbm_population_bytes", "mclbm_run_to_residual", "mclbm_set_launch", "mclbm_set_bands", "mclbm_set_graph",
            "mclbm_required_bytes_batch", "mclbm_init_batch", "mclbm_get_sample_monitors", "mclbm_get_step",
            "mclbm_synchronize", "mclbm_autotune", "mclbm_set_wall_rate", "mclbm_get_deposit", "mclbm_set_deposit", "mclbm_destroy",
            "mclbm_last_error", "mclbm_hbm_probe", "mclbm_set_addressing", "mclbm_set_thermal",
@@ -154,6 +154,7 @@ def load(path: str = LIB_PATH):
     lib.mclbm_population_bytes.argtypes = [vp, i32, ct.POINTER(sz)]
     lib.mclbm_run_to_residual.argtypes = [vp, dbl, i64, ct.POINTER(i64)]
     lib.mclbm_set_launch.argtypes = [vp, i32, i32]
+    lib.mclbm_set_bands.argtypes = [vp, i32]
     lib.mclbm_set_graph.argtypes = [vp, i32]
     lib.mclbm_set_addressing.argtypes = [vp, i32]
     lib.mclbm_set_thermal.argtypes = [vp, ct.POINTER(ThermalParams)]
@@ -166,8 +167,8 @@ def load(path: str = LIB_PATH):
     lib.mclbm_get_sample_monitors.argtypes = [vp, i32, vp]
     lib.mclbm_get_step.argtypes = [vp, ct.POINTER(i64)]
     lib.mclbm_synchronize.argtypes = [vp]
-    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp, i32,
-                                   ct.POINTER(i32)]
+    lib.mclbm_autotune.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(dbl), vp,
+                                   i32, ct.POINTER(i32)]
     lib.mclbm_hbm_probe.argtypes = [i32, vp, vp, sz, i32, i32, vp, ct.POINTER(dbl)]
     lib.mclbm_destroy.argtypes = [vp]
     lib.mclbm_destroy.restype = None
@@ -333,18 +334,23 @@ def set_launch(h, block_threads=256, grid_blocks=0):
     _check(load().mclbm_set_launch(h, int(block_threads), int(grid_blocks)), h)
 
 
+def set_bands(h, bands=0):
+    _check(load().mclbm_set_bands(h, int(bands)), h)
+
+
 def set_addressing(h, flat: bool):
     _check(load().mclbm_set_addressing(h, int(bool(flat))), h)
 
 
 def autotune(h, trial_steps=20):
-    """Native launch-shape tuner; returns (block, grid, ms_per_step, table rows (block, grid, ms))."""
-    b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    """Native tuner of the numbering and launch shape; returns (bands, block, grid,
+    ms_per_step, table rows (bands, block, grid, ms))."""
+    nb, b, g, n = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
     ms = ct.c_double()
-    table = np.zeros((64, 3))
-    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(b), ct.byref(g), ct.byref(ms), _ptr(table), 64,
-                                 ct.byref(n)), h)
-    return b.value, g.value, ms.value, table[: n.value].tolist()
+    table = np.zeros((128, 4))
+    _check(load().mclbm_autotune(h, int(trial_steps), ct.byref(nb), ct.byref(b), ct.byref(g), ct.byref(ms),
+                                 _ptr(table), 128, ct.byref(n)), h)
+    return nb.value, b.value, g.value, ms.value, table[: n.value].tolist()
 
 
 def tune_key(plist):
@@ -471,6 +477,9 @@ class Lattice:
     def set_launch(self, block_threads=256, grid_blocks=0):
         set_launch(self.h, block_threads, grid_blocks)
 
+    def set_bands(self, bands=0):
+        set_bands(self.h, bands)
+
     def set_graph(self, enable=True):
         set_graph(self.h, enable)
 
@@ -507,11 +516,13 @@ class Lattice:
 
 
     def autotune(self, trial_steps=20, cache_path=None):
-        """Choose the launch shape (after set_geometry; init_fields must follow).
+        """Choose the band count of the numbering and the launch shape (after
+        set_geometry; init_fields must follow).
 
-        With ``cache_path`` (a JSON file), a shape already chosen for the same
+        With ``cache_path`` (a JSON file), a choice already made for the same
         physics and size class is reused without timing, and new choices are
-        added to the file.  Returns (block, grid, ms_per_step or None if cached)."""
+        added to the file.  Returns (bands, block, grid, ms_per_step or None if
+        cached)."""
         import json
 
         key = tune_key(getattr(self, "plist", [self.params]))
@@ -520,15 +531,16 @@ class Lattice:
             with open(cache_path) as f:
                 cache = json.load(f)
         if key in cache:
-            b, g = cache[key]["block"], cache[key]["grid"]
+            nb, b, g = cache[key]["bands"], cache[key]["block"], cache[key]["grid"]
+            self.set_bands(nb)
             self.set_launch(b, g)
-            return b, g, None
-        b, g, ms, table = autotune(self.h, trial_steps)
+            return nb, b, g, None
+        nb, b, g, ms, table = autotune(self.h, trial_steps)
         if cache_path:
-            cache[key] = dict(block=b, grid=g, ms_per_step=ms, table=table)
+            cache[key] = dict(bands=nb, block=b, grid=g, ms_per_step=ms, table=table)
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)
-        return b, g, ms
+        return nb, b, g, ms
 
     @property
     def step_count(self):

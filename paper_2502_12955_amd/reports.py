@@ -137,7 +137,7 @@ def batch(args):
     fluid = int(b.monitors()[8])
     ms = _timed_steps(b, args.steps)
     out["fluid_nodes"] = fluid
-    out["batched"] = dict(launch=dict(block=tuned[0], grid=tuned[1]), ms_per_step=ms / args.steps,
+    out["batched"] = dict(launch=dict(bands=tuned[0] or 8, block=tuned[1], grid=tuned[2]), ms_per_step=ms / args.steps,
                           mlups=nodes / (ms / args.steps * 1e-3) / 1e6,
                           mflups=fluid / (ms / args.steps * 1e-3) / 1e6)
     b.close()
@@ -157,8 +157,9 @@ def batch(args):
     print(f"[batch] sequential: {seq_ms / args.steps:.3f} ms/step", flush=True)
 
     b = mclbm.Batch([c[0] for c in cases])
+    b.set_bands(tuned[0])
     b.set_geometry([c[1] for c in cases])
-    b.set_launch(tuned[0], tuned[1])
+    b.set_launch(tuned[1], tuned[2])
     b.set_graph(True)
     b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
     b.synchronize()

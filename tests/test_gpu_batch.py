@@ -150,8 +150,8 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     b = mclbm.Batch([c[0] for c in cases])
     b.set_geometry([c[1] for c in cases])
     cache = str(tmp_path / "tune.json")
-    blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
-    assert blk in (64, 128, 256) and grid % 8 == 0 and ms > 0
+    nb, blk, grid, ms = b.autotune(trial_steps=4, cache_path=cache)
+    assert nb in (0, 4, 16) and blk in (64, 128, 256) and grid % 8 == 0 and ms > 0
     with pytest.raises(mclbm.MclbmError) as e:      # populations were overwritten
         b.step(1)
     assert e.value.code == mclbm.ESTATE
@@ -163,9 +163,39 @@ def test_autotune_picks_a_candidate_and_keeps_results_identical(tmp_path):
     # a second handle of the same class takes the cached shape without timing
     b2 = mclbm.Batch([c[0] for c in cases])
     b2.set_geometry([c[1] for c in cases])
-    assert b2.autotune(trial_steps=4, cache_path=cache) == (blk, grid, None)
+    assert b2.autotune(trial_steps=4, cache_path=cache) == (nb, blk, grid, None)
     for x in (b, b2, ref):
         x.close()
+
+
+def test_band_count_changes_the_numbering_not_the_results():
+    """The fluid numbering's band count (1, 4, 16 bands, and 16 set again after
+    the geometry, which numbers the nodes anew) leaves every population
+    bit-identical to the default eight bands; monitors agree to rounding."""
+    cases = _samples(3, seed=57)
+    ref = _batch(cases)
+    ref.step(12)
+    want = ref.populations(raw=True)
+    mref = ref.monitors()
+    ref.close()
+    for nb, after in ((1, False), (4, False), (16, False), (16, True)):
+        b = mclbm.Batch([c[0] for c in cases])
+        if not after:
+            b.set_bands(nb)
+        b.set_geometry([c[1] for c in cases])
+        if after:
+            b.set_bands(nb)
+        b.init_fields([c[2] for c in cases], None, [c[3] for c in cases])
+        b.step(12)
+        assert np.array_equal(b.populations(raw=True), want), nb
+        m = b.monitors()
+        assert np.allclose(m[1:10], mref[1:10], rtol=1e-12, atol=0), nb
+        b.close()
+    b = mclbm.Batch([c[0] for c in cases])
+    with pytest.raises(mclbm.MclbmError) as e:
+        b.set_bands(65)
+    assert e.value.code == mclbm.EINVAL
+    b.close()
 
 
 def test_a_diverged_sample_is_frozen_and_the_others_finish():

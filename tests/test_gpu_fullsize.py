@@ -73,12 +73,16 @@ def test_full_size_sampled_step_matches_oracle(workload, storage, tol):
 def test_full_size_every_autotune_shape_is_bit_identical(workload):
     p, mask, m, rho, C = workload
     ref = None
-    shapes = [(256, 0)]
     lat = mclbm.Lattice(p)
     lat.set_geometry(mask)
     *_, table = mclbm.autotune(lat.h, 1)
-    shapes += [(int(b), int(g)) for b, g, _ in table]
-    for blk, grid in shapes:
+    bands = sorted({int(r[0]) for r in table})
+    assert bands == [0, 4, 16]
+    # every launch shape with the default numbering, then each other numbering once
+    shapes = [(0, 256, 0)] + [(0, int(b), int(g)) for nb, b, g, _ in table if nb == 0]
+    shapes += [(nb, 256, 0) for nb in bands if nb != 0]
+    for nb, blk, grid in shapes:
+        lat.set_bands(nb)
         lat.set_launch(blk, grid)
         lat.init_fields(rho, None, C)
         lat.step(2)
@@ -86,8 +90,9 @@ def test_full_size_every_autotune_shape_is_bit_identical(workload):
         if ref is None:
             ref = pops
         else:
-            assert np.array_equal(pops, ref), (blk, grid)
+            assert np.array_equal(pops, ref), (nb, blk, grid)
     # flat 64-bit addressing instead of buffer offsets: same values
+    lat.set_bands(0)
     lat.set_addressing(flat=True)
     lat.set_launch(256, 0)
     lat.init_fields(rho, None, C)
