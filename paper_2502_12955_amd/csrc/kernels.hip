@@ -281,11 +281,17 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
     constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
     R u[3];
     flow_collide<LAT, NC, R, decltype(psi_nb), FC>(P, lw, f, psi_nb, u);
+    // fluid indices of the 18 neighbours, gathered together before any store
+    // (a solid neighbour reads -1 and is not used), so the pushes wait for one
+    // round trip instead of one per direction
+    unsigned dst[Q];
+    dst[0] = k;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) dst[i] = dest(i);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
-        unsigned kd = k;
-        if (i != 0 && !bb) kd = dest(i);
+        const unsigned kd = (i != 0 && !bb) ? dst[i] : k;
         const int dir = bb ? L::opp[i] : i;
 #pragma unroll
         for (int s = 0; s < NC; ++s) io.fstore(s * Q + dir, kd, f[s][i], sh[s][i]);  // w_i = w_opp(i)
@@ -305,7 +311,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             const int dx = L::cx[d];
             const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
             if (!seam && !(lw & (1u << L::opp[d]))) {
-                const unsigned kd = dest(d);
+                const unsigned kd = dst[d];
                 io.hstore(d, kd, h[d]);
                 if (!TH && (lw & (1u << (L::HOP_SHIFT + d)))) {   // with heat: the interface solve
                     const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
@@ -331,7 +337,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
                 const int dx = L::cx[d];
                 const bool seam = seam_mode && ((x == nx - 1 && dx == 1) || (x == 0 && dx == -1));
                 if (!seam && !(lw & (1u << L::opp[d]))) {
-                    const unsigned kd = dest(d);
+                    const unsigned kd = dst[d];
                     io.hstore(QS + d, kd, h2[d]);
                     if (!TH && (lw & (1u << (L::HOP_SHIFT + d)))) {
                         const R Cb = R(2) * h[d] * (KF ? P.kfield[kd] : P.wet_inv_den);
@@ -367,7 +373,7 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
             if (i == 0)
                 io.template gstore<Q>(0, k, post);
             else if (!(lw & (1u << L::opp[i])))
-                io.template gstore<Q>(i, dest(i), post);
+                io.template gstore<Q>(i, dst[i], post);
         }
     }
 }
