@@ -516,6 +516,22 @@ int upload_work(mclbm_handle* h) {
     return MCLBM_OK;
 }
 
+static inline size_t blk_index(size_t P, size_t j, size_t k) { return ((k >> 6) * P + j) * 64 + (k & 63); }
+// flow arrays with 16-bit storage of two components pair the components of a
+// direction in one 32-bit word (the device-side fidx): element (j, k) at
+// ((k >> 6) Q + i) 128 + 2 (k & 63) + s with j = s Q + i
+static inline bool flow_pairs(const mclbm_handle* h) {
+    return (h->p.storage == MCLBM_F16_SHIFT || h->p.storage == MCLBM_BF16_SHIFT) && h->NC == 2;
+}
+static inline size_t flow_index(const mclbm_handle* h, size_t j, size_t k) {
+    const size_t Q = (size_t)h->Q;
+    if (flow_pairs(h)) {
+        const size_t s = j >= Q ? 1 : 0;
+        return ((k >> 6) * Q + (j - s * Q)) * 128 + 2 * (k & 63) + s;
+    }
+    return blk_index((size_t)h->NC * Q, j, k);
+}
+
 // Copy a frozen sample's current state into buffer B as well, so that later
 // A/B swaps keep presenting its final state.
 int mirror_sample(mclbm_handle* h, const SampleHost& s) {
@@ -1054,7 +1070,11 @@ static int convert_deposits(mclbm_handle* h) {
     int* d_from = (int*)h->dep_snap;
     HIPCHK(h, hipMemcpyAsync(d_from, fromp.data(), fromp.size() * 4, hipMemcpyHostToDevice, h->stream));
     const int sb = (int)store_bytes(h->p.storage);
-    HIPCHK(h, k_remap_planes(h->fB, h->fA, h->NC * h->Q, d_from, padded, sb, h->stream));
+    // paired 16-bit flow storage moves as Q planes of 32-bit words
+    if (flow_pairs(h))
+        HIPCHK(h, k_remap_planes(h->fB, h->fA, h->Q, d_from, padded, 2 * sb, h->stream));
+    else
+        HIPCHK(h, k_remap_planes(h->fB, h->fA, h->NC * h->Q, d_from, padded, sb, h->stream));
     std::swap(h->fA, h->fB);
     HIPCHK(h, k_remap_planes(h->hB, h->hA, h->HP, d_from, padded, sb, h->stream));
     std::swap(h->hA, h->hB);
@@ -1271,7 +1291,6 @@ int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes) {
 }
 
 // Position of (plane j, fluid node k) in a chunked fluid-only array with P planes.
-static inline size_t blk_index(size_t P, size_t j, size_t k) { return ((k >> 6) * P + j) * 64 + (k & 63); }
 
 int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw) {
     if (!h || !dst) return MCLBM_EINVAL;
@@ -1296,7 +1315,7 @@ int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw) {
             const int s = flow ? (int)(j / h->Q) : 0, i = flow ? (int)(j % h->Q) : 0;
             const float shift = flow ? shift_f32(c, s, i) : 0.0f;
             for (size_t k = 0; k < (size_t)sm.nf; ++k) {
-                const size_t q = blk_index(P, jj, (size_t)sm.kbase + k);
+                const size_t q = flow ? flow_index(h, j, (size_t)sm.kbase + k) : blk_index(P, jj, (size_t)sm.kbase + k);
                 const size_t o = j * N + sm.pos[k];
                 if (raw) {
                     memcpy(out + o * sb, src + q * sb, sb);
@@ -1337,7 +1356,7 @@ int mclbm_set_populations(mclbm_handle* h, const void* src, int32_t raw) {
             unsigned char* dstp = flow ? dev.data() : dev.data() + PF * M * eb;
             const size_t P = flow ? PF : PS, jj = flow ? j : j - PF;
             for (size_t k = 0; k < (size_t)sm.nf; ++k) {
-                const size_t q = blk_index(P, jj, (size_t)sm.kbase + k);
+                const size_t q = flow ? flow_index(h, j, (size_t)sm.kbase + k) : blk_index(P, jj, (size_t)sm.kbase + k);
                 const size_t o = j * N + sm.pos[k];
                 memcpy(dstp + q * eb, in + o * eb, eb);
             }

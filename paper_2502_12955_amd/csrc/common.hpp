@@ -87,6 +87,8 @@ template <>
 struct Store<ST_F16S> {
     using R = float;
     using T = __half;
+    __device__ static inline R from_bits(uint32_t b) { return __half2float(__ushort_as_half((unsigned short)b)); }
+    __device__ static inline uint32_t to_bits(R v) { return __half_as_ushort(__float2half_rn(v)); }
     __device__ static inline R load(const T* p, R shift) {
         return __half2float(__ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p))) + shift;
     }
@@ -121,6 +123,8 @@ template <>
 struct Store<ST_BF16S> {
     using R = float;
     using T = bf16_t;
+    __device__ static inline R from_bits(uint32_t b) { return bf16_to_float((uint16_t)b); }
+    __device__ static inline uint32_t to_bits(R v) { return float_to_bf16_rne(v); }
     __device__ static inline R load(const T* p, R shift) { return bf16_to_float(__builtin_nontemporal_load(&p->bits)) + shift; }
     __device__ static inline void store(T* p, R v, R shift) { p->bits = float_to_bf16_rne(v - shift); }
     __device__ static inline R load_plain(const T* p) { return bf16_to_float(__builtin_nontemporal_load(&p->bits)); }
@@ -166,6 +170,28 @@ struct Phys {
 template <typename T>
 __device__ __forceinline__ T* blk(T* base, int P, int j, unsigned k) {
     return base + ((size_t)(k >> 6) * (size_t)P + (size_t)j) * 64u + (k & 63u);
+}
+
+// Flow population arrays: plane j = s Q + i holds component s, direction i.
+// With 16-bit storage and two components the two components' values of one
+// direction share a 32-bit word (they are read together and pushed to the
+// same node, so one load and one store move both): element (j, k) at
+//   ((k >> 6) Q + i) 128 + 2 (k & 63) + s
+// in stored-type units, i.e. 32-bit word ((k >> 6) Q + i) 64 + (k & 63).
+// Otherwise the chunked plane layout above with P = NC Q planes.
+template <int ST, int NC>
+struct FlowPairs {
+    static constexpr bool value = (ST >= ST_F16S) && NC == 2;
+};
+
+template <int ST, int NC, int Q>
+__device__ __forceinline__ size_t fidx(int j, unsigned k) {
+    if constexpr (FlowPairs<ST, NC>::value) {
+        const int s = j >= Q ? 1 : 0;
+        return ((size_t)(k >> 6) * Q + (size_t)(j - s * Q)) * 128u + 2u * (k & 63u) + (size_t)s;
+    } else {
+        return ((size_t)(k >> 6) * (size_t)(NC * Q) + (size_t)j) * 64u + (k & 63u);
+    }
 }
 
 __device__ __forceinline__ void coords(const unsigned n, int nx, int ny, int& x, int& y, int& z) {

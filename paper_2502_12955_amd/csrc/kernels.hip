@@ -9,8 +9,10 @@
 // a solid node).  Populations are kept in chunks of 64 fluid nodes (one
 // wavefront): element (plane j, node k) lives at
 //   ((k >> 6) * P + j) * 64 + (k & 63),   P = planes of the array,
-// so a wavefront reads every plane of its 64 nodes as contiguous 256-byte
-// rows, and no byte of a solid node is moved.  The pseudo-potential field is
+// so a wavefront reads every plane of its 64 nodes as contiguous rows, and no
+// byte of a solid node is moved.  With 16-bit storage of two components the
+// flow array pairs the components of each direction in 32-bit words (fidx in
+// common.hpp): one load and one store per direction instead of two.  The pseudo-potential field is
 // dense over each sample's box, zero on solid nodes, with the components of a
 // node adjacent (psi[n * NC + s]) so one load fetches both.
 //
@@ -71,6 +73,11 @@ struct GlobalIO {
     const T* __restrict__ gA;   // fluid energy populations (GQ planes), conjugate heat transfer only
     T* __restrict__ gB;
     __device__ __forceinline__ void fstore(int j, unsigned kd, R v, R shift) const { S::store(blk(fB, PF, j, kd), v, shift); }
+    // paired 16-bit flow storage: both components of direction i (already shifted)
+    __device__ __forceinline__ void fstore2(int i, unsigned kd, R v0, R v1) const {
+        uint32_t* w = (uint32_t*)fB + ((size_t)(kd >> 6) * (size_t)(PF / 2) + (size_t)i) * 64u + (kd & 63u);
+        *w = S::to_bits(v0) | (S::to_bits(v1) << 16);
+    }
     __device__ __forceinline__ R hload(int q, unsigned k) const { return S::load_plain(blk(hA, HP, q, k)); }
     __device__ __forceinline__ void hstore(int q, unsigned kd, R v) const { S::store_plain(blk(hB, HP, q, kd), v); }
     template <int GQ>
@@ -148,6 +155,11 @@ struct BufIO {
     }
     __device__ __forceinline__ void fstore(int j, unsigned kd, R v, R shift) const {
         BufBits<ST>::st(fB, v - shift, node_off<PF>(kd) + (uint32_t)j * PS, 0);
+    }
+    // paired 16-bit flow storage: both components of direction i (already shifted)
+    __device__ __forceinline__ void fstore2(int i, unsigned kd, R v0, R v1) const {
+        const uint32_t o = (__umul24(kd >> 6, (uint32_t)(PF / 2 * 64)) + (kd & 63u)) * 4u + (uint32_t)i * 256u;
+        __builtin_amdgcn_raw_buffer_store_b32(S::to_bits(v0) | (S::to_bits(v1) << 16), fB, o, 0, 0);
     }
     __device__ __forceinline__ R hload(int q, unsigned k) const {
         return BufBits<ST>::template ld<2>(hA, node_off<HP>(k), (uint32_t)q * PS);
@@ -236,12 +248,25 @@ __device__ __forceinline__ void density_chunk(const Phys<typename Store<ST>::R>&
     // record; tail lanes are discarded below
     const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
     R rho[NC];
+    if constexpr (FlowPairs<ST, NC>::value) {
+        const uint32_t* fw = (const uint32_t*)fA + (size_t)(k >> 6) * (L::Q * 64u) + (k & 63u);
+        R r0 = 0, r1 = 0;
 #pragma unroll
-    for (int s = 0; s < NC; ++s) {
-        R r = 0;
+        for (int i = 0; i < L::Q; ++i) {
+            const uint32_t w = __builtin_nontemporal_load(fw + i * 64);
+            r0 += S::from_bits(w & 0xffffu) + sh[0][i];
+            r1 += S::from_bits(w >> 16) + sh[NC - 1][i];
+        }
+        rho[0] = r0;
+        rho[NC - 1] = r1;
+    } else {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
-        rho[s] = r;
+        for (int s = 0; s < NC; ++s) {
+            R r = 0;
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) r += S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
+            rho[s] = r;
+        }
     }
     const unsigned n = g.pos[k];
     const SampleDev sd = sample_of(g, ch);
@@ -293,8 +318,12 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
         const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
         const unsigned kd = (i != 0 && !bb) ? dst[i] : k;
         const int dir = bb ? L::opp[i] : i;
+        if constexpr (FlowPairs<ST, NC>::value) {
+            io.fstore2(dir, kd, f[0][i] - sh[0][i], f[NC - 1][i] - sh[NC - 1][i]);  // w_i = w_opp(i)
+        } else {
 #pragma unroll
-        for (int s = 0; s < NC; ++s) io.fstore(s * Q + dir, kd, f[s][i], sh[s][i]);  // w_i = w_opp(i)
+            for (int s = 0; s < NC; ++s) io.fstore(s * Q + dir, kd, f[s][i], sh[s][i]);
+        }
     }
     if (P.solute) {
         // loaded only now: fewer registers live through the flow part (loading
@@ -404,7 +433,25 @@ __device__ __forceinline__ void collide_chunk(const Phys<typename Store<ST>::R>&
     const unsigned n = g.pos[k];
     const uint32_t lw = g.links[k];
     R f[NC][Q];
-    if constexpr (BUF) {
+    if constexpr (FlowPairs<ST, NC>::value) {
+        // both components of direction i in one 32-bit word
+        uint32_t w[Q];
+        if constexpr (BUF) {
+            const __amdgpu_buffer_rsrc_t fr = make_rsrc(fA, fbytes);
+            const uint32_t vo = (__umul24(k >> 6, (uint32_t)(Q * 64)) + (k & 63u)) * 4u;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) w[i] = __builtin_amdgcn_raw_buffer_load_b32(fr, vo, (uint32_t)i * 256u, 2);
+        } else {
+            const uint32_t* fw = (const uint32_t*)fA + (size_t)(k >> 6) * (Q * 64u) + (k & 63u);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) w[i] = __builtin_nontemporal_load(fw + i * 64);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            f[0][i] = S::from_bits(w[i] & 0xffffu) + sh[0][i];
+            f[NC - 1][i] = S::from_bits(w[i] >> 16) + sh[NC - 1][i];
+        }
+    } else if constexpr (BUF) {
         const __amdgpu_buffer_rsrc_t fr = make_rsrc(fA, fbytes);
         const uint32_t vo = BufIO<ST, PF, HP>::template node_off<PF>(k);
 #pragma unroll
@@ -514,7 +561,7 @@ __global__ void __launch_bounds__(256) k_init_eq(Phys<typename Store<ST>::R> P, 
             for (int i = 0; i < L::Q; ++i) {
                 const R cv = R(L::cx[i]) * v[0] + R(L::cy[i]) * v[1] + R(L::cz[i]) * v[2];
                 const R feq = wgt<LAT, R>(i) * r * (R(1) + R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
-                S::store(blk(fA, NC * L::Q, s * L::Q + i, k), feq, sh[s][i]);
+                S::store(fA + fidx<ST, NC, L::Q>(s * L::Q + i, k), feq, sh[s][i]);
             }
         }
         if (P.solute) {
@@ -561,7 +608,7 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
         R r = 0;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            f[s][i] = S::load(blk(fA, NC * L::Q, s * L::Q + i, k), sh[s][i]);
+            f[s][i] = S::load(fA + fidx<ST, NC, L::Q>(s * L::Q + i, k), sh[s][i]);
             r += f[s][i];
         }
         rho[s] = r;
@@ -621,24 +668,34 @@ __global__ void __launch_bounds__(256) k_moments_out(Phys<typename Store<ST>::R>
 // ---------------------------------------------------------------------------
 // encoding of caller-supplied FP64 populations into the storage format, with
 // the same store the step kernels use: elements q0 .. q0 + cnt - 1 of a
-// chunked array of P planes; in a flow array (flow = 1) plane j is component
-// j / Q, direction j % Q and carries the storage shift of that pair; solute
-// planes are stored unshifted.  The value is rounded to the arithmetic type
-// first, then shifted and rounded to the stored type.
+// chunked array of P planes (a flow array in its own layout, fidx); in a flow
+// array (flow = 1) plane j is component j / Q, direction j % Q and carries the
+// storage shift of that pair; solute planes are stored unshifted.  The value
+// is rounded to the arithmetic type first, then shifted and rounded to the
+// stored type.
 // ---------------------------------------------------------------------------
-template <int LAT, int ST>
+template <int LAT, int ST, int NC>
 __global__ void __launch_bounds__(256) k_encode(Phys<typename Store<ST>::R> P, const double* __restrict__ src,
                                                 typename Store<ST>::T* __restrict__ dst, long long q0, long long cnt,
                                                 int planes, int flow) {
     using S = Store<ST>;
     using R = typename S::R;
+    constexpr int Q = Lat<LAT>::Q;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= cnt) return;
     const long long q = q0 + t;
-    const int j = (int)((q >> 6) % planes);
     const R v = (R)src[t];
     if (flow) {
-        const int s = j / Lat<LAT>::Q, i = j % Lat<LAT>::Q;
+        int s, i;
+        if constexpr (FlowPairs<ST, NC>::value) {
+            const int r = (int)(q % (Q * 128));   // element within its chunk: (i, node, s)
+            i = r >> 7;
+            s = r & 1;
+        } else {
+            const int j = (int)((q >> 6) % planes);
+            s = j / Q;
+            i = j % Q;
+        }
         S::store(dst + q, v, (ST >= ST_F16S) ? P.sh[s][i] : R(0));
     } else {
         S::store_plain(dst + q, v);
@@ -989,7 +1046,7 @@ static hipError_t encode_t(const Ctx& c, const double* src, void* dst, long long
                            int flow) {
     if (cnt <= 0) return hipSuccess;
     auto P = make_phys<SR<ST>>(c);
-    hipLaunchKernelGGL((k_encode<LAT, ST>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c.stream, P, src,
+    hipLaunchKernelGGL((k_encode<LAT, ST, NC>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c.stream, P, src,
                        (STT<ST>*)dst, q0, cnt, planes, flow);
     return hipGetLastError();
 }
