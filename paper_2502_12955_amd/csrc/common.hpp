@@ -82,6 +82,10 @@ struct Store<ST_F32> {
     __device__ static inline void store_plain(T* p, R v) { *p = v; }
 };
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 // FP16 stores (f - shift) rounded to nearest even.
 template <>
 struct Store<ST_F16S> {
@@ -89,6 +93,10 @@ struct Store<ST_F16S> {
     using T = __half;
     __device__ static inline R from_bits(uint32_t b) { return __half2float(__ushort_as_half((unsigned short)b)); }
     __device__ static inline uint32_t to_bits(R v) { return __half_as_ushort(__float2half_rn(v)); }
+    // a in the low half, b in the high half, each rounded to nearest even (one packed conversion)
+    __device__ static inline uint32_t pack2(R a, R b) {
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, f16x2_t));
+    }
     __device__ static inline R load(const T* p, R shift) {
         return __half2float(__ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p))) + shift;
     }
@@ -119,16 +127,23 @@ __device__ __host__ static inline uint16_t float_to_bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// On the device the conversion is the hardware one (v_cvt_pk_bf16_f32, round to
+// nearest even, the same bits as float_to_bf16_rne for every non-NaN input).
+__device__ static inline uint16_t bf16_rne_dev(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
 template <>
 struct Store<ST_BF16S> {
     using R = float;
     using T = bf16_t;
     __device__ static inline R from_bits(uint32_t b) { return bf16_to_float((uint16_t)b); }
-    __device__ static inline uint32_t to_bits(R v) { return float_to_bf16_rne(v); }
+    __device__ static inline uint32_t to_bits(R v) { return bf16_rne_dev(v); }
+    __device__ static inline uint32_t pack2(R a, R b) {
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
+    }
     __device__ static inline R load(const T* p, R shift) { return bf16_to_float(__builtin_nontemporal_load(&p->bits)) + shift; }
-    __device__ static inline void store(T* p, R v, R shift) { p->bits = float_to_bf16_rne(v - shift); }
+    __device__ static inline void store(T* p, R v, R shift) { p->bits = bf16_rne_dev(v - shift); }
     __device__ static inline R load_plain(const T* p) { return bf16_to_float(__builtin_nontemporal_load(&p->bits)); }
-    __device__ static inline void store_plain(T* p, R v) { p->bits = float_to_bf16_rne(v); }
+    __device__ static inline void store_plain(T* p, R v) { p->bits = bf16_rne_dev(v); }
 };
 
 // ---------------------------------------------------------------------------

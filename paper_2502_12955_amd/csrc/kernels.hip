@@ -76,7 +76,7 @@ struct GlobalIO {
     // paired 16-bit flow storage: both components of direction i (already shifted)
     __device__ __forceinline__ void fstore2(int i, unsigned kd, R v0, R v1) const {
         uint32_t* w = (uint32_t*)fB + ((size_t)(kd >> 6) * (size_t)(PF / 2) + (size_t)i) * 64u + (kd & 63u);
-        *w = S::to_bits(v0) | (S::to_bits(v1) << 16);
+        *w = S::pack2(v0, v1);
     }
     __device__ __forceinline__ R hload(int q, unsigned k) const { return S::load_plain(blk(hA, HP, q, k)); }
     __device__ __forceinline__ void hstore(int q, unsigned kd, R v) const { S::store_plain(blk(hB, HP, q, kd), v); }
@@ -137,7 +137,7 @@ struct BufBits<ST_BF16S> {
         return bf16_to_float(__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, AUX));
     }
     __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, uint32_t vo, uint32_t so) {
-        __builtin_amdgcn_raw_buffer_store_b16(float_to_bf16_rne(v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(bf16_rne_dev(v), r, vo, so, 0);
     }
 };
 
@@ -159,7 +159,7 @@ struct BufIO {
     // paired 16-bit flow storage: both components of direction i (already shifted)
     __device__ __forceinline__ void fstore2(int i, unsigned kd, R v0, R v1) const {
         const uint32_t o = (__umul24(kd >> 6, (uint32_t)(PF / 2 * 64)) + (kd & 63u)) * 4u + (uint32_t)i * 256u;
-        __builtin_amdgcn_raw_buffer_store_b32(S::to_bits(v0) | (S::to_bits(v1) << 16), fB, o, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(S::pack2(v0, v1), fB, o, 0, 0);
     }
     __device__ __forceinline__ R hload(int q, unsigned k) const {
         return BufBits<ST>::template ld<2>(hA, node_off<HP>(k), (uint32_t)q * PS);
