@@ -516,6 +516,7 @@ int upload_work(mclbm_handle* h) {
     return MCLBM_OK;
 }
 
+// Position of (plane j, fluid node k) in a chunked fluid-only array with P planes.
 static inline size_t blk_index(size_t P, size_t j, size_t k) { return ((k >> 6) * P + j) * 64 + (k & 63); }
 // flow arrays with 16-bit storage of two components pair the components of a
 // direction in one 32-bit word (the device-side fidx): element (j, k) at
@@ -1289,8 +1290,6 @@ int mclbm_population_bytes(mclbm_handle* h, int32_t raw, size_t* bytes) {
     *bytes = nval * (raw ? store_bytes(h->p.storage) : 8);
     return MCLBM_OK;
 }
-
-// Position of (plane j, fluid node k) in a chunked fluid-only array with P planes.
 
 int mclbm_get_populations(mclbm_handle* h, void* dst, int32_t raw) {
     if (!h || !dst) return MCLBM_EINVAL;
