@@ -61,8 +61,9 @@ def test_batch_samples_bit_identical_to_single_runs():
     b.close()
 
 
-def test_persistent_grid_and_block_sizes_bit_identical():
-    cases = _samples(3, seed=7)
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_persistent_grid_and_block_sizes_bit_identical(storage):
+    cases = _samples(3, seed=7, storage=storage)
     ref = _batch(cases)
     ref.step(20)
     want = ref.populations(raw=True)
