@@ -99,8 +99,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
-              f"(the path's multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path runs on a single GPU; sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

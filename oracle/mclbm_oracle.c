@@ -21,8 +21,7 @@
  * for solute species sp (0: the reacting species O2, 1: the product CO2).
  * Solid nodes carry no populations (their slots are left untouched).
  *
- * Readings taken where the paper is silent or ambiguous (listed with reasons
- * in the design notes):
+ * Readings taken where the paper is silent or ambiguous:
  *   - psi of a solid node is 0; walls act only through the adhesion force.
  *   - Guo forcing is one option, the Shan-Chen velocity shift the other.
  *   - body force on component s is rho_s * accel.
