@@ -7,6 +7,11 @@
         residual history of each storage on a smaller box (steps to the
         tolerance, or the floor reached).
 
+    python -m paper_2502_12955_amd.reports thermal [--n 256 --steps 500]
+        Conjugate heat transfer on the benchmark lattice: step time with and
+        without the energy fields, node counts of the solid list and the
+        interface, interface iterations per solve.
+
     python -m paper_2502_12955_amd.reports batch [--count 64]
         A batch of samples with independent per-axis edges in {32, 48, 64,
         96, 128}: aggregate throughput of the batched, graph-replayed run
@@ -116,6 +121,55 @@ def precision(args):
     return out
 
 
+def thermal(args):
+    """The 256^3 porous workload with conjugate heat transfer (FP32): the fluid
+    energy populations ride with the flow, the solid ones on the solid list,
+    the interface solve runs per interface node with the Arrhenius rate law of
+    the interface temperature (k(1) equal to the benchmark's uniform rate)."""
+    p, mask, rho, _, C = inputs.porous_case(n=args.n, config=2, storage=args.storage)
+    E_over_R = 1.5
+    th = dict(tau_ef=0.85, tau_es=1.4, rhocp_f=1.0, rhocp_s=2.5, h_r=0.5, arr_A=p["k_wall"] * np.exp(E_over_R),
+              arr_E_over_R=E_over_R, T_tol=1e-6, T_maxit=50)
+    out = dict(study="conjugate heat transfer", n=args.n, steps=args.steps, storage=args.storage, thermal=th)
+    res = {}
+    for on in (False, True):
+        lat = mclbm.Lattice(p)
+        if on:
+            lat.set_thermal(th)
+        lat.set_geometry(mask)
+        lat.init_fields(rho, None, C)
+        if on:
+            lat.init_temperature(np.ones(mask.size))
+        lat.set_graph(True)
+        lat.step(100)                    # warm-up and graph capture
+        ms = _timed_steps(lat, args.steps) / args.steps
+        entry = dict(ms_per_step=ms)
+        if on:
+            stats = lat.thermal_stats()
+            gm, _, _ = lat.get_geometry()
+            solid = gm.reshape(-1) != 0
+            nz, ny, nx = mask.shape
+            s3 = solid.reshape(nz, ny, nx)
+            near = np.zeros_like(s3)
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        if abs(dx) + abs(dy) + abs(dz) in (1, 2):   # the D3Q19 neighbours
+                            near |= np.roll(s3, (dz, dy, dx), axis=(0, 1, 2))
+            iface = int(np.count_nonzero(near & ~s3))
+            T = lat.temperature()
+            entry.update(fluid_nodes=int(np.count_nonzero(~solid)), solid_nodes=int(np.count_nonzero(solid)),
+                         interface_nodes=iface, iterations_total=stats[0], unsettled=stats[1],
+                         degenerate=stats[2],
+                         iterations_per_solve=stats[0] / max(1, iface * (100 + args.steps)),
+                         T_min=float(T.min()), T_max=float(T.max()))
+        lat.close()
+        res["thermal" if on else "flow_and_solute"] = entry
+        print(f"[thermal] {'on' if on else 'off'}: {ms:.3f} ms/step", flush=True)
+    out["runs"] = res
+    return out
+
+
 def batch(args):
     edges = inputs.batch_edges(args.count)
     cases = []
@@ -207,6 +261,11 @@ def main(argv=None):
     a.add_argument("--tol", type=float, default=1e-6)
     a.add_argument("--cap", type=int, default=30000)
     a.add_argument("--out", default=None)
+    t = sub.add_parser("thermal")
+    t.add_argument("--n", type=int, default=256)
+    t.add_argument("--steps", type=int, default=500)
+    t.add_argument("--storage", default="f32")
+    t.add_argument("--out", default=None)
     b = sub.add_parser("batch")
     b.add_argument("--count", type=int, default=64)
     b.add_argument("--steps", type=int, default=500)
@@ -215,7 +274,7 @@ def main(argv=None):
     b.add_argument("--cap", type=int, default=40000)
     b.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    rep = precision(args) if args.what == "precision" else batch(args)
+    rep = {"precision": precision, "batch": batch, "thermal": thermal}[args.what](args)
     line = json.dumps(rep)
     print(line)
     if args.out:
