@@ -12,6 +12,11 @@
         without the energy fields, node counts of the solid list and the
         interface, interface iterations per solve.
 
+    python -m paper_2502_12955_amd.reports variants [--n 256 --steps 500]
+        Step time of the benchmark lattice with the product species, the
+        per-node rate field, both, one component, and of the 128 x 64 FP64
+        droplet (latency: its state fits the caches).
+
     python -m paper_2502_12955_amd.reports batch [--count 64]
         A batch of samples with independent per-axis edges in {32, 48, 64,
         96, 128}: aggregate throughput of the batched, graph-replayed run
@@ -170,6 +175,53 @@ def thermal(args):
     return out
 
 
+def variants(args):
+    """Step time of the kernel variants on the benchmark lattice (FP32): the
+    reacting solute alone, with the product species (eq:reactCO2), with a
+    per-node rate field k(x) (eq:reactO2, from a prescribed temperature), with
+    both, and a single component (the diagonal cohesion of eq:1.12, G = -5
+    with the solute); plus the 2-D two-component droplet in FP64."""
+    p, mask, rho, _, C = inputs.porous_case(n=args.n, config=2, storage=args.storage)
+    nz, ny, nx = mask.shape
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    T = 1.0 + 0.1 * np.sin(2 * np.pi * xx / nx) * np.cos(2 * np.pi * zz / nz)
+    kfield = inputs.arrhenius_rate_field(T, p["k_wall"] * np.exp(1.5), 1.5).reshape(-1)
+    one = np.where(mask == 0, 1.0, 0.0)[None] * 0.15   # outside the spinodal of G = -5
+    cases = [("reacting solute", dict(), None, rho),
+             ("product species", dict(product=1, D2=0.12, C_in2=0.0), None, rho),
+             ("rate field", dict(), kfield, rho),
+             ("product species and rate field", dict(product=1, D2=0.12, C_in2=0.0), kfield, rho),
+             ("one component, G = -5", dict(ncomp=1, G=((-5.0, 0.0), (0.0, 0.0)), G_ads=(0.0, 0.0)), None, one)]
+    out = dict(study="kernel variants", n=args.n, steps=args.steps, storage=args.storage, runs={})
+    nodes = nx * ny * nz
+    for name, upd, kf, r in cases:
+        q = dict(p, **upd)
+        if kf is not None:
+            q["rate_field"] = 1
+        lat = mclbm.Lattice(q)
+        lat.set_geometry(mask)
+        if kf is not None:
+            lat.set_wall_rate(kf)
+        lat.init_fields(r, None, C)
+        lat.set_graph(True)
+        lat.step(100)
+        ms = _timed_steps(lat, args.steps) / args.steps
+        lat.close()
+        out["runs"][name] = dict(ms_per_step=ms, mlups=nodes / (ms * 1e-3) / 1e6)
+        print(f"[variants] {name}: {ms:.3f} ms/step", flush=True)
+    p2, m2, r2, _, _ = inputs.droplet_2d_case(nx=128, ny=64, radius=20.0, storage="f64")
+    lat = mclbm.Lattice(p2)
+    lat.set_geometry(m2)
+    lat.init_fields(r2)
+    lat.set_graph(True)
+    lat.step(200)
+    ms = _timed_steps(lat, 2000) / 2000
+    lat.close()
+    out["runs"]["2-D droplet 128 x 64, FP64"] = dict(us_per_step=ms * 1e3, mlups=128 * 64 / (ms * 1e-3) / 1e6)
+    print(f"[variants] droplet: {ms * 1e3:.1f} us/step", flush=True)
+    return out
+
+
 def batch(args):
     edges = inputs.batch_edges(args.count)
     cases = []
@@ -266,6 +318,11 @@ def main(argv=None):
     t.add_argument("--steps", type=int, default=500)
     t.add_argument("--storage", default="f32")
     t.add_argument("--out", default=None)
+    v = sub.add_parser("variants")
+    v.add_argument("--n", type=int, default=256)
+    v.add_argument("--steps", type=int, default=500)
+    v.add_argument("--storage", default="f32")
+    v.add_argument("--out", default=None)
     b = sub.add_parser("batch")
     b.add_argument("--count", type=int, default=64)
     b.add_argument("--steps", type=int, default=500)
@@ -274,7 +331,7 @@ def main(argv=None):
     b.add_argument("--cap", type=int, default=40000)
     b.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    rep = {"precision": precision, "batch": batch, "thermal": thermal}[args.what](args)
+    rep = {"precision": precision, "batch": batch, "thermal": thermal, "variants": variants}[args.what](args)
     line = json.dumps(rep)
     print(line)
     if args.out:
