@@ -265,7 +265,10 @@ namespace mclbm {
 
 // Conjugate heat transfer node lists (periodic wrap in every direction):
 //   solid list: solid nodes and interface nodes (fluid nodes with a solid
-//   flow-lattice neighbour), in the band order of the fluid numbering;
+//   flow-lattice neighbour), in the band order of the fluid numbering, the
+//   interface nodes of each plane of a band ahead of its solid nodes (so the
+//   interface solve, one thread per interface node, reads and writes
+//   consecutive solid-list entries);
 //   interface list: box index of every interface node (same order) and the
 //   bits i of its unknown solid populations: those whose upstream node
 //   n - c_i is a fluid node that is not an interface node (nothing streams
@@ -296,13 +299,14 @@ void thermal_lists(const GeomSpec& s, const std::vector<uint8_t>& mask, int band
     ms_bits.clear();
     for (int y0 = 0; y0 < s.ny; y0 += band_rows)
         for (int z = 0; z < s.nz; ++z)
-            for (int y = y0; y < std::min(s.ny, y0 + band_rows); ++y)
-                for (int x = 0; x < s.nx; ++x) {
-                    const long long n = at(x, y, z);
-                    if (!mask[(size_t)n] && !itf[(size_t)n]) continue;
-                    smap[(size_t)n] = (int)spos.size();
-                    spos.push_back((unsigned)n);
-                }
+            for (int pass = 0; pass < 2; ++pass)   // interface nodes, then solid nodes
+                for (int y = y0; y < std::min(s.ny, y0 + band_rows); ++y)
+                    for (int x = 0; x < s.nx; ++x) {
+                        const long long n = at(x, y, z);
+                        if (!(pass == 0 ? itf[(size_t)n] : mask[(size_t)n])) continue;
+                        smap[(size_t)n] = (int)spos.size();
+                        spos.push_back((unsigned)n);
+                    }
     for (int y0 = 0; y0 < s.ny; y0 += band_rows)
         for (int z = 0; z < s.nz; ++z)
             for (int y = y0; y < std::min(s.ny, y0 + band_rows); ++y)
