@@ -101,7 +101,7 @@ typedef struct {
 } mclbm_params;
 
 /* Device bytes the lattice needs for these parameters (populations A and B,
- * link words, pseudo-potential field, residual snapshot, staging, monitor
+ * link words, pseudo-potentials, residual snapshot, staging, monitor
  * partials).  Returns MCLBM_EINVAL for invalid parameters. */
 int mclbm_required_bytes(const mclbm_params* p, size_t* bytes);
 
@@ -263,8 +263,8 @@ int mclbm_run_to_residual(mclbm_handle* h, double tol, int64_t max_steps, int64_
 int mclbm_set_launch(mclbm_handle* h, int32_t block_threads, int32_t grid_blocks);
 
 /* Addressing of the collide pass.  flat = 0 (default): raw buffer
- * instructions with 32-bit byte offsets whenever every population array and
- * each sample's dense fields are below 4 GiB, flat 64-bit addresses
+ * instructions with 32-bit byte offsets whenever every population array, the
+ * pseudo-potentials and each sample's node map are below 4 GiB, flat 64-bit addresses
  * otherwise; flat = 1: flat 64-bit addresses always.  Both forms store the
  * same values to the same elements (results are bit-identical); the buffer
  * form issues fewer instructions.  Drops captured graphs.  EINVAL for other

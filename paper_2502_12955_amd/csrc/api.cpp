@@ -203,7 +203,7 @@ Layout layout_for(const mclbm_params* ps, int n) {
     L.map = take((size_t)Ntot * 4);
     L.pos = take((size_t)M * 4);
     L.links = take((size_t)M * 4);
-    L.psi = take((size_t)NC * Ntot * ab);
+    L.psi = take((size_t)NC * M * ab);
     L.snap = take((size_t)5 * M * ab);
     L.stage = take((size_t)(NC + 4 + (p.solute && p.product ? 1 : 0)) * Ntot * 8);
     L.partials = take(nch * MON_NV * 8);
@@ -1080,10 +1080,6 @@ static int convert_deposits(mclbm_handle* h) {
     HIPCHK(h, k_remap_planes(h->hB, h->hA, h->HP, d_from, padded, sb, h->stream));
     std::swap(h->hA, h->hB);
     HIPCHK(h, hipMemcpyAsync(h->dep, dn.data(), dn.size() * 8, hipMemcpyHostToDevice, h->stream));
-    // the dense pseudo-potential field is written only at fluid nodes (each step's
-    // density pass): the nodes that just turned solid must read 0 there, as every
-    // solid node does after init_fields
-    HIPCHK(h, hipMemsetAsync(h->psi, 0, (size_t)h->NC * h->Ntot * arith_bytes(h->p.storage), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));   // before the host vectors go
     int rc = upload_work(h);
     if (rc != MCLBM_OK) return rc;

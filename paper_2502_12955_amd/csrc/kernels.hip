@@ -12,9 +12,11 @@
 // so a wavefront reads every plane of its 64 nodes as contiguous rows, and no
 // byte of a solid node is moved.  With 16-bit storage of two components the
 // flow array pairs the components of each direction in 32-bit words (fidx in
-// common.hpp): one load and one store per direction instead of two.  The pseudo-potential field is
-// dense over each sample's box, zero on solid nodes, with the components of a
-// node adjacent (psi[n * NC + s]) so one load fetches both.
+// common.hpp): one load and one store per direction instead of two.  The
+// pseudo-potentials follow the fluid numbering, the components of a node
+// adjacent (psi[k * NC + s]) so one load fetches both; the collide pass reads
+// a neighbour's through the fluid index it also pushes to (a solid neighbour's
+// index is -1, and its pseudo-potential counts as 0).
 //
 // Work distribution: each wavefront processes one chunk at a time, taken from
 // a device-side list of active chunks (samples that have converged are left
@@ -25,7 +27,7 @@
 //
 // One step = two kernels, one thread per fluid node:
 //   k_density:  rho_s = sum_i f^s_i (eq:1.7), psi_s = rho0 (1 - exp(-rho_s/rho0))
-//               (eq:1.11) written to the dense psi field.
+//               (eq:1.11) written at the node's fluid index.
 //   k_collide:  forces, velocities, BGK collision with forcing, solute collision,
 //               push streaming into buffer B.
 // Per fluid node (paper, multi-component LBM section):
@@ -243,9 +245,9 @@ __device__ __forceinline__ void density_chunk(const Phys<typename Store<ST>::R>&
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
-    // populations and pos first: every lane of a chunk is inside the
-    // (chunk-padded) arrays, so these loads need not wait for the sample
-    // record; tail lanes are discarded below
+    // populations first: every lane of a chunk is inside the (chunk-padded)
+    // arrays, so these loads need not wait for the sample record; tail lanes
+    // are discarded below
     const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
     R rho[NC];
     if constexpr (FlowPairs<ST, NC>::value) {
@@ -268,12 +270,10 @@ __device__ __forceinline__ void density_chunk(const Phys<typename Store<ST>::R>&
             rho[s] = r;
         }
     }
-    const unsigned n = g.pos[k];
     const SampleDev sd = sample_of(g, ch);
     if ((int)(k - (unsigned)sd.kbase) >= sd.Nf) return;
-    R* ps = psi + (size_t)NC * sd.dbase;
 #pragma unroll
-    for (int s = 0; s < NC; ++s) ps[(size_t)n * NC + s] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
+    for (int s = 0; s < NC; ++s) psi[(size_t)k * NC + s] = P.rho0 * (R(1) - exp_r<R>(-rho[s] * P.inv_rho0));
 }
 
 template <int LAT, int ST, int NC>
@@ -291,8 +291,9 @@ __global__ void __launch_bounds__(256) k_density(Phys<typename Store<ST>::R> P, 
 // (flow with halfway bounce-back; solute with the wet-node reaction, inlet and
 // outlet).
 //   f: pre-collision flow populations of node k (overwritten)
-//   psi_nb(t, i): pseudo-potential of component t at x + c_i (0 for solids)
-//   dest(i): fluid index of x + c_i (called only where that node is fluid)
+//   psi_nb(t, d): pseudo-potential of component t of fluid node d (0 for
+//                 d = -1, a solid neighbour)
+//   dest(i): fluid index of x + c_i, -1 where that node is solid
 //   x, nx: x coordinate of the node and the box edge (solute seams)
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC, int FC, int PR, int KF, int TH, class PsiNb, class Dest, class IO>
@@ -305,14 +306,15 @@ __device__ __forceinline__ void collide_push(const Phys<typename Store<ST>::R>& 
     using R = typename S::R;
     constexpr int Q = L::Q, QS = L::QS, PF = NC * Q;
     R u[3];
-    flow_collide<LAT, NC, R, decltype(psi_nb), FC>(P, lw, f, psi_nb, u);
-    // fluid indices of the 18 neighbours, gathered together before any store
-    // (a solid neighbour reads -1 and is not used), so the pushes wait for one
-    // round trip instead of one per direction
+    // fluid indices of the 18 neighbours, gathered together (a solid
+    // neighbour reads -1): the pseudo-potential gathers go through them, and
+    // the pushes use them without another round trip
     unsigned dst[Q];
     dst[0] = k;
 #pragma unroll
     for (int i = 1; i < Q; ++i) dst[i] = dest(i);
+    auto psi_d = [&](int t, int i) -> R { return psi_nb(t, dst[i]); };
+    flow_collide<LAT, NC, R, decltype(psi_d), FC>(P, lw, f, psi_d, u);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const bool bb = (i != 0) && (lw & (1u << L::opp[i]));
@@ -420,7 +422,8 @@ __device__ __forceinline__ void collide_chunk(const Phys<typename Store<ST>::R>&
                                               typename Store<ST>::T* __restrict__ hB,
                                               const typename Store<ST>::R* __restrict__ psi, uint32_t fbytes,
                                               uint32_t hbytes, const typename Store<ST>::T* __restrict__ gA,
-                                              typename Store<ST>::T* __restrict__ gB, uint32_t gbytes, int ch) {
+                                              typename Store<ST>::T* __restrict__ gB, uint32_t gbytes,
+                                              uint32_t pbytes, int ch) {
     using L = Lat<LAT>;
     using S = Store<ST>;
     using R = typename S::R;
@@ -472,12 +475,14 @@ __device__ __forceinline__ void collide_chunk(const Phys<typename Store<ST>::R>&
     coords(n, sd.nx, sd.ny, x, y, z);
     const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
     const int* mp = g.map + sd.dbase;
-    const R* ps = psi + (size_t)NC * sd.dbase;
     if constexpr (BUF) {
         const __amdgpu_buffer_rsrc_t mr = make_rsrc(mp, (uint32_t)sd.N * 4u);
-        const __amdgpu_buffer_rsrc_t pr = make_rsrc(ps, (uint32_t)sd.N * (uint32_t)(NC * sizeof(R)));
-        auto psi_nb = [&](int t, int i) -> R {
-            const uint32_t o = nb.at(L::cx[i], L::cy[i], L::cz[i]) * (uint32_t)(NC * sizeof(R)) + t * sizeof(R);
+        const __amdgpu_buffer_rsrc_t pr = make_rsrc(psi, pbytes);
+        // d = -1 gives a byte offset of at least 2^32 - 16 (32-bit wrap), past
+        // the record size (a multiple of 256 below 2^32), and a raw buffer load
+        // outside the record returns 0: the solid neighbour's value
+        auto psi_nb = [&](int t, unsigned d) -> R {
+            const uint32_t o = d * (uint32_t)(NC * sizeof(R)) + t * sizeof(R);
             if constexpr (sizeof(R) == 8) return BufBits<ST_F64>::template ld<0>(pr, o, 0);
             else return BufBits<ST_F32>::template ld<0>(pr, o, 0);
         };
@@ -493,7 +498,7 @@ __device__ __forceinline__ void collide_chunk(const Phys<typename Store<ST>::R>&
         collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest,
                                                                               io);
     } else {
-        auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
+        auto psi_nb = [&](int t, unsigned d) -> R { return d == ~0u ? R(0) : psi[(size_t)d * NC + t]; };
         auto dest = [&](int i) -> unsigned { return (unsigned)mp[nb.at(L::cx[i], L::cy[i], L::cz[i])]; };
         const GlobalIO<ST, PF, HP> io{fB, hA, hB, gA, gB};
         collide_push<LAT, ST, NC, FC, (SV & 1), ((SV >> 1) & 1), (SV >> 2)>(P, sh, k, lw, x, sd.nx, f, psi_nb, dest,
@@ -515,12 +520,14 @@ __global__ void __launch_bounds__(256) k_collide(Phys<typename Store<ST>::R> P, 
                                                  const typename Store<ST>::R* __restrict__ psi,
                                                  uint32_t fbytes, uint32_t hbytes,
                                                  const typename Store<ST>::T* __restrict__ gA,
-                                                 typename Store<ST>::T* __restrict__ gB, uint32_t gbytes) {
+                                                 typename Store<ST>::T* __restrict__ gB, uint32_t gbytes,
+                                                 uint32_t pbytes) {
     using R = typename Store<ST>::R;
     R sh[NC][Lat<LAT>::Q];
     load_shifts<LAT, ST, NC>(P, sh);
     for_each_chunk(g, [&](int ch) {
-        collide_chunk<LAT, ST, NC, FC, SV, BUF>(P, g, sh, fA, fB, hA, hB, psi, fbytes, hbytes, gA, gB, gbytes, ch);
+        collide_chunk<LAT, ST, NC, FC, SV, BUF>(P, g, sh, fA, fB, hA, hB, psi, fbytes, hbytes, gA, gB, gbytes, pbytes,
+                                                ch);
     });
 }
 
@@ -601,7 +608,7 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
     int x, y, z;
     coords(n, sd.nx, sd.ny, x, y, z);
     const NbIdx nb = make_nb(x, y, z, sd.nx, sd.ny, sd.nz);
-    const R* ps = psi + (size_t)NC * sd.dbase;
+    const int* mp = g.map + sd.dbase;
     R f[NC][L::Q];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
@@ -613,7 +620,10 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
         }
         rho[s] = r;
     }
-    auto psi_nb = [&](int t, int i) -> R { return ps[(size_t)nb.at(L::cx[i], L::cy[i], L::cz[i]) * NC + t]; };
+    auto psi_nb = [&](int t, int i) -> R {
+        const int d = mp[nb.at(L::cx[i], L::cy[i], L::cz[i])];
+        return d < 0 ? R(0) : psi[(size_t)d * NC + t];
+    };
     flow_collide<LAT, NC, R>(P, lw, f, psi_nb, u);
     C = 0;
     C2 = 0;
@@ -628,12 +638,6 @@ __device__ __forceinline__ void node_moments(const Phys<typename Store<ST>::R>& 
 __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, long long n, double v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_fill_r(R* __restrict__ p, long long n) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = R(0);
 }
 
 template <int LAT, int ST, int NC>
@@ -932,15 +936,16 @@ static hipError_t step_t(const Ctx& c) {
     const STT<ST>* hA = (const STT<ST>*)c.hA;
     STT<ST>* hB = (STT<ST>*)c.hB;
     const SR<ST>* psi = (const SR<ST>*)c.psi;
-    // buffer addressing needs every population array, and each sample's map
-    // and pseudo-potential field, below 4 GiB (32-bit byte offsets)
+    // buffer addressing needs every population array, the pseudo-potentials
+    // and each sample's map below 4 GiB (32-bit byte offsets)
     const size_t fbytes = (size_t)c.nchunks * 64 * NC * Lat<LAT>::Q * sizeof(STT<ST>);
+    const size_t pbytes = (size_t)c.nchunks * 64 * NC * sizeof(SR<ST>);
     const size_t hbytes = (size_t)c.nchunks * 64 * (size_t)(c.hplanes > 0 ? c.hplanes : 1) * sizeof(STT<ST>);
     const size_t gbytes = c.thermal ? (size_t)c.nchunks * 64 * Lat<LAT>::Q * sizeof(STT<ST>) : 0;
     const bool buf = !c.flat && fbytes < (1ull << 32) && hbytes < (1ull << 32) && gbytes < (1ull << 32) &&
-                     (size_t)c.max_sample_nodes * NC * sizeof(SR<ST>) < (1ull << 32);
+                     pbytes < (1ull << 32) && (size_t)c.max_sample_nodes * 4 < (1ull << 32);
     const uint32_t fb32 = (uint32_t)(buf ? fbytes : 0), hb32 = (uint32_t)(buf ? hbytes : 0),
-                   gb32 = (uint32_t)(buf ? gbytes : 0);
+                   gb32 = (uint32_t)(buf ? gbytes : 0), pb32 = (uint32_t)(buf ? pbytes : 0);
     const STT<ST>* gA = (const STT<ST>*)c.gA;
     STT<ST>* gB = (STT<ST>*)c.gB;
     hipLaunchKernelGGL((k_density<LAT, ST, NC>), grid, dim3(bs), 0, c.stream, P, g, (const STT<ST>*)c.fA,
@@ -949,10 +954,10 @@ static hipError_t step_t(const Ctx& c) {
     do {                                                                                                         \
         if (buf)                                                                                                 \
             hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV, 1>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, \
-                               hA, hB, psi, fb32, hb32, gA, gB, gb32);                                           \
+                               hA, hB, psi, fb32, hb32, gA, gB, gb32, pb32);                                     \
         else                                                                                                     \
             hipLaunchKernelGGL((k_collide<LAT, ST, NC, FC, SV, 0>), grid, dim3(bs), 0, c.stream, P, gr, fA, fB, \
-                               hA, hB, psi, fb32, hb32, gA, gB, gb32);                                           \
+                               hA, hB, psi, fb32, hb32, gA, gB, gb32, pb32);                                     \
     } while (0)
     if (c.thermal) {
         // conjugate heat transfer (F64 / F32 storage, uniform rate law of T):
@@ -990,10 +995,6 @@ template <int LAT, int ST, int NC>
 static hipError_t init_t(const Ctx& c, const double* rho, const double* u, const double* C) {
     auto P = make_phys<SR<ST>>(c);
     const Geo g = make_geo(c, false);
-    // the dense psi field must read 0 on solid nodes
-    const long long np = (long long)NC * c.Ntot;
-    hipLaunchKernelGGL((k_fill_r<SR<ST>>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, c.stream,
-                       (SR<ST>*)c.psi, np);
     hipLaunchKernelGGL((k_init_eq<LAT, ST, NC>), grid_for(c, 256, false), dim3(256), 0, c.stream, P, g,
                        (STT<ST>*)c.fA, (STT<ST>*)c.hA, rho, u, C);
     return hipGetLastError();

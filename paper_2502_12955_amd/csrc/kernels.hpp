@@ -40,7 +40,7 @@ struct Ctx {
     const unsigned* pos;        // [nchunks*64] box index (within its sample) of fluid node k
     const int* map;             // [Ntot] fluid index of box node, -1 if solid
     const uint32_t* links;      // [nchunks*64] link words
-    void* psi;                  // pseudo-potential, per sample [nc][N_s] (arith type, 0 on solids)
+    void* psi;                  // pseudo-potentials [nchunks*64][nc] in the fluid numbering (arith type)
     void* snap;                 // residual snapshot [5][nchunks*64] (arith type)
     const int* work;            // active chunk list (device) or nullptr = every chunk
     const int* nwork;           // device count of `work`
