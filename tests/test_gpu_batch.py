@@ -242,3 +242,44 @@ def test_a_diverged_sample_is_frozen_and_the_others_finish():
         assert np.array_equal(out[off: off + ref.size], ref)
         lat.close()
     b.close()
+
+
+def test_tiny_samples_padded_beyond_their_box_match_the_oracle():
+    """Samples of a few nodes each pad their fluid nodes to a whole 64-node
+    chunk, so the batch holds more fluid slots than box nodes (the
+    pseudo-potentials are stored per fluid slot); FP64 moments against the
+    oracle and populations bit-identical to single-lattice runs."""
+    shapes = [(1, 5, 6), (1, 3, 7), (1, 9, 9)]   # (nz, ny, nx)
+    cases = []
+    for s, shape in enumerate(shapes):
+        nz, ny, nx = shape
+        p = inputs.base_params(lattice="D2Q9", nx=nx, ny=ny, nz=1, G=((0.0, 4.2), (4.2, 0.0)),
+                               G_ads=(-0.1, 0.1), accel=(1e-5, 0.0, 0.0), solute="periodic",
+                               D=0.1, J0=0.4, k_wall=0.02, monitor_every=10)
+        mask = np.zeros(shape, np.uint8)
+        mask[0, 1, 2] = 1
+        rho = inputs.droplet(shape, 1.6)
+        rng = inputs.SplitMix64(inputs.seed_for(3, 700 + s))
+        C = 0.3 * rng.uniform(int(np.prod(shape))).reshape(shape)
+        cases.append((p, mask, rho, C))
+    fluid = [int((oracle.pinch_fill(c[0], c[1])[0] == 0).sum()) for c in cases]
+    assert sum(-(-nf // 64) * 64 for nf in fluid) > sum(int(np.prod(c[1].shape)) for c in cases)
+    b = _batch(cases)
+    b.step(12)
+    rhos, us, Cs = b.moments()
+    pops = b.populations(raw=True)
+    nplanes = 2 * 9 + 5
+    off = 0
+    for s, (c, n) in enumerate(zip(cases, b.sizes)):
+        p, mask, rho, C = c
+        m, _ = oracle.pinch_fill(p, mask)
+        f, h = oracle.init(p, m, rho, None, C)
+        oracle.step(p, m, f, h, 12)
+        ro, uo, Co = oracle.moments(p, m, f, h)
+        assert maxrel(rhos[s], ro) < 1e-12
+        assert maxrel(us[s], uo) < 1e-12
+        assert maxrel(Cs[s][0], Co) < 1e-12
+        mine = pops[off: off + nplanes * n]
+        off += nplanes * n
+        assert np.array_equal(mine, _single_pops(c, 12))
+    b.close()
