@@ -433,8 +433,10 @@ __device__ __forceinline__ void collide_chunk(const Phys<typename Store<ST>::R>&
     // link blocked, so they read inside the sample and store only into
     // their own (unused) slots.  Node-local loads are issued first.
     const unsigned k = (unsigned)ch * 64u + (threadIdx.x & 63u);
-    const unsigned n = g.pos[k];
-    const uint32_t lw = g.links[k];
+    // read once per step, like the populations: non-temporal, so they do not
+    // displace the neighbour indices and pseudo-potentials that other nodes gather
+    const unsigned n = __builtin_nontemporal_load(g.pos + k);
+    const uint32_t lw = __builtin_nontemporal_load(g.links + k);
     R f[NC][Q];
     if constexpr (FlowPairs<ST, NC>::value) {
         // both components of direction i in one 32-bit word
